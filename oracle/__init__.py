@@ -1,0 +1,233 @@
+"""FP64 CPU oracle of the sampling / rendering path -- TEST INFRASTRUCTURE.
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+(``paper_2305_04966_amd``) and imports nothing from it; both sides receive the
+same seeded inputs from the ``scenes`` module.
+
+The numerical work lives in ``txs_oracle.c`` (plain C loops, binary32 for the
+geometric decisions, binary64 for everything continuous).  This module only
+builds it with gcc and marshals numpy arrays.  The proposal-MLP, histogram
+loss and optimiser references live in ``oracle.learned``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "txs_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+          "-std=c11", "-Wall"]
+
+
+def build(force: bool = True) -> str:
+    """Compile txs_oracle.c into liboracle.so next to it (gcc)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH) or (os.path.getmtime(_LIB_PATH)
+                                                 < os.path.getmtime(_SRC)):
+                build(force=True)
+            _lib = C.CDLL(_LIB_PATH)
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def num_threads() -> int:
+    L = lib()
+    L.oracle_num_threads.restype = C.c_int32
+    return int(L.oracle_num_threads())
+
+
+# ----------------------------------------------------------------------------
+def clip(o, d, bmin, bmax, near=0.0, far=float("inf")):
+    """Slab clip in the binary32 recipe -> (t_near, t_far) float32 arrays."""
+    o, d = _f32(o), _f32(d)
+    n = o.shape[0]
+    tn = np.empty(n, np.float32)
+    tf = np.empty(n, np.float32)
+    lib().oracle_clip(C.c_int32(n), _p(o), _p(d), _p(_f32(bmin)), _p(_f32(bmax)),
+                      C.c_float(near), C.c_float(far), _p(tn), _p(tf))
+    return tn, tf
+
+
+def march(o, d, bits, res, *, n_levels=1, center=(0.0, 0.0, 0.0), half_extent0=1.5,
+          near=0.0, far=float("inf"), dt0=0.005, max_per_ray=0, want_level=False):
+    """Dense-definition occupancy march.
+
+    Returns dict(packed_info [N,2] int32, t0, t1 float32 [S], ray_id int32 [S],
+    counts [N], total, level (optional)).
+    """
+    o, d = _f32(o), _f32(d)
+    bits = np.ascontiguousarray(bits, dtype=np.uint32)
+    n = o.shape[0]
+    assert bits.size * 32 >= n_levels * res ** 3
+    cen = _f32(center)
+    args_head = (C.c_int32(n), _p(o), _p(d), _p(bits), C.c_int32(res), C.c_int32(n_levels),
+                 _p(cen), C.c_float(half_extent0), C.c_float(near), C.c_float(far),
+                 C.c_float(dt0), C.c_int32(max_per_ray))
+    counts = np.zeros(n, np.int32)
+    L = lib()
+    L.oracle_march(*args_head, _p(counts), None, None, None, None, None)
+    offsets = np.zeros(n, np.int64)
+    if n:
+        offsets[1:] = np.cumsum(counts.astype(np.int64))[:-1]
+    total = int(counts.astype(np.int64).sum())
+    t0 = np.empty(total, np.float32)
+    t1 = np.empty(total, np.float32)
+    rid = np.empty(total, np.int32)
+    lvl = np.empty(total, np.int32) if want_level else None
+    counts2 = np.zeros(n, np.int32)
+    L.oracle_march(*args_head, _p(counts2), _p(offsets), _p(t0), _p(t1), _p(rid), _p(lvl))
+    assert np.array_equal(counts, counts2)
+    info = np.stack([offsets.astype(np.int32), counts], axis=1)
+    out = dict(packed_info=np.ascontiguousarray(info), t0=t0, t1=t1, ray_id=rid,
+               counts=counts, total=total)
+    if want_level:
+        out["level"] = lvl
+    return out
+
+
+def render_fwd(packed_info, t0, t1, sigma, rgb, bg=None, want_weights=False):
+    """FP64 compositing of packed samples -> dict(rgb [N,3], opacity, depth, weights)."""
+    info = _i32(packed_info)
+    n = info.shape[0]
+    t0, t1, sigma, rgb = _f32(t0), _f32(t1), _f32(sigma), _f32(rgb)
+    bg = None if bg is None else _f32(bg)
+    out_rgb = np.zeros((n, 3), np.float64)
+    out_op = np.zeros(n, np.float64)
+    out_dep = np.zeros(n, np.float64)
+    w = np.zeros(t0.shape[0], np.float64) if want_weights else None
+    lib().oracle_render_fwd(C.c_int32(n), _p(info), _p(t0), _p(t1), _p(sigma), _p(rgb), _p(bg),
+                            _p(out_rgb), _p(out_op), _p(out_dep), _p(w))
+    return dict(rgb=out_rgb, opacity=out_op, depth=out_dep, weights=w)
+
+
+def render_bwd(packed_info, t0, t1, sigma, rgb, g_rgb, g_opacity=None, g_depth=None, bg=None):
+    """FP64 adjoint -> (d_sigma [S], d_rgb [S,3])."""
+    info = _i32(packed_info)
+    n = info.shape[0]
+    t0, t1, sigma, rgb = _f32(t0), _f32(t1), _f32(sigma), _f32(rgb)
+    g_rgb = _f32(g_rgb)
+    g_opacity = None if g_opacity is None else _f32(g_opacity)
+    g_depth = None if g_depth is None else _f32(g_depth)
+    bg = None if bg is None else _f32(bg)
+    ds = np.zeros(t0.shape[0], np.float64)
+    dr = np.zeros((t0.shape[0], 3), np.float64)
+    lib().oracle_render_bwd(C.c_int32(n), _p(info), _p(t0), _p(t1), _p(sigma), _p(rgb), _p(bg),
+                            _p(g_rgb), _p(g_opacity), _p(g_depth), _p(ds), _p(dr))
+    return ds, dr
+
+
+def weights_bwd(packed_info, t0, t1, sigma, g_w):
+    info = _i32(packed_info)
+    t0, t1, sigma, g_w = _f32(t0), _f32(t1), _f32(sigma), _f32(g_w)
+    ds = np.zeros(t0.shape[0], np.float64)
+    lib().oracle_weights_bwd(C.c_int32(info.shape[0]), _p(info), _p(t0), _p(t1), _p(sigma),
+                             _p(g_w), _p(ds))
+    return ds
+
+
+def transmittance_prefix(packed_info, t0, t1, sigma, t_min=1e-4):
+    """kept[r] = #samples with T_i >= t_min; band[r] flags near-threshold rays."""
+    info = _i32(packed_info)
+    n = info.shape[0]
+    kept = np.zeros(n, np.int32)
+    band = np.zeros(n, np.int32)
+    lib().oracle_transmittance_prefix(C.c_int32(n), _p(info), _p(_f32(t0)), _p(_f32(t1)),
+                                      _p(_f32(sigma)), C.c_double(t_min), _p(kept), _p(band))
+    return kept, band.astype(bool)
+
+
+def gather_prefix(packed_info, kept, t0, t1, ray_id):
+    """Repack the first kept[r] samples of each ray -> (packed_info_out, t0, t1, ray_id)."""
+    info = _i32(packed_info)
+    kept = _i32(kept)
+    n = info.shape[0]
+    starts = np.zeros(n, np.int64)
+    if n:
+        starts[1:] = np.cumsum(kept.astype(np.int64))[:-1]
+    total = int(kept.astype(np.int64).sum())
+    idx = (np.repeat(info[:, 0].astype(np.int64) - starts, kept)
+           + np.arange(total, dtype=np.int64))
+    info_out = np.stack([starts.astype(np.int32), kept], axis=1)
+    return np.ascontiguousarray(info_out), t0[idx], t1[idx], ray_id[idx]
+
+
+def exclusive_scan(counts):
+    counts = np.asarray(counts, np.int64)
+    starts = np.zeros_like(counts)
+    if counts.size:
+        starts[1:] = np.cumsum(counts)[:-1]
+    info = np.stack([starts, counts], axis=1).astype(np.int32)
+    return info, int(counts.sum())
+
+
+MODE_SIGMA, MODE_WEIGHTS = 0, 1
+
+
+def resample(edges, vals, n_out, mode=MODE_SIGMA, u=None):
+    """Inverse-CDF resampling -> (edges_out float64 [N,n_out+1], bin int32, band bool [N])."""
+    edges, vals = _f32(edges), _f32(vals)
+    n, nb = vals.shape
+    assert edges.shape == (n, nb + 1)
+    out = np.zeros((n, n_out + 1), np.float64)
+    bins = np.zeros((n, n_out + 1), np.int32)
+    band = np.zeros(n, np.int32)
+    uu = None if u is None else _f32(u)
+    lib().oracle_resample(C.c_int32(n), C.c_int32(nb), _p(edges), _p(vals), C.c_int32(mode),
+                          C.c_int32(n_out), _p(uu), _p(out), _p(bins), _p(band))
+    return out, bins, band.astype(bool)
+
+
+def field(x, params):
+    """FP64 analytic field at points x [n,3] -> (sigma [n], rgb [n,3])."""
+    x = _f64(x).reshape(-1, 3)
+    p = _f64(params)
+    n = x.shape[0]
+    s = np.zeros(n, np.float64)
+    c = np.zeros((n, 3), np.float64)
+    lib().oracle_field(C.c_int64(n), _p(x), _p(p), _p(s), _p(c))
+    return s, c
+
+
+def field_at_samples(o, d, t0, t1, ray_id, params):
+    """Field at interval midpoints x = o + (t0+t1)/2 d (FP64)."""
+    o = np.asarray(o, np.float64)
+    d = np.asarray(d, np.float64)
+    tm = 0.5 * (np.asarray(t0, np.float64) + np.asarray(t1, np.float64))
+    rid = np.asarray(ray_id, np.int64)
+    x = o[rid] + tm[:, None] * d[rid]
+    return field(x, params)
