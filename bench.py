@@ -1,0 +1,212 @@
+"""Benchmark of the sampling + packed-rendering hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of rays, inputs resident
+in HBM:  march (count, scan, fill) -> field density without grad ->
+transmittance filter (prefix, scan, gather) -> field density and colour ->
+render forward -> render backward against a fixed upstream gradient.
+The field is the analytic stand-in for the user's radiance field (support,
+not part of the library's roofline).  Two device->host reads per step (the
+sample totals that size the packed tensors) are part of the step.
+
+Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic HBM bytes of each library entry point (N rays, Sm marched, S kept)
+BYTES = {
+    "march_count": lambda N, Sm, S: 28 * N,
+    "exclusive_scan": lambda N, Sm, S: 16 * N,
+    "march_fill": lambda N, Sm, S: 32 * N + 12 * Sm,
+    "transmittance_prefix": lambda N, Sm, S: 12 * N + 12 * Sm,
+    "gather_prefix": lambda N, Sm, S: 16 * N + 4 * Sm + 20 * S,
+    "render_fwd": lambda N, Sm, S: 28 * N + 24 * S,
+    "render_bwd": lambda N, Sm, S: 20 * N + 40 * S,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="image", choices=["image", "tiny", "unbounded"])
+    ap.add_argument("--cpu-sample", type=int, default=16,
+                    help="oracle baseline runs on every k-th ray (0 = skip)")
+    return ap.parse_args()
+
+
+def make_workload(name):
+    import scenes
+    if name == "tiny":
+        return scenes.tiny(), "tiny: 8 blobs, 64^3 grid, 4096 sphere rays, step 0.005"
+    if name == "unbounded":
+        return (scenes.unbounded(), "unbounded: 64 blobs + shell, 4x128^3 cascade, "
+                "8 cameras 512x256 (2^20 rays), step 0.0050744*2^l")
+    return (scenes.image(), "image: 32 blobs, 128^3 grid over [-1.5,1.5]^3, 1024x1024 pinhole "
+            "fov 40 (2^20 rays), step sqrt(3)*3/1024")
+
+
+class Timeline:
+    """HIP events around each library call on torch's current stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.marks = []
+        self.on = False
+
+    def run(self, name, fn, *a, **k):
+        if not self.on:
+            return fn(*a, **k)
+        s = self.torch.cuda.current_stream()
+        e0 = self.torch.cuda.Event(enable_timing=True)
+        e1 = self.torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        r = fn(*a, **k)
+        e1.record(s)
+        self.marks.append((name, e0, e1))
+        return r
+
+    def summary(self):
+        out = {}
+        for name, e0, e1 in self.marks:
+            out.setdefault(name, []).append(e0.elapsed_time(e1))
+        return {k: (float(np.mean(v)), len(v)) for k, v in out.items()}
+
+
+def gpu_bench(args, w):
+    import torch
+
+    import paper_2305_04966_amd as txs
+    txs.load()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    grid = txs.GridSpec(dev(w.bits.view(np.int32)), w.res, w.n_levels, (0.0, 0.0, 0.0),
+                        w.half_extent0)
+    o, d = dev(w.rays_o), dev(w.rays_d)
+    params = dev(w.fld.packed_params().astype(np.float32))
+    nb = w.fld.n_blobs
+    g_rgb = dev(w.grads)
+    N = w.n_rays
+    tl = Timeline(torch)
+    stats = {}
+
+    def step():
+        counts = tl.run("march_count", txs.march_count, grid, o, d, dt0=w.dt0)
+        info, total = tl.run("exclusive_scan", txs.exclusive_scan, counts)
+        sm = int(total.item())
+        t0, t1, rid = tl.run("march_fill", txs.march_fill, grid, o, d, info, sm, dt0=w.dt0)
+        sig_ng, _ = tl.run("field_density", txs.blob_field, params, nb, o, d, t0, t1, rid,
+                           want_rgb=False)
+        kept = tl.run("transmittance_prefix", txs.transmittance_prefix, info, t0, t1, sig_ng,
+                      w.t_min)
+        info2, total2 = tl.run("exclusive_scan", txs.exclusive_scan, kept)
+        s = int(total2.item())
+        q0, q1, qr = tl.run("gather_prefix", txs.gather_prefix, info, info2, s, t0, t1, rid)
+        sig, rgb = tl.run("field_density_rgb", txs.blob_field, params, nb, o, d, q0, q1, qr)
+        out = tl.run("render_fwd", txs.render_fwd, info2, q0, q1, sig, rgb)
+        grads = tl.run("render_bwd", txs.render_bwd, info2, q0, q1, sig, rgb, g_rgb)
+        stats["Sm"], stats["S"] = sm, s
+        return out, grads
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tl.on = True
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    return elapsed, tl.summary(), stats
+
+
+def cpu_baseline(w, every):
+    """The oracle on every `every`-th ray of the same workload (same steps)."""
+    import oracle
+    idx = np.arange(0, w.n_rays, every)
+    o, d = w.rays_o[idx], w.rays_d[idx]
+    p = w.fld.packed_params()
+    t = time.perf_counter()
+    m = oracle.march(o, d, w.bits, w.res, n_levels=w.n_levels, half_extent0=w.half_extent0,
+                     dt0=w.dt0)
+    s_ng, _ = oracle.field_at_samples(o, d, m["t0"], m["t1"], m["ray_id"], p)
+    kept, _ = oracle.transmittance_prefix(m["packed_info"], m["t0"], m["t1"],
+                                          s_ng.astype(np.float32), w.t_min)
+    info, t0, t1, rid = oracle.gather_prefix(m["packed_info"], kept, m["t0"], m["t1"],
+                                             m["ray_id"])
+    s, c = oracle.field_at_samples(o, d, t0, t1, rid, p)
+    s32, c32 = s.astype(np.float32), c.astype(np.float32)
+    oracle.render_fwd(info, t0, t1, s32, c32)
+    oracle.render_bwd(info, t0, t1, s32, c32, w.grads[idx])
+    dt = time.perf_counter() - t
+    return {"value": len(idx) / dt, "unit": "rays/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"every {every}th ray ({len(idx)} rays) of the same workload, full path "
+                      f"(dense march, FP64 field, filter, render fwd+bwd), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not "
+              "supported (rays shard with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+    w, desc = make_workload(args.workload)
+    elapsed, ker, st = gpu_bench(args, w)
+    N, K = w.n_rays, args.steps
+    ms = 1000.0 * elapsed / K
+    lib_ms = sum(t * n for name, (t, n) in ker.items() if not name.startswith("field")) / K
+    field_ms = sum(t * n for name, (t, n) in ker.items() if name.startswith("field")) / K
+    # dominant library kernel by total time
+    lib = {k: v for k, v in ker.items() if k in BYTES}
+    dom = max(lib, key=lambda k: lib[k][0] * lib[k][1])
+    launches_per_step = lib[dom][1] / K
+    bytes_launch = BYTES[dom](N, st["Sm"], st["S"]) / launches_per_step
+    achieved = bytes_launch / (lib[dom][0] * 1e-3) / 1e9
+    alg_total = sum(f(N, st["Sm"], st["S"]) for f in BYTES.values())
+    rec = {
+        "metric": "rays/s fwd+bwd at <=1e-3 rgb err vs FP64 oracle; learned vs grid; HBM GB/s",
+        "value": N * K / elapsed,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "rays": N, "marched_samples": st["Sm"],
+                   "kept_samples": st["S"], "parallelism": "single GPU"},
+        "samples_per_s": st["S"] * K / elapsed,
+        "library_ms_per_step": lib_ms,
+        "field_ms_per_step": field_ms,
+        "library_rays_per_s": N / (lib_ms * 1e-3),
+        "library_alg_GBps": alg_total / (lib_ms * 1e-3) / 1e9,
+        "kernels_ms": {k: round(v[0], 4) for k, v in ker.items()},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+    }
+    if rank == 0 and args.cpu_sample > 0:
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    if rank == 0:
+        print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * txs.h -- C ABI of the MI355X (gfx950) library for transmittance-estimator
+ * ray sampling and packed volume rendering.
+ *
+ * The method follows Li, Gao, Tancik, Kanazawa, "NerfAcc: Efficient Sampling
+ * Accelerates NeRFs" (2023): every sampler is an estimator of transmittance T,
+ * whose complement 1 - T is the CDF used for importance sampling (Section 3.1,
+ * Eqs. 1-3); samples are intervals (t0, t1, ray) stored in packed tensors with
+ * a per-ray (start, count) table (Section 4.2); samples with T < 1e-4 are
+ * dropped before the differentiable pass (Section 4.2, "No Gradient
+ * Filtering").  Algorithm 1 of the paper is the call sequence this ABI serves:
+ * sample (march -> field density -> filter), render forward, render backward,
+ * estimator update.
+ *
+ * Conventions for every entry point
+ *  - Array pointers are DEVICE pointers owned by the caller; the library never
+ *    allocates or frees them and keeps no reference after the call returns.
+ *  - Work is enqueued on `stream` (a hipStream_t, NULL = the default stream)
+ *    and is asynchronous: no entry point synchronises the device.
+ *  - Return value: TXS_OK (0) or a negative txs_status.  On error nothing is
+ *    enqueued and txs_last_error() returns a message (thread-local).  No C++
+ *    exception crosses the ABI.
+ *  - Results are bitwise deterministic run to run (no floating-point atomics).
+ *  - Layouts: float = IEEE binary32, rows are contiguous (row-major), "[N,3]"
+ *    means 3 consecutive floats per row.  packed_info is int32 [n_rays, 2]
+ *    = (start, count); starts are non-decreasing and the ray segments
+ *    [start, start+count) do not overlap (gaps between them are allowed).
+ *  - Sample counts are int64 on the host side; packed starts are int32, so a
+ *    packed tensor holds fewer than 2^31 samples (TXS_EOVERFLOW otherwise).
+ */
+#ifndef TXS_H_
+#define TXS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t txs_status;
+#define TXS_OK 0
+#define TXS_EINVAL (-1)    /* bad argument (null pointer, size, layout) */
+#define TXS_ECAPACITY (-2) /* an output buffer is smaller than required */
+#define TXS_EHIP (-3)      /* a HIP runtime call or kernel launch failed */
+#define TXS_EOVERFLOW (-4) /* a count does not fit the int32 packed layout */
+
+#define TXS_ABI_VERSION 1
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* txs_last_error(void);
+int32_t txs_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Occupancy grid (the spatial-skipping estimator of Section 3.1 and Table 1,
+ * second row).  Level l is the cube center +- half_extent0 * 2^l, divided into
+ * res^3 cells; its occupancy bits start at bit l*res^3 of `bits`; the bit of
+ * cell (x, y, z) is bit (i & 31) of word i >> 5 with i = x + res*(y + res*z).
+ * n_levels > 1 is the cascade used for unbounded scenes (Section 3.2): each
+ * level doubles the extent and the marching step.                           */
+typedef struct {
+  const uint32_t* bits; /* device, n_levels * res^3 / 32 words */
+  int32_t res;          /* cells per axis: a power of two in [2, 1024] */
+  int32_t n_levels;     /* 1 .. 8 */
+  float center[3];
+  float half_extent0;   /* > 0 */
+} txs_grid;
+
+typedef struct {
+  float near_plane; /* rays start at max(near_plane, box entry); >= 0 */
+  float far_plane;  /* and end at min(far_plane, box exit); may be +inf */
+  float dt0;        /* lattice step on level 0 (> 0); level l uses dt0 * 2^l */
+  int32_t max_per_ray; /* keep at most this many samples per ray; 0 = no cap */
+} txs_march_params;
+
+/*
+ * Occupancy-grid marching (Section 3.1 "Spatial Skipping"; Section 4.2
+ * "Sample as Interval").  For each ray, each constant-level segment [a, b)
+ * of its chord through the grid carries the lattice t_k = a + k*dt
+ * (midpoints m_k = a + (k+1/2)*dt < b); sample k is emitted iff the cell that
+ * holds o + m_k*d is occupied, as the interval [t_k, min(a+(k+1)*dt, b)].
+ * The occupancy test is evaluated in binary32 with the fixed operation order
+ *   u = ((o + m*d) - bmin) * (res / (bmax - bmin)),  cell = clamp(floor(u))
+ * (no fused multiply-add) so that the emitted samples are exactly those of a
+ * dense test of every lattice point; empty cells are skipped with a DDA whose
+ * jumps provably never pass a lattice point that the dense test would keep.
+ *
+ * txs_march_count writes counts[n_rays] (int32).
+ * rays_o, rays_d: float [n_rays, 3]; rays_d need not be normalised (the
+ * paper's rays are unit vectors; t is measured in units of |d|).
+ */
+txs_status txs_march_count(const txs_grid* grid, const txs_march_params* params,
+                           const float* rays_o, const float* rays_d, int32_t n_rays,
+                           int32_t* counts, void* stream);
+
+/*
+ * Exclusive scan of per-ray counts into the packed table (Section 4.2,
+ * "Packed Tensor"): packed_info[r] = (sum_{q<r} counts[q], counts[r]) and
+ * *d_total (device int64) = sum of all counts.  Starts that would exceed
+ * INT32_MAX are still summed correctly into *d_total; the caller must check
+ * *d_total < 2^31 before using the table.  workspace: device scratch of at
+ * least txs_scan_workspace_size(n_rays) bytes (contents need not be zero).
+ */
+size_t txs_scan_workspace_size(int32_t n_rays);
+txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays, int32_t* packed_info,
+                              int64_t* d_total, void* workspace, size_t workspace_bytes,
+                              void* stream);
+
+/*
+ * Second marching pass: writes the samples of ray r at packed_info[r].start,
+ * ray-major and t-ascending: t0, t1 (float [capacity]) and ray_id (int32
+ * [capacity], may be NULL).  packed_info must come from counts produced by
+ * txs_march_count with the same grid, params and rays.  No write goes at or
+ * beyond `capacity` samples.
+ */
+txs_status txs_march_fill(const txs_grid* grid, const txs_march_params* params,
+                          const float* rays_o, const float* rays_d, int32_t n_rays,
+                          const int32_t* packed_info, int64_t capacity, float* t0, float* t1,
+                          int32_t* ray_id, void* stream);
+
+/*
+ * No-gradient filtering (Section 4.2): with tau_i = sigma_i (t1_i - t0_i) and
+ * T_i = exp(-sum_{j<i} tau_j) over the samples of a ray, kept_counts[r] is
+ * the number of leading samples with T_i >= t_min (the paper uses 1e-4).
+ * T is non-increasing, so the kept samples are a prefix of the ray.  The
+ * decision is taken in binary32 as sum_{j<i} tau_j <= -ln(t_min).
+ * sigma: float [n_samples] (density from the radiance field, no gradient).
+ */
+txs_status txs_transmittance_prefix(const int32_t* packed_info, int32_t n_rays,
+                                    int64_t n_samples, const float* t0, const float* t1,
+                                    const float* sigma, float t_min, int32_t* kept_counts,
+                                    void* stream);
+
+/*
+ * Repacks the first packed_info_out[r].count samples of every ray from the
+ * input packed tensor (described by packed_info_in and ray_id) to
+ * packed_info_out[r].start in the output tensor.  ray_id (int32 [n_in]) is
+ * required; t0o, t1o, ray_ido have room for `capacity` samples (ray_ido may
+ * be NULL).  Typical use: packed_info_out = txs_exclusive_scan(kept_counts).
+ */
+txs_status txs_gather_prefix(const int32_t* packed_info_in, const int32_t* packed_info_out,
+                             int32_t n_rays, int64_t n_in, const float* t0, const float* t1,
+                             const int32_t* ray_id, int64_t capacity, float* t0o, float* t1o,
+                             int32_t* ray_ido, void* stream);
+
+/*
+ * Packed volume rendering forward (Eq. 2, discretised):
+ *   tau_i = sigma_i (t1_i - t0_i),  T_i = exp(-sum_{j<i} tau_j),
+ *   w_i = T_i (1 - exp(-tau_i)),
+ *   out_rgb = sum w_i rgb_i + (1 - sum w_i) * bg,  out_opacity = sum w_i,
+ *   out_depth = sum w_i (t0_i + t1_i)/2   (unnormalised expected depth).
+ * packed_info may be NULL: then ray r owns samples [r*fixed_count,
+ * (r+1)*fixed_count) (dense layout, e.g. proposal resampling output).
+ * sigma float [n_samples], rgb float [n_samples, 3], bg float [n_rays, 3] or
+ * NULL (black).  Outputs: out_rgb [n_rays,3], out_opacity [n_rays],
+ * out_depth [n_rays], out_weights [n_samples] or NULL.
+ */
+txs_status txs_render_fwd(const int32_t* packed_info, int32_t fixed_count, int32_t n_rays,
+                          int64_t n_samples, const float* t0, const float* t1,
+                          const float* sigma, const float* rgb, const float* bg,
+                          float* out_rgb, float* out_opacity, float* out_depth,
+                          float* out_weights, void* stream);
+
+/*
+ * Adjoint of txs_render_fwd (the gradients that reach the radiance field in
+ * Algorithm 1; the intervals carry none, Section 4.2).  With
+ *   v_i = g.(rgb_i - bg) + h + q (t0_i + t1_i)/2,
+ *   d_rgb_i   = w_i g,
+ *   d_sigma_i = (t1_i - t0_i) (T_{i+1} v_i - sum_{j>i} w_j v_j),
+ * where g = g_rgb[r] (float [n_rays,3]), h = g_opacity[r], q = g_depth[r]
+ * (both may be NULL = 0).  T and w are recomputed from the inputs (nothing is
+ * stored by the forward); the suffix sum is an exact reverse scan.
+ * d_sigma float [n_samples], d_rgb float [n_samples,3] (may be NULL).
+ */
+txs_status txs_render_bwd(const int32_t* packed_info, int32_t fixed_count, int32_t n_rays,
+                          int64_t n_samples, const float* t0, const float* t1,
+                          const float* sigma, const float* rgb, const float* bg,
+                          const float* g_rgb, const float* g_opacity, const float* g_depth,
+                          float* d_sigma, float* d_rgb, void* stream);
+
+/*
+ * Adjoint of the weights alone: given g_w[i] = dL/dw_i (float [n_samples]),
+ *   d_sigma_i = (t1_i - t0_i) (T_{i+1} g_w_i - sum_{j>i} w_j g_w_j).
+ * Used to train a proposal estimator through its rendering weights.
+ */
+txs_status txs_weights_bwd(const int32_t* packed_info, int32_t fixed_count, int32_t n_rays,
+                           int64_t n_samples, const float* t0, const float* t1,
+                           const float* sigma, const float* g_w, float* d_sigma, void* stream);
+
+/*
+ * Inverse transform sampling (Eq. 1) of a piecewise-constant estimator whose
+ * CDF is read off the transmittance, F = 1 - T (Eq. 3):
+ *   mode TXS_PDF_SIGMA:   F_{i+1} = 1 - exp(-sum_{j<=i} vals_j (e_{j+1} - e_j))
+ *   mode TXS_PDF_WEIGHTS: F_{i+1} = sum_{j<=i} vals_j
+ * Per ray: u' = u * F_n, i = the largest i in [0, n_bins] with F_i <= u',
+ * t = e_i + (u' - F_i) / (F_{i+1} - F_i) * (e_{i+1} - e_i)  (t = e_n if
+ * i = n_bins).  A ray whose F_n <= 1e-12 uses the uniform estimator
+ * (F_i = i/n_bins, Table 1, first row).  u is float [n_rays, n_out+1] with
+ * values in [0,1], non-decreasing per ray, or NULL for u_k = k/n_out.
+ * edges float [n_rays, n_bins+1] (non-decreasing), vals float
+ * [n_rays, n_bins] (>= 0); out_edges float [n_rays, n_out+1] are the
+ * n_out+1 edges of n_out contiguous intervals.  n_bins <= 1024.
+ */
+#define TXS_PDF_SIGMA 0
+#define TXS_PDF_WEIGHTS 1
+txs_status txs_resample(int32_t n_rays, int32_t n_bins, const float* edges, const float* vals,
+                        int32_t mode, int32_t n_out, const float* u, float* out_edges,
+                        void* stream);
+
+/*
+ * Uniform estimator (Table 1, first row): n_bins+1 equally spaced edges per
+ * ray over its chord through the outermost cube of `grid` (bits unused),
+ *   e_k = t_near + (t_far - t_near) * (k / n_bins),   out: float [n_rays, n_bins+1].
+ * A ray that misses gets all edges equal to max(near_plane, 0) and t_far = t_near.
+ */
+txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, float far_plane,
+                            const float* rays_o, const float* rays_d, int32_t n_rays,
+                            int32_t n_bins, float* out_edges, void* stream);
+
+/*
+ * Support (not part of the method): an analytic radiance field standing in for
+ * the user's NeRF of Algorithm 1, evaluated at interval midpoints
+ * x = o[ray] + (t0+t1)/2 * d[ray]:
+ *   sigma(x) = sum_b peak exp(-|x-c_b|^2/(2 w^2)) + shell_peak exp(-(|x|-R)^2/(2 ws^2))
+ *   rgb(x)   = density-weighted mix of sigmoid(A x + b) and sigmoid(A2 x/|x| + b2).
+ * params: device float array of 32 + 3*n_blobs values in the layout
+ * [0] (unused), [1] peak, [2] width, [3] shell flag, [4] R, [5] ws,
+ * [6] shell_peak, [7:16] A, [16:19] b, [19:28] A2, [28:31] b2,
+ * [32:32+3*n_blobs] centres.
+ * rays_o, rays_d: float [n_rays, 3].  ray_id int32 [n] or NULL with
+ * fixed_count > 0 (ray = i / fixed_count); a ray index outside [0, n_rays)
+ * reads ray 0.  rgb may be NULL (density only).
+ */
+txs_status txs_blob_field(const float* params, int32_t n_blobs, const float* rays_o,
+                          const float* rays_d, int32_t n_rays, const float* t0, const float* t1,
+                          const int32_t* ray_id, int32_t fixed_count, int64_t n, float* sigma,
+                          float* rgb, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TXS_H_ */

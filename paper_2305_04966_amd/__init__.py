@@ -1,0 +1,15 @@
+"""MI355X (gfx950) transmittance-estimator sampling and packed volume rendering.
+
+The compute runs in libtxs.so (hand-written HIP kernels behind the C ABI of
+include/txs.h); this package only marshals torch tensors into that ABI.
+Importing it does not touch the GPU; `load()` raises if the library is absent.
+"""
+from ._lib import (TXS_EHIP, TXS_EINVAL, TXS_ECAPACITY, TXS_EOVERFLOW, TXS_OK,
+                   TXS_PDF_SIGMA, TXS_PDF_WEIGHTS, LIB_PATH, TxsError, exported_symbols, load)
+from .ops import (GridSpec, blob_field, exclusive_scan, gather_prefix, march_count, march_fill,
+                  render_bwd, render_fwd, resample, transmittance_prefix, uniform_bins,
+                  weights_bwd)
+from .pipeline import (Packed, RenderFn, filter_transmittance, march, rendering,
+                       rendering_dense, sampling)
+
+__all__ = [n for n in dir() if not n.startswith("_")]

@@ -1,0 +1,149 @@
+// Inverse transform sampling from a transmittance estimator (Eqs. 1-3,
+// Section 3.1): the CDF of the rendering weights is 1 - T, so a piecewise-
+// constant density estimate gives its CDF in closed form and new interval
+// edges come from inverting it.  Also the uniform estimator (Table 1, first
+// row) that seeds a proposal round.
+#include <cmath>
+
+#include "txs_common.h"
+
+namespace txs {
+namespace {
+
+constexpr int kMaxBins = 1024;
+constexpr int kRsWaves = 4;
+
+// One wave per ray: wave-wide scan of the bin masses into the CDF, kept in
+// LDS, then one binary search per output edge.
+__global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(
+    int32_t n_rays, int32_t n_bins, const float* __restrict__ edges,
+    const float* __restrict__ vals, int32_t mode, int32_t n_out, const float* __restrict__ u,
+    float* __restrict__ out) {
+  __shared__ float lds_F[kRsWaves][kMaxBins + 1];
+  __shared__ float lds_e[kRsWaves][kMaxBins + 1];
+  const int w = threadIdx.x / kWave, ln = lane();
+  const int64_t r = (int64_t)blockIdx.x * kRsWaves + w;
+  if (r >= n_rays) return;
+  float* F = lds_F[w];
+  float* e = lds_e[w];
+  const float* er = edges + r * (n_bins + 1);
+  const float* vr = vals + r * n_bins;
+  for (int i = ln; i <= n_bins; i += kWave) e[i] = er[i];
+  wave_sync();
+  // running sum over bins in chunks of 64
+  float carry = 0.0f;
+  if (ln == 0) F[0] = 0.0f;
+  for (int base = 0; base < n_bins; base += kWave) {
+    const int i = base + ln;
+    float m = 0.0f;
+    if (i < n_bins) m = (mode == TXS_PDF_SIGMA) ? vr[i] * (e[i + 1] - e[i]) : vr[i];
+    float incl = m;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const float t = shfl_up(incl, d);
+      if (ln >= d) incl += t;
+    }
+    incl += carry;
+    if (i < n_bins) F[i + 1] = (mode == TXS_PDF_SIGMA) ? -expm1f(-incl) : incl;
+    carry = readlane(incl, kWave - 1);
+  }
+  wave_sync();
+  float Fn = F[n_bins];
+  const bool uniform = !(Fn > 1e-12f);
+  if (uniform) {
+    for (int i = ln; i <= n_bins; i += kWave) F[i] = (float)i / (float)n_bins;
+    wave_sync();
+    Fn = 1.0f;
+  }
+  for (int k = ln; k <= n_out; k += kWave) {
+    const float uk = u ? u[r * (n_out + 1) + k] : (float)k / (float)n_out;
+    const float up = uk * Fn;
+    // largest i in [0, n_bins] with F[i] <= up (F[0] = 0 <= up)
+    int lo = 0, hi = n_bins;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (F[mid] <= up) lo = mid;
+      else hi = mid - 1;
+    }
+    float t;
+    if (lo >= n_bins) {
+      t = e[n_bins];
+    } else {
+      const float f0 = F[lo], f1 = F[lo + 1];
+      const float frac = (up - f0) / (f1 - f0);
+      t = e[lo] + frac * (e[lo + 1] - e[lo]);
+    }
+    out[r * (n_out + 1) + k] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void uniform_bins_kernel(txs_grid g, float near_plane,
+                                                           float far_plane,
+                                                           const float* __restrict__ ro,
+                                                           const float* __restrict__ rd,
+                                                           int32_t n_rays, int32_t n_bins,
+                                                           float* __restrict__ out) {
+  const int64_t total = (int64_t)n_rays * (n_bins + 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t r = i / (n_bins + 1);
+  const int k = (int)(i - r * (n_bins + 1));
+  const float h = g.half_extent0 * (float)(1 << (g.n_levels - 1));
+  float tn = near_plane, tf = far_plane;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float inv = 1.0f / rd[3 * r + a];
+    const float o = ro[3 * r + a];
+    const float tlo = ((g.center[a] - h) - o) * inv;
+    const float thi = ((g.center[a] + h) - o) * inv;
+    tn = fmaxf(tn, fminf(tlo, thi));
+    tf = fminf(tf, fmaxf(tlo, thi));
+  }
+  if (!(tn < tf)) {
+    tn = near_plane;
+    tf = near_plane;
+  }
+  out[i] = tn + (tf - tn) * ((float)k / (float)n_bins);
+}
+
+}  // namespace
+}  // namespace txs
+
+extern "C" txs_status txs_resample(int32_t n_rays, int32_t n_bins, const float* edges,
+                                   const float* vals, int32_t mode, int32_t n_out,
+                                   const float* u, float* out_edges, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(n_rays >= 0, "txs_resample: n_rays < 0");
+  TXS_REQUIRE(n_bins >= 1 && n_bins <= kMaxBins, "txs_resample: n_bins must be in [1,%d]",
+              kMaxBins);
+  TXS_REQUIRE(n_out >= 1, "txs_resample: n_out must be >= 1");
+  TXS_REQUIRE(mode == TXS_PDF_SIGMA || mode == TXS_PDF_WEIGHTS, "txs_resample: bad mode %d",
+              mode);
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(edges && vals && out_edges, "txs_resample: null array");
+  const int64_t blocks = ((int64_t)n_rays + kRsWaves - 1) / kRsWaves;
+  hipLaunchKernelGGL(resample_kernel, dim3((unsigned)blocks), dim3(kWave * kRsWaves), 0,
+                     as_stream(stream), n_rays, n_bins, edges, vals, mode, n_out, u, out_edges);
+  return launch_status("txs_resample");
+}
+
+extern "C" txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, float far_plane,
+                                       const float* rays_o, const float* rays_d, int32_t n_rays,
+                                       int32_t n_bins, float* out_edges, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(grid, "txs_uniform_bins: null grid");
+  TXS_REQUIRE(grid->n_levels >= 1 && grid->n_levels <= 8, "txs_uniform_bins: bad n_levels");
+  TXS_REQUIRE(std::isfinite(grid->half_extent0) && grid->half_extent0 > 0,
+              "txs_uniform_bins: bad half_extent0");
+  TXS_REQUIRE(n_rays >= 0 && n_bins >= 1, "txs_uniform_bins: bad size");
+  TXS_REQUIRE(near_plane >= 0.0f && far_plane > near_plane, "txs_uniform_bins: bad planes");
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(rays_o && rays_d && out_edges, "txs_uniform_bins: null array");
+  const int64_t total = (int64_t)n_rays * (n_bins + 1);
+  hipLaunchKernelGGL(uniform_bins_kernel, dim3(grid_1d(total, 256)), dim3(256), 0,
+                     as_stream(stream), *grid, near_plane, far_plane, rays_o, rays_d, n_rays,
+                     n_bins, out_edges);
+  return launch_status("txs_uniform_bins");
+}

@@ -1,0 +1,165 @@
+// Packed-tensor bookkeeping (Section 4.2 "Packed Tensor"): exclusive scan of
+// per-ray counts into (start, count) rows, and the prefix repack that follows
+// no-gradient filtering.
+#include "txs_common.h"
+
+namespace txs {
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kPerThread = 16;
+constexpr int kTile = kScanBlock * kPerThread;  // counts per tile
+constexpr int kTopBlock = 1024;
+
+// Block-wide exclusive scan of one int64 per thread; returns the block total.
+__device__ int64_t block_exclusive_scan(int64_t& v, int64_t* lds_wave) {
+  const int ln = lane(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  int64_t incl = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t t = shfl_up(incl, d);
+    if (ln >= d) incl += t;
+  }
+  if (ln == kWave - 1) lds_wave[w] = incl;
+  __syncthreads();
+  int64_t wave_off = 0, total = 0;
+  for (int i = 0; i < nw; ++i) {
+    const int64_t s = lds_wave[i];
+    if (i < w) wave_off += s;
+    total += s;
+  }
+  __syncthreads();
+  v = incl - v + wave_off;
+  return total;
+}
+
+// Pass 1: per-tile sums of the counts.
+__global__ __launch_bounds__(kScanBlock) void tile_sums(const int32_t* __restrict__ counts,
+                                                        int32_t n, int64_t* __restrict__ sums) {
+  __shared__ int64_t lds[kScanBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * kPerThread;
+  int64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kPerThread; ++j)
+    if (base + j < n) s += counts[base + j];
+  const int64_t total = block_exclusive_scan(s, lds);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Pass 2: one block scans the tile sums in place (exclusive) and writes the total.
+__global__ __launch_bounds__(kTopBlock) void scan_tile_sums(int64_t* sums, int32_t n_tiles,
+                                                            int64_t* d_total) {
+  __shared__ int64_t lds[kTopBlock / kWave];
+  int64_t carry = 0;
+  for (int32_t base = 0; base < n_tiles; base += kTopBlock) {
+    const int32_t i = base + threadIdx.x;
+    int64_t v = (i < n_tiles) ? sums[i] : 0;
+    const int64_t total = block_exclusive_scan(v, lds);
+    if (i < n_tiles) sums[i] = v + carry;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *d_total = carry;
+}
+
+// Pass 3: per-tile exclusive scan plus tile offset -> packed_info rows.
+__global__ __launch_bounds__(kScanBlock) void write_packed(const int32_t* __restrict__ counts,
+                                                           int32_t n,
+                                                           const int64_t* __restrict__ offs,
+                                                           int32_t* __restrict__ info) {
+  __shared__ int64_t lds[kScanBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * kPerThread;
+  int32_t c[kPerThread];
+  int64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kPerThread; ++j) {
+    c[j] = (base + j < n) ? counts[base + j] : 0;
+    s += c[j];
+  }
+  block_exclusive_scan(s, lds);
+  int64_t start = s + offs[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kPerThread; ++j) {
+    if (base + j < n) {
+      // starts beyond INT32_MAX wrap; the caller checks the int64 total
+      info[2 * (base + j)] = (int32_t)start;
+      info[2 * (base + j) + 1] = c[j];
+    }
+    start += c[j];
+  }
+}
+
+// Repack: one thread per input sample; keeps sample i of ray r iff its rank
+// inside the ray is below the output count of r.
+__global__ __launch_bounds__(256) void gather_prefix_kernel(
+    const int32_t* __restrict__ info_in, const int32_t* __restrict__ info_out, int32_t n_rays,
+    int64_t n_in, const float* __restrict__ t0, const float* __restrict__ t1,
+    const int32_t* __restrict__ ray_id, int64_t capacity, float* __restrict__ t0o,
+    float* __restrict__ t1o, int32_t* __restrict__ rido) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += stride) {
+    const int32_t r = ray_id[i];
+    if (r < 0 || r >= n_rays) continue;
+    const int64_t rank = i - (int64_t)info_in[2 * (int64_t)r];
+    const int32_t keep = info_out[2 * (int64_t)r + 1];
+    if (rank < 0 || rank >= keep) continue;
+    const int64_t o = (int64_t)info_out[2 * (int64_t)r] + rank;
+    if (o >= capacity) continue;
+    t0o[o] = t0[i];
+    t1o[o] = t1[i];
+    if (rido) rido[o] = r;
+  }
+}
+
+}  // namespace
+}  // namespace txs
+
+extern "C" size_t txs_scan_workspace_size(int32_t n_rays) {
+  const int64_t tiles = n_rays > 0 ? ((int64_t)n_rays + txs::kTile - 1) / txs::kTile : 1;
+  return (size_t)tiles * sizeof(int64_t);
+}
+
+extern "C" txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays,
+                                         int32_t* packed_info, int64_t* d_total,
+                                         void* workspace, size_t workspace_bytes, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(n_rays >= 0, "txs_exclusive_scan: n_rays < 0");
+  TXS_REQUIRE(d_total, "txs_exclusive_scan: null d_total");
+  TXS_REQUIRE(n_rays == 0 || (counts && packed_info), "txs_exclusive_scan: null array");
+  const size_t need = txs_scan_workspace_size(n_rays);
+  if (!workspace || workspace_bytes < need) {
+    set_error("txs_exclusive_scan: workspace needs %zu bytes, got %zu", need, workspace_bytes);
+    return TXS_ECAPACITY;
+  }
+  const int32_t tiles = (int32_t)((int64_t)std::max<int32_t>(n_rays, 1) + kTile - 1) / kTile;
+  int64_t* sums = static_cast<int64_t*>(workspace);
+  hipStream_t s = as_stream(stream);
+  if (n_rays > 0)
+    hipLaunchKernelGGL(tile_sums, dim3(tiles), dim3(kScanBlock), 0, s, counts, n_rays, sums);
+  else
+    hipLaunchKernelGGL(tile_sums, dim3(1), dim3(kScanBlock), 0, s, counts, 0, sums);
+  hipLaunchKernelGGL(scan_tile_sums, dim3(1), dim3(kTopBlock), 0, s, sums, tiles, d_total);
+  if (n_rays > 0)
+    hipLaunchKernelGGL(write_packed, dim3(tiles), dim3(kScanBlock), 0, s, counts, n_rays, sums,
+                       packed_info);
+  return launch_status("txs_exclusive_scan");
+}
+
+extern "C" txs_status txs_gather_prefix(const int32_t* packed_info_in,
+                                        const int32_t* packed_info_out, int32_t n_rays,
+                                        int64_t n_in, const float* t0, const float* t1,
+                                        const int32_t* ray_id, int64_t capacity, float* t0o,
+                                        float* t1o, int32_t* ray_ido, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(n_rays >= 0 && n_in >= 0 && capacity >= 0, "txs_gather_prefix: negative size");
+  if (n_rays == 0 || n_in == 0) return TXS_OK;
+  TXS_REQUIRE(packed_info_in && packed_info_out && t0 && t1 && ray_id,
+              "txs_gather_prefix: null input");
+  TXS_REQUIRE(capacity == 0 || (t0o && t1o), "txs_gather_prefix: null output");
+  const int64_t blocks = std::min<int64_t>((n_in + 255) / 256, 65536);
+  hipLaunchKernelGGL(gather_prefix_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     as_stream(stream), packed_info_in, packed_info_out, n_rays, n_in, t0, t1,
+                     ray_id, capacity, t0o, t1o, ray_ido);
+  return launch_status("txs_gather_prefix");
+}

@@ -1,0 +1,75 @@
+// Shared host/device helpers of the txs HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "txs.h"
+
+namespace txs {
+
+// ---------------------------------------------------------------- host side
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+// Status of the kernel launches enqueued since the last check.
+txs_status launch_status(const char* what);
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+#define TXS_REQUIRE(cond, ...)           \
+  do {                                   \
+    if (!(cond)) {                       \
+      ::txs::set_error(__VA_ARGS__);     \
+      return TXS_EINVAL;                 \
+    }                                    \
+  } while (0)
+
+inline unsigned grid_1d(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+// -------------------------------------------------------------- device side
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane() { return static_cast<int>(__lane_id()); }
+
+template <typename T>
+__device__ __forceinline__ T shfl_up(T v, int d) { return __shfl_up(v, d, kWave); }
+template <typename T>
+__device__ __forceinline__ T shfl_down(T v, int d) { return __shfl_down(v, d, kWave); }
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, kWave); }
+
+__device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ int64_t wave_max(int64_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t t = __shfl_xor((long long)v, d, kWave);
+    v = v > t ? v : t;
+  }
+  return v;
+}
+__device__ __forceinline__ int64_t wave_min(int64_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t t = __shfl_xor((long long)v, d, kWave);
+    v = v < t ? v : t;
+  }
+  return v;
+}
+
+// Keeps the compiler from moving memory operations across this point; the
+// hardware already executes one wave's LDS operations in order.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
+}  // namespace txs

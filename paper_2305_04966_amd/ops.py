@@ -1,0 +1,258 @@
+"""Thin Python binding of the txs C ABI: one function per entry point, same names.
+
+Every function takes CUDA (HIP) torch tensors, checks dtype / layout / device,
+allocates the outputs with torch (device memory only) and calls the library on
+torch's current stream.  No computation of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from ._lib import TXS_PDF_SIGMA, TXS_PDF_WEIGHTS, Grid, MarchParams, check, load
+
+__all__ = ["GridSpec", "march_count", "exclusive_scan", "march_fill", "transmittance_prefix",
+           "gather_prefix", "render_fwd", "render_bwd", "weights_bwd", "resample",
+           "uniform_bins", "blob_field", "TXS_PDF_SIGMA", "TXS_PDF_WEIGHTS"]
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _opt(t, name, dtype, shape=None):
+    return None if t is None else _need(t, name, dtype, shape)
+
+
+@dataclass
+class GridSpec:
+    """Occupancy grid: bits (uint32-in-int32 tensor), res, levels, box."""
+    bits: torch.Tensor
+    res: int
+    n_levels: int = 1
+    center: tuple = (0.0, 0.0, 0.0)
+    half_extent0: float = 1.5
+
+    def struct(self) -> Grid:
+        _need(self.bits, "grid.bits", torch.int32)
+        if self.bits.numel() * 32 < self.n_levels * self.res ** 3:
+            raise ValueError("grid.bits holds fewer than n_levels*res^3 bits")
+        g = Grid()
+        g.bits = self.bits.data_ptr()
+        g.res = self.res
+        g.n_levels = self.n_levels
+        g.center = (C.c_float * 3)(*self.center)
+        g.half_extent0 = self.half_extent0
+        return g
+
+
+def _params(near, far, dt0, max_per_ray):
+    p = MarchParams()
+    p.near_plane, p.far_plane, p.dt0, p.max_per_ray = near, far, dt0, max_per_ray
+    return p
+
+
+def _rays(rays_o, rays_d):
+    n = rays_o.shape[0]
+    _need(rays_o, "rays_o", torch.float32, (n, 3))
+    _need(rays_d, "rays_d", torch.float32, (n, 3))
+    return n
+
+
+def march_count(grid: GridSpec, rays_o, rays_d, *, near=0.0, far=float("inf"), dt0,
+                max_per_ray=0, counts=None):
+    n = _rays(rays_o, rays_d)
+    counts = counts if counts is not None else torch.empty(n, dtype=torch.int32,
+                                                           device=rays_o.device)
+    _need(counts, "counts", torch.int32, (n,))
+    g, p = grid.struct(), _params(near, far, dt0, max_per_ray)
+    check(load().txs_march_count(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d), n,
+                                 _ptr(counts), _stream()), "txs_march_count")
+    return counts
+
+
+def exclusive_scan(counts, packed_info=None, total=None):
+    """-> (packed_info int32 [N,2], total int64 [1] on the device)."""
+    n = counts.shape[0]
+    _need(counts, "counts", torch.int32, (n,))
+    dev = counts.device
+    packed_info = packed_info if packed_info is not None else torch.empty(
+        (n, 2), dtype=torch.int32, device=dev)
+    total = total if total is not None else torch.empty(1, dtype=torch.int64, device=dev)
+    _need(packed_info, "packed_info", torch.int32, (n, 2))
+    _need(total, "total", torch.int64, (1,))
+    L = load()
+    ws_bytes = int(L.txs_scan_workspace_size(n))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    check(L.txs_exclusive_scan(_ptr(counts), n, _ptr(packed_info), _ptr(total), _ptr(ws),
+                               ws_bytes, _stream()), "txs_exclusive_scan")
+    return packed_info, total
+
+
+def march_fill(grid: GridSpec, rays_o, rays_d, packed_info, n_samples, *, near=0.0,
+               far=float("inf"), dt0, max_per_ray=0, want_ray_id=True):
+    n = _rays(rays_o, rays_d)
+    _need(packed_info, "packed_info", torch.int32, (n, 2))
+    dev = rays_o.device
+    t0 = torch.empty(n_samples, dtype=torch.float32, device=dev)
+    t1 = torch.empty(n_samples, dtype=torch.float32, device=dev)
+    rid = torch.empty(n_samples, dtype=torch.int32, device=dev) if want_ray_id else None
+    g, p = grid.struct(), _params(near, far, dt0, max_per_ray)
+    check(load().txs_march_fill(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d), n,
+                                _ptr(packed_info), n_samples, _ptr(t0), _ptr(t1), _ptr(rid),
+                                _stream()), "txs_march_fill")
+    return t0, t1, rid
+
+
+def transmittance_prefix(packed_info, t0, t1, sigma, t_min=1e-4):
+    n = packed_info.shape[0]
+    s = t0.shape[0]
+    _need(packed_info, "packed_info", torch.int32, (n, 2))
+    for name, t in (("t0", t0), ("t1", t1), ("sigma", sigma)):
+        _need(t, name, torch.float32, (s,))
+    kept = torch.empty(n, dtype=torch.int32, device=t0.device)
+    check(load().txs_transmittance_prefix(_ptr(packed_info), n, s, _ptr(t0), _ptr(t1),
+                                          _ptr(sigma), float(t_min), _ptr(kept), _stream()),
+          "txs_transmittance_prefix")
+    return kept
+
+
+def gather_prefix(packed_info_in, packed_info_out, n_out, t0, t1, ray_id, want_ray_id=True):
+    n = packed_info_in.shape[0]
+    s = t0.shape[0]
+    _need(packed_info_in, "packed_info_in", torch.int32, (n, 2))
+    _need(packed_info_out, "packed_info_out", torch.int32, (n, 2))
+    _need(t0, "t0", torch.float32, (s,))
+    _need(t1, "t1", torch.float32, (s,))
+    _need(ray_id, "ray_id", torch.int32, (s,))
+    dev = t0.device
+    t0o = torch.empty(n_out, dtype=torch.float32, device=dev)
+    t1o = torch.empty(n_out, dtype=torch.float32, device=dev)
+    rido = torch.empty(n_out, dtype=torch.int32, device=dev) if want_ray_id else None
+    check(load().txs_gather_prefix(_ptr(packed_info_in), _ptr(packed_info_out), n, s, _ptr(t0),
+                                   _ptr(t1), _ptr(ray_id), n_out, _ptr(t0o), _ptr(t1o),
+                                   _ptr(rido), _stream()), "txs_gather_prefix")
+    return t0o, t1o, rido
+
+
+def _layout(packed_info, fixed_count, n_rays):
+    if packed_info is not None:
+        _need(packed_info, "packed_info", torch.int32, (n_rays, 2))
+        return 0
+    if fixed_count is None or fixed_count < 0:
+        raise ValueError("dense layout needs fixed_count >= 0")
+    return int(fixed_count)
+
+
+def render_fwd(packed_info, t0, t1, sigma, rgb, *, n_rays=None, fixed_count=None, bg=None,
+               want_weights=False):
+    """-> (rgb [N,3], opacity [N], depth [N], weights [S] or None)."""
+    n = packed_info.shape[0] if packed_info is not None else int(n_rays)
+    fc = _layout(packed_info, fixed_count, n)
+    s = t0.shape[0]
+    for name, t in (("t0", t0), ("t1", t1), ("sigma", sigma)):
+        _need(t, name, torch.float32, (s,))
+    _need(rgb, "rgb", torch.float32, (s, 3))
+    _opt(bg, "bg", torch.float32, (n, 3))
+    dev = t0.device
+    out_rgb = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    out_op = torch.empty(n, dtype=torch.float32, device=dev)
+    out_d = torch.empty(n, dtype=torch.float32, device=dev)
+    w = torch.empty(s, dtype=torch.float32, device=dev) if want_weights else None
+    check(load().txs_render_fwd(_ptr(packed_info), fc, n, s, _ptr(t0), _ptr(t1), _ptr(sigma),
+                                _ptr(rgb), _ptr(bg), _ptr(out_rgb), _ptr(out_op), _ptr(out_d),
+                                _ptr(w), _stream()), "txs_render_fwd")
+    return out_rgb, out_op, out_d, w
+
+
+def render_bwd(packed_info, t0, t1, sigma, rgb, g_rgb, g_opacity=None, g_depth=None, *,
+               n_rays=None, fixed_count=None, bg=None, want_d_rgb=True):
+    """-> (d_sigma [S], d_rgb [S,3] or None)."""
+    n = packed_info.shape[0] if packed_info is not None else int(n_rays)
+    fc = _layout(packed_info, fixed_count, n)
+    s = t0.shape[0]
+    for name, t in (("t0", t0), ("t1", t1), ("sigma", sigma)):
+        _need(t, name, torch.float32, (s,))
+    _need(rgb, "rgb", torch.float32, (s, 3))
+    _need(g_rgb, "g_rgb", torch.float32, (n, 3))
+    _opt(g_opacity, "g_opacity", torch.float32, (n,))
+    _opt(g_depth, "g_depth", torch.float32, (n,))
+    _opt(bg, "bg", torch.float32, (n, 3))
+    dev = t0.device
+    ds = torch.empty(s, dtype=torch.float32, device=dev)
+    dr = torch.empty((s, 3), dtype=torch.float32, device=dev) if want_d_rgb else None
+    check(load().txs_render_bwd(_ptr(packed_info), fc, n, s, _ptr(t0), _ptr(t1), _ptr(sigma),
+                                _ptr(rgb), _ptr(bg), _ptr(g_rgb), _ptr(g_opacity),
+                                _ptr(g_depth), _ptr(ds), _ptr(dr), _stream()), "txs_render_bwd")
+    return ds, dr
+
+
+def weights_bwd(packed_info, t0, t1, sigma, g_w, *, n_rays=None, fixed_count=None):
+    n = packed_info.shape[0] if packed_info is not None else int(n_rays)
+    fc = _layout(packed_info, fixed_count, n)
+    s = t0.shape[0]
+    for name, t in (("t0", t0), ("t1", t1), ("sigma", sigma), ("g_w", g_w)):
+        _need(t, name, torch.float32, (s,))
+    ds = torch.empty(s, dtype=torch.float32, device=t0.device)
+    check(load().txs_weights_bwd(_ptr(packed_info), fc, n, s, _ptr(t0), _ptr(t1), _ptr(sigma),
+                                 _ptr(g_w), _ptr(ds), _stream()), "txs_weights_bwd")
+    return ds
+
+
+def resample(edges, vals, n_out, mode=TXS_PDF_SIGMA, u=None):
+    n, nb1 = edges.shape
+    _need(edges, "edges", torch.float32, (n, nb1))
+    _need(vals, "vals", torch.float32, (n, nb1 - 1))
+    _opt(u, "u", torch.float32, (n, n_out + 1))
+    out = torch.empty((n, n_out + 1), dtype=torch.float32, device=edges.device)
+    check(load().txs_resample(n, nb1 - 1, _ptr(edges), _ptr(vals), mode, n_out, _ptr(u),
+                              _ptr(out), _stream()), "txs_resample")
+    return out
+
+
+def uniform_bins(grid: GridSpec, rays_o, rays_d, n_bins, *, near=0.0, far=float("inf")):
+    n = _rays(rays_o, rays_d)
+    out = torch.empty((n, n_bins + 1), dtype=torch.float32, device=rays_o.device)
+    g = grid.struct()
+    check(load().txs_uniform_bins(C.byref(g), float(near), float(far), _ptr(rays_o),
+                                  _ptr(rays_d), n, n_bins, _ptr(out), _stream()),
+          "txs_uniform_bins")
+    return out
+
+
+def blob_field(params, n_blobs, rays_o, rays_d, t0, t1, ray_id=None, fixed_count=0,
+               want_rgb=True):
+    """Support: analytic stand-in radiance field at interval midpoints."""
+    n_rays = _rays(rays_o, rays_d)
+    s = t0.shape[0]
+    _need(params, "params", torch.float32, (32 + 3 * n_blobs,))
+    _need(t0, "t0", torch.float32, (s,))
+    _need(t1, "t1", torch.float32, (s,))
+    _opt(ray_id, "ray_id", torch.int32, (s,))
+    dev = t0.device
+    sigma = torch.empty(s, dtype=torch.float32, device=dev)
+    rgb = torch.empty((s, 3), dtype=torch.float32, device=dev) if want_rgb else None
+    check(load().txs_blob_field(_ptr(params), n_blobs, _ptr(rays_o), _ptr(rays_d), n_rays, _ptr(t0),
+                                _ptr(t1), _ptr(ray_id), int(fixed_count), s, _ptr(sigma),
+                                _ptr(rgb), _stream()), "txs_blob_field")
+    return sigma, rgb

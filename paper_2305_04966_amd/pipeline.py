@@ -1,0 +1,104 @@
+"""Composition of the C-ABI calls into the paper's rendering pipeline (Algorithm 1).
+
+sampling:  march_count -> exclusive_scan -> (one host read of the total) ->
+           march_fill -> density (no grad) -> transmittance_prefix ->
+           exclusive_scan -> gather_prefix
+rendering: render_fwd, with render_bwd as the autograd backward.
+Only argument plumbing lives here; every step runs in the HIP library.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Callable, Optional
+
+import torch
+
+from . import ops
+from ._lib import TXS_EOVERFLOW, TxsError
+
+INT32_LIMIT = 2 ** 31
+
+
+@dataclass
+class Packed:
+    """Packed interval samples (Section 4.2): per-ray (start, count) + samples."""
+    packed_info: torch.Tensor  # int32 [N, 2]
+    t0: torch.Tensor           # float32 [S]
+    t1: torch.Tensor           # float32 [S]
+    ray_id: Optional[torch.Tensor]  # int32 [S]
+
+    @property
+    def n_samples(self) -> int:
+        return int(self.t0.shape[0])
+
+
+def _host_total(total: torch.Tensor) -> int:
+    s = int(total.item())  # the one device -> host read of a sampling pass
+    if s >= INT32_LIMIT:
+        raise TxsError(TXS_EOVERFLOW, f"{s} samples do not fit the int32 packed layout")
+    return s
+
+
+def march(grid: ops.GridSpec, rays_o, rays_d, *, dt0, near=0.0, far=float("inf"),
+          max_per_ray=0) -> Packed:
+    counts = ops.march_count(grid, rays_o, rays_d, near=near, far=far, dt0=dt0,
+                             max_per_ray=max_per_ray)
+    info, total = ops.exclusive_scan(counts)
+    s = _host_total(total)
+    t0, t1, rid = ops.march_fill(grid, rays_o, rays_d, info, s, near=near, far=far, dt0=dt0,
+                                 max_per_ray=max_per_ray)
+    return Packed(info, t0, t1, rid)
+
+
+def filter_transmittance(p: Packed, sigma, t_min=1e-4) -> Packed:
+    """No-gradient filtering: keep each ray's prefix with T >= t_min."""
+    kept = ops.transmittance_prefix(p.packed_info, p.t0, p.t1, sigma, t_min)
+    info, total = ops.exclusive_scan(kept)
+    s = _host_total(total)
+    t0, t1, rid = ops.gather_prefix(p.packed_info, info, s, p.t0, p.t1, p.ray_id)
+    return Packed(info, t0, t1, rid)
+
+
+def sampling(grid: ops.GridSpec, rays_o, rays_d, density_fn: Callable, *, dt0,
+             near=0.0, far=float("inf"), t_min=1e-4) -> Packed:
+    """Occupancy-grid sampling followed by no-gradient filtering (Algorithm 1)."""
+    p = march(grid, rays_o, rays_d, dt0=dt0, near=near, far=far)
+    with torch.no_grad():
+        sigma = density_fn(p.t0, p.t1, p.ray_id)
+    return filter_transmittance(p, sigma, t_min)
+
+
+class RenderFn(torch.autograd.Function):
+    """Differentiable packed compositing; backward recomputes T and w."""
+
+    @staticmethod
+    def forward(ctx, sigma, rgb, packed_info, t0, t1, bg, n_rays, fixed_count):
+        out_rgb, out_op, out_d, _ = ops.render_fwd(packed_info, t0, t1, sigma.contiguous(),
+                                                   rgb.contiguous(), n_rays=n_rays,
+                                                   fixed_count=fixed_count, bg=bg)
+        ctx.save_for_backward(sigma, rgb, packed_info, t0, t1, bg)
+        ctx.n_rays, ctx.fixed_count = n_rays, fixed_count
+        return out_rgb, out_op, out_d
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_op, g_d):
+        sigma, rgb, packed_info, t0, t1, bg = ctx.saved_tensors
+        n = ctx.n_rays
+        dev = t0.device
+        g_rgb = g_rgb.contiguous() if g_rgb is not None else torch.zeros((n, 3), device=dev)
+        g_op = g_op.contiguous() if g_op is not None else None
+        g_d = g_d.contiguous() if g_d is not None else None
+        ds, dr = ops.render_bwd(packed_info, t0, t1, sigma.contiguous(), rgb.contiguous(),
+                                g_rgb, g_op, g_d, n_rays=n, fixed_count=ctx.fixed_count, bg=bg,
+                                want_d_rgb=ctx.needs_input_grad[1])
+        return ds, dr, None, None, None, None, None, None
+
+
+def rendering(p: Packed, sigma, rgb, bg=None):
+    """-> (rgb [N,3], opacity [N], depth [N]); differentiable in sigma and rgb."""
+    n = p.packed_info.shape[0]
+    return RenderFn.apply(sigma, rgb, p.packed_info, p.t0, p.t1, bg, n, None)
+
+
+def rendering_dense(t0, t1, sigma, rgb, n_rays, fixed_count, bg=None):
+    return RenderFn.apply(sigma, rgb, None, t0, t1, bg, n_rays, fixed_count)

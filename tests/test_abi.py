@@ -1,0 +1,51 @@
+"""The C-ABI library loads and exports every entry point include/txs.h declares
+(no GPU needed: nothing is launched)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "txs.h")
+LIB = os.path.join(ROOT, "paper_2305_04966_amd", "libtxs.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(txs_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import paper_2305_04966_amd.build as b
+        b.build()
+    return C.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_binding_covers_the_header():
+    from paper_2305_04966_amd import exported_symbols
+    assert set(declared_symbols()) == set(exported_symbols())
+
+
+def test_version_and_error_without_gpu(lib):
+    lib.txs_abi_version.restype = C.c_int32
+    lib.txs_last_error.restype = C.c_char_p
+    assert lib.txs_abi_version() == 1
+    # argument validation happens on the host before any launch
+    lib.txs_resample.restype = C.c_int32
+    st = lib.txs_resample(C.c_int32(4), C.c_int32(0), None, None, C.c_int32(0), C.c_int32(8),
+                          None, None, None)
+    assert st == -1
+    assert b"n_bins" in lib.txs_last_error()
+    lib.txs_scan_workspace_size.restype = C.c_size_t
+    assert lib.txs_scan_workspace_size(C.c_int32(1 << 20)) >= 8 * 256

@@ -1,0 +1,436 @@
+"""GPU parity: every C-ABI entry point of the HIP library against the FP64 oracle.
+
+Indices, counts and packed layouts must match bit for bit; floating-point
+outputs within the relative bar |x - x_ref| <= 1e-5 |x_ref| + 1e-5 s, where s
+is 1e-3 max|x_ref| for forward outputs and the per-sample conditioning scale
+Delta_k (T_{k+1}|v_k| + sum_{j>k} w_j |v_j|) for the density adjoint.
+Threshold decisions on accumulated quantities (the T >= 1e-4 prefix, the CDF
+bin of an inverse-CDF edge) may differ only where the oracle flags the value
+as within relative 1e-5 of the threshold.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from gpu_util import assert_close, bwd_condition, dev, grid_spec, host, segment_ids
+
+pytestmark = pytest.mark.gpu
+
+
+# ----------------------------------------------------------------------------
+# fixtures
+# ----------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def tiny():
+    w = scenes.tiny()
+    return w
+
+
+def gpu_march(txs, w, rays=None, **kw):
+    o, d = (w.rays_o, w.rays_d) if rays is None else rays
+    g = grid_spec(txs, w.bits, w.res, w.n_levels, w.half_extent0)
+    p = txs.march(g, dev(o), dev(d), dt0=w.dt0, near=kw.get("near", w.near),
+                  far=kw.get("far", w.far), max_per_ray=kw.get("max_per_ray", 0))
+    torch.cuda.synchronize()
+    return p
+
+
+def oracle_march(w, rays=None, **kw):
+    o, d = (w.rays_o, w.rays_d) if rays is None else rays
+    return oracle.march(o, d, w.bits, w.res, n_levels=w.n_levels, half_extent0=w.half_extent0,
+                        near=kw.get("near", w.near), far=kw.get("far", w.far), dt0=w.dt0,
+                        max_per_ray=kw.get("max_per_ray", 0))
+
+
+def assert_march_equal(p, ref):
+    assert np.array_equal(host(p.packed_info), ref["packed_info"])
+    assert np.array_equal(host(p.t0), ref["t0"])
+    assert np.array_equal(host(p.t1), ref["t1"])
+    assert np.array_equal(host(p.ray_id), ref["ray_id"])
+
+
+def field_inputs(w, ref):
+    """float32 sigma / rgb of the analytic field at the oracle's samples."""
+    s, c = oracle.field_at_samples(w.rays_o, w.rays_d, ref["t0"], ref["t1"], ref["ray_id"],
+                                   w.fld.packed_params())
+    return s.astype(np.float32), c.astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# march
+# ----------------------------------------------------------------------------
+def test_march_tiny_bit_exact(gpu_lib, tiny):
+    p = gpu_march(gpu_lib, tiny)
+    ref = oracle_march(tiny)
+    assert ref["total"] > 10000
+    assert_march_equal(p, ref)
+
+
+def test_march_image_reduced_bit_exact(gpu_lib):
+    w = scenes.image(256, 256)
+    assert_march_equal(gpu_march(gpu_lib, w), oracle_march(w))
+
+
+def test_march_image_full_size_sampled_rays(gpu_lib):
+    # 1024x1024 rays in the benchmark's launch; every 37th ray checked by the oracle
+    w = scenes.image()
+    p = gpu_march(gpu_lib, w)
+    idx = np.arange(0, w.n_rays, 37)
+    ref = oracle_march(w, rays=(w.rays_o[idx], w.rays_d[idx]))
+    info = host(p.packed_info)
+    assert np.array_equal(info[idx, 1], ref["counts"])
+    t0, t1 = host(p.t0), host(p.t1)
+    sel = np.concatenate([np.arange(info[r, 0], info[r, 0] + info[r, 1]) for r in idx])
+    assert np.array_equal(t0[sel], ref["t0"]) and np.array_equal(t1[sel], ref["t1"])
+    # packed layout is the exclusive scan of the counts
+    counts = info[:, 1].astype(np.int64)
+    assert np.array_equal(info[:, 0], np.concatenate([[0], np.cumsum(counts)[:-1]]))
+    assert p.n_samples == counts.sum()
+
+
+def test_march_cascade_bit_exact(gpu_lib):
+    w = scenes.unbounded(128, 64, n_cams=8, res=64)
+    ref = oracle_march(w)
+    assert ref["total"] > 0
+    assert_march_equal(gpu_march(gpu_lib, w), ref)
+
+
+@pytest.mark.parametrize("kw", [dict(max_per_ray=11), dict(near=2.5, far=3.4),
+                                dict(near=0.5)])
+def test_march_options(gpu_lib, tiny, kw):
+    assert_march_equal(gpu_march(gpu_lib, tiny, **kw), oracle_march(tiny, **kw))
+
+
+def test_march_adversarial_rays(gpu_lib):
+    # axis-parallel rays on cell planes, rays through cell corners, tiny components
+    res = 16
+    g = scenes.rng(5)
+    cell = 3.0 / res
+    n = 4000
+    o = np.zeros((n, 3))
+    d = np.zeros((n, 3))
+    for i in range(n):
+        a = g.integers(0, 3)
+        oo = g.integers(0, res + 1, 3) * cell - 1.5
+        if g.random() < 0.5:
+            oo = oo + g.integers(-2, 3, 3) * 1e-7
+        oo[a] = -3.0 if g.random() < 0.5 else 3.0
+        dd = np.zeros(3)
+        dd[a] = -np.sign(oo[a])
+        if g.random() < 0.3:
+            dd = dd + g.standard_normal(3) * [1e-7, 1e-3, 1e-5][g.integers(0, 3)]
+        o[i], d[i] = oo, dd / np.linalg.norm(dd)
+    diag = g.choice([-1.0, 1.0], (n, 3))
+    diag /= np.linalg.norm(diag, axis=1, keepdims=True)
+    o = np.concatenate([o, -3 * diag + g.integers(-4, 5, (n, 3)) * cell]).astype(np.float32)
+    d = np.concatenate([d, diag]).astype(np.float32)
+    w = scenes.Workload("adv", scenes.blob_field(8), scenes.random_bits(res, 0.3, 7), res, 1, 1.5,
+                        o, d, 0.0123)
+    assert_march_equal(gpu_march(gpu_lib, w), oracle_march(w))
+
+
+def test_march_degenerate_grids_and_sizes(gpu_lib, tiny):
+    o, d = tiny.rays_o[:777], tiny.rays_d[:777]
+    for bits in (np.zeros_like(tiny.bits), np.full_like(tiny.bits, 0xFFFFFFFF)):
+        w = scenes.Workload("x", tiny.fld, bits, 64, 1, 1.5, o, d, 0.01)
+        assert_march_equal(gpu_march(gpu_lib, w), oracle_march(w))
+    # no rays at all; rays that all miss
+    w0 = scenes.Workload("x", tiny.fld, tiny.bits, 64, 1, 1.5, o[:0], d[:0], 0.01)
+    p = gpu_march(gpu_lib, w0)
+    assert p.n_samples == 0 and p.packed_info.shape == (0, 2)
+    miss_o = np.tile(np.float32([[0, 0, 5.0]]), (100, 1))
+    miss_d = np.tile(np.float32([[0, 0, 1.0]]), (100, 1))
+    p = gpu_march(gpu_lib, tiny, rays=(miss_o, miss_d))
+    assert p.n_samples == 0 and host(p.packed_info)[:, 1].sum() == 0
+
+
+# ----------------------------------------------------------------------------
+# scan / filter / gather
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [0, 1, 63, 4096, 4097, 123457, (1 << 20) + 17])
+def test_exclusive_scan(gpu_lib, n):
+    g = scenes.rng(n + 1)
+    counts = g.integers(0, 700, n).astype(np.int32)
+    counts[g.random(n) < 0.3] = 0
+    info, total = gpu_lib.exclusive_scan(dev(counts))
+    ref_info, ref_total = oracle.exclusive_scan(counts)
+    assert int(total.item()) == ref_total
+    assert np.array_equal(host(info), ref_info.reshape(n, 2))
+
+
+def test_filter_and_gather(gpu_lib, tiny):
+    ref = oracle_march(tiny)
+    sig, _ = field_inputs(tiny, ref)
+    p = gpu_march(gpu_lib, tiny)
+    kept = host(gpu_lib.transmittance_prefix(p.packed_info, p.t0, p.t1, dev(sig), 1e-4))
+    ref_kept, band = oracle.transmittance_prefix(ref["packed_info"], ref["t0"], ref["t1"], sig,
+                                                 1e-4)
+    diff = kept != ref_kept
+    assert not (diff & ~band).any()
+    assert (kept < ref["counts"]).sum() > 100  # the filter is exercised
+    # repack with the oracle's decision so both sides gather the same prefix
+    kept_t = dev(ref_kept)
+    info2, total2 = gpu_lib.exclusive_scan(kept_t)
+    s2 = int(total2.item())
+    t0o, t1o, rido = gpu_lib.gather_prefix(p.packed_info, info2, s2, p.t0, p.t1, p.ray_id)
+    r_info, r_t0, r_t1, r_rid = oracle.gather_prefix(ref["packed_info"], ref_kept, ref["t0"],
+                                                     ref["t1"], ref["ray_id"])
+    assert np.array_equal(host(info2), r_info)
+    assert np.array_equal(host(t0o), r_t0) and np.array_equal(host(t1o), r_t1)
+    assert np.array_equal(host(rido), r_rid)
+
+
+def test_filter_thresholds(gpu_lib):
+    # constant-density rays: kept = #{i : i sigma Delta <= ln(1e4)}
+    counts = np.array([400, 400, 400, 5, 1, 0], np.int32)
+    info, S = oracle.exclusive_scan(counts)
+    dt = np.float32(0.01)
+    t0 = np.concatenate([np.arange(c) * dt for c in counts]).astype(np.float32)
+    t1 = (t0 + dt).astype(np.float32)
+    sig = np.concatenate([np.full(c, s) for c, s in zip(counts, [0.0, 7.3, 123.0, 1e4, 3.0, 1.0])
+                          ]).astype(np.float32)
+    kept = host(gpu_lib.transmittance_prefix(dev(info), dev(t0), dev(t1), dev(sig), 1e-4))
+    ref, band = oracle.transmittance_prefix(info, t0, t1, sig, 1e-4)
+    assert np.array_equal(kept[~band], ref[~band])
+    assert kept[0] == 400 and kept[3] == 1 and kept[4] == 1 and kept[5] == 0
+
+
+# ----------------------------------------------------------------------------
+# render forward / backward
+# ----------------------------------------------------------------------------
+def random_packed(seed, n_rays, max_count, gaps=False, long_rays=()):
+    g = scenes.rng(seed)
+    counts = g.integers(0, max_count + 1, n_rays).astype(np.int64)
+    for r, c in long_rays:
+        counts[r] = c
+    gap = g.integers(0, 5, n_rays) if gaps else np.zeros(n_rays, np.int64)
+    starts = np.concatenate([[0], np.cumsum(counts + gap)[:-1]]) + gap
+    S = int(starts[-1] + counts[-1]) if n_rays else 0
+    t0 = np.zeros(S, np.float32)
+    t1 = np.zeros(S, np.float32)
+    for r in range(n_rays):
+        c = counts[r]
+        a = g.uniform(0.5, 3.0)
+        dts = g.uniform(0.001, 0.02, c)
+        e = a + np.concatenate([[0], np.cumsum(dts)])
+        t0[starts[r]:starts[r] + c] = e[:-1]
+        t1[starts[r]:starts[r] + c] = e[1:]
+    sig = (g.exponential(1.0, S) * g.choice([0.5, 5, 50], S)).astype(np.float32)
+    rgb = g.random((S, 3)).astype(np.float32)
+    info = np.stack([starts, counts], 1).astype(np.int32)
+    return info, t0, t1, sig, rgb
+
+
+def check_fwd(txs, info, t0, t1, sig, rgb, bg=None, dense=None):
+    n = info.shape[0]
+    if dense is None:
+        out = txs.render_fwd(dev(info), dev(t0), dev(t1), dev(sig), dev(rgb),
+                             bg=None if bg is None else dev(bg), want_weights=True)
+    else:
+        out = txs.render_fwd(None, dev(t0), dev(t1), dev(sig), dev(rgb), n_rays=n,
+                             fixed_count=dense, bg=None if bg is None else dev(bg),
+                             want_weights=True)
+    ref = oracle.render_fwd(info, t0, t1, sig, rgb, bg=bg, want_weights=True)
+    assert_close(host(out[0]), ref["rgb"], name="rgb")
+    assert_close(host(out[1]), ref["opacity"], name="opacity")
+    assert_close(host(out[2]), ref["depth"], name="depth")
+    own = np.concatenate([np.arange(s, s + c) for s, c in info]) if len(info) else np.zeros(0, int)
+    assert_close(host(out[3])[own], ref["weights"][own], name="weights")
+
+
+def check_bwd(txs, info, t0, t1, sig, rgb, bg=None, hq=False, seed=0, dense=None):
+    n = info.shape[0]
+    g = scenes.rng(100 + seed)
+    gr = g.standard_normal((n, 3)).astype(np.float32)
+    gh = g.standard_normal(n).astype(np.float32) if hq else None
+    gq = g.standard_normal(n).astype(np.float32) if hq else None
+    kw = dict(bg=None if bg is None else dev(bg))
+    if dense is not None:
+        kw.update(n_rays=n, fixed_count=dense)
+    ds, dr = txs.render_bwd(None if dense is not None else dev(info), dev(t0), dev(t1), dev(sig),
+                            dev(rgb), dev(gr), None if gh is None else dev(gh),
+                            None if gq is None else dev(gq), **kw)
+    rds, rdr = oracle.render_bwd(info, t0, t1, sig, rgb, gr, gh, gq, bg=bg)
+    own = np.concatenate([np.arange(s, s + c) for s, c in info]) if len(info) else np.zeros(0, int)
+    seg = segment_ids(info)
+    bgc = np.zeros((n, 3)) if bg is None else bg.astype(np.float64)
+    mid = 0.5 * (t0.astype(np.float64) + t1)
+    if len(own):
+        v = ((rgb[own].astype(np.float64) - bgc[seg]) * gr[seg]).sum(1)
+        if hq:
+            v += gh[seg] + gq[seg] * mid[own]
+        cond = bwd_condition(np.stack([np.concatenate([[0], np.cumsum(info[:, 1])[:-1]]),
+                                       info[:, 1]], 1), t0[own], t1[own], sig[own], v)
+        assert_close(host(ds)[own], rds[own], floor_scale=cond, name="d_sigma")
+        assert_close(host(dr)[own], rdr[own], name="d_rgb")
+
+
+def test_render_tiny_field(gpu_lib, tiny):
+    ref = oracle_march(tiny)
+    sig, rgb = field_inputs(tiny, ref)
+    kept, _ = oracle.transmittance_prefix(ref["packed_info"], ref["t0"], ref["t1"], sig, 1e-4)
+    info, t0, t1, rid = oracle.gather_prefix(ref["packed_info"], kept, ref["t0"], ref["t1"],
+                                             ref["ray_id"])
+    sel = np.concatenate([np.arange(ref["packed_info"][r, 0], ref["packed_info"][r, 0] + kept[r])
+                          for r in range(tiny.n_rays)])
+    s2, c2 = sig[sel], rgb[sel]
+    check_fwd(gpu_lib, info, t0, t1, s2, c2)
+    check_bwd(gpu_lib, info, t0, t1, s2, c2)
+    check_bwd(gpu_lib, info, t0, t1, s2, c2, hq=True, seed=1)
+
+
+@pytest.mark.parametrize("case", ["short", "mixed", "long", "gaps", "ones"])
+def test_render_random_layouts(gpu_lib, case):
+    if case == "short":
+        args = random_packed(1, 3000, 12)
+    elif case == "mixed":
+        args = random_packed(2, 2000, 300)
+    elif case == "long":  # rays beyond one 512-sample window, incl. >64 windows
+        args = random_packed(3, 300, 40, long_rays=[(0, 513), (5, 1500), (64, 4096),
+                                                    (130, 40000), (299, 777)])
+    elif case == "gaps":
+        args = random_packed(4, 1000, 200, gaps=True, long_rays=[(10, 2000)])
+    else:
+        args = random_packed(5, 5000, 1)
+    info, t0, t1, sig, rgb = args
+    g = scenes.rng(9)
+    bg = g.random((info.shape[0], 3)).astype(np.float32)
+    check_fwd(gpu_lib, info, t0, t1, sig, rgb)
+    check_fwd(gpu_lib, info, t0, t1, sig, rgb, bg=bg)
+    check_bwd(gpu_lib, info, t0, t1, sig, rgb, bg=bg, hq=True)
+
+
+def test_render_dense_layout(gpu_lib):
+    n, F = 3000, 32
+    info = np.stack([np.arange(n) * F, np.full(n, F)], 1).astype(np.int32)
+    _, t0, t1, sig, rgb = random_packed(7, n, F, long_rays=[(r, F) for r in range(n)])
+    check_fwd(gpu_lib, info, t0, t1, sig, rgb, dense=F)
+    check_bwd(gpu_lib, info, t0, t1, sig, rgb, dense=F, hq=True)
+
+
+def test_render_extreme_densities(gpu_lib):
+    info, t0, t1, sig, rgb = random_packed(8, 500, 50)
+    g = scenes.rng(10)
+    sig = sig.copy()
+    sig[g.random(sig.size) < 0.2] = 0.0
+    sig[g.random(sig.size) < 0.05] = 1e6
+    check_fwd(gpu_lib, info, t0, t1, sig, rgb)
+    check_bwd(gpu_lib, info, t0, t1, sig, rgb, hq=True)
+
+
+def test_weights_bwd(gpu_lib):
+    info, t0, t1, sig, rgb = random_packed(11, 1500, 150, long_rays=[(3, 900)])
+    g = scenes.rng(12)
+    gw = g.standard_normal(t0.size).astype(np.float32)
+    ds = host(gpu_lib.weights_bwd(dev(info), dev(t0), dev(t1), dev(sig), dev(gw)))
+    ref = oracle.weights_bwd(info, t0, t1, sig, gw)
+    cond = bwd_condition(info, t0, t1, sig, gw.astype(np.float64))
+    assert_close(ds, ref, floor_scale=cond, name="weights_bwd")
+
+
+def test_render_autograd_and_determinism(gpu_lib, tiny):
+    info, t0, t1, sig, rgb = random_packed(13, 800, 100)
+    s = dev(sig).requires_grad_(True)
+    c = dev(rgb).requires_grad_(True)
+    p = gpu_lib.Packed(dev(info), dev(t0), dev(t1), None)
+    out_rgb, out_op, out_d = gpu_lib.rendering(p, s, c)
+    g = scenes.rng(14)
+    gr = dev(g.standard_normal((800, 3)).astype(np.float32))
+    go = dev(g.standard_normal(800).astype(np.float32))
+    ((out_rgb * gr).sum() + (out_op * go).sum()).backward()
+    rds, rdr = oracle.render_bwd(info, t0, t1, sig, rgb, host(gr), host(go), None)
+    v = None
+    seg = segment_ids(info)
+    v = (rgb.astype(np.float64) * host(gr)[seg]).sum(1) + host(go)[seg]
+    cond = bwd_condition(info, t0, t1, sig, v)
+    assert_close(host(s.grad), rds, floor_scale=cond, name="autograd d_sigma")
+    assert_close(host(c.grad), rdr, name="autograd d_rgb")
+    # bitwise determinism of two identical launches
+    a = gpu_lib.render_bwd(dev(info), dev(t0), dev(t1), dev(sig), dev(rgb), gr, go)
+    b = gpu_lib.render_bwd(dev(info), dev(t0), dev(t1), dev(sig), dev(rgb), gr, go)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_render_empty(gpu_lib):
+    info = np.zeros((5, 2), np.int32)
+    z = np.zeros(0, np.float32)
+    out = gpu_lib.render_fwd(dev(info), dev(z), dev(z), dev(z), dev(np.zeros((0, 3), np.float32)))
+    assert host(out[1]).tolist() == [0.0] * 5
+    ds, dr = gpu_lib.render_bwd(dev(info), dev(z), dev(z), dev(z),
+                                dev(np.zeros((0, 3), np.float32)),
+                                dev(np.ones((5, 3), np.float32)))
+    assert ds.numel() == 0
+
+
+# ----------------------------------------------------------------------------
+# resample / uniform bins / field
+# ----------------------------------------------------------------------------
+def resample_tol(edges, vals, mode, out_ref, bins_ref):
+    """Inverse-CDF conditioning: a CDF error eps moves t by eps/(F_{i+1}-F_i) of the bin."""
+    e = edges.astype(np.float64)
+    v = vals.astype(np.float64)
+    if mode == 0:
+        F = -np.expm1(-np.cumsum(v * np.diff(e, axis=1), axis=1))
+    else:
+        F = np.cumsum(v, axis=1)
+    F = np.concatenate([np.zeros((F.shape[0], 1)), F], 1)
+    Fn = F[:, -1:]
+    uni = Fn[:, 0] <= 1e-12
+    F[uni] = np.linspace(0, 1, F.shape[1])
+    Fn = F[:, -1:]
+    i = np.minimum(bins_ref, e.shape[1] - 2)
+    dF = np.take_along_axis(F, i + 1, 1) - np.take_along_axis(F, i, 1)
+    width = np.take_along_axis(e, i + 1, 1) - np.take_along_axis(e, i, 1)
+    span = e[:, -1:] - e[:, :1]
+    return (1e-5 * np.abs(out_ref) + 1e-6 * span
+            + width * np.minimum(1.0, 4e-6 * Fn / np.maximum(dF, 1e-300)))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("use_u", [False, True])
+def test_resample(gpu_lib, mode, use_u):
+    g = scenes.rng(20 + mode + 2 * use_u)
+    n, nb, n_out = 4000, 128, 32
+    a = g.uniform(1.0, 2.0, (n, 1))
+    edges = (a + np.concatenate([np.zeros((n, 1)), np.cumsum(g.uniform(0.005, 0.03, (n, nb)), 1)],
+                                1)).astype(np.float32)
+    vals = (g.exponential(1.0, (n, nb)) * (g.random((n, nb)) < 0.3) *
+            g.choice([1.0, 30.0], (n, 1))).astype(np.float32)
+    vals[:10] = 0.0  # zero-mass rays fall back to the uniform estimator
+    u = np.sort(g.random((n, n_out + 1)), 1).astype(np.float32) if use_u else None
+    out = host(gpu_lib.resample(dev(edges), dev(vals), n_out, mode, None if u is None else dev(u)))
+    ref, bins, band = oracle.resample(edges, vals, n_out, mode, u)
+    tol = resample_tol(edges, vals, mode, ref, bins)
+    err = np.abs(out - ref)
+    bad = (err > tol) & ~band[:, None]
+    assert not bad.any(), (bad.sum(), np.argwhere(bad)[:5])
+
+
+def test_uniform_bins(gpu_lib, tiny):
+    o, d = tiny.rays_o, tiny.rays_d
+    g = grid_spec(gpu_lib, tiny.bits, 64)
+    e = host(gpu_lib.uniform_bins(g, dev(o), dev(d), 128))
+    tn, tf = oracle.clip(o, d, np.full(3, -1.5, np.float32), np.full(3, 1.5, np.float32))
+    hit = tn < tf
+    k = np.arange(129) / 128.0
+    ref = tn[:, None].astype(np.float64) + (tf - tn)[:, None].astype(np.float64) * k
+    assert_close(e[hit], ref[hit], rel=1e-6, name="uniform edges")
+    assert np.all(e[~hit] == 0.0)
+
+
+def test_blob_field(gpu_lib):
+    w = scenes.unbounded(64, 32, n_cams=2, res=32)
+    ref = oracle_march(w)
+    params = w.fld.packed_params().astype(np.float32)
+    s, c = gpu_lib.blob_field(dev(params), w.fld.n_blobs, dev(w.rays_o), dev(w.rays_d),
+                              dev(ref["t0"]), dev(ref["t1"]), dev(ref["ray_id"]))
+    rs, rc = oracle.field_at_samples(w.rays_o, w.rays_d, ref["t0"], ref["t1"], ref["ray_id"],
+                                     w.fld.packed_params())
+    # support kernel: float32 positions and a float32 parameter copy bound its accuracy
+    s = host(s)
+    assert np.all(np.abs(s - rs) <= 2e-4 * rs + 1e-6 * w.fld.peak)
+    assert np.all(np.abs(host(c) - rc) <= 1e-4)
