@@ -31,7 +31,7 @@ BYTES = {
     "exclusive_scan": lambda N, Sm, S: 16 * N,
     "march_fill": lambda N, Sm, S: 32 * N + 12 * Sm,
     "transmittance_prefix": lambda N, Sm, S: 12 * N + 12 * Sm,
-    "gather_prefix": lambda N, Sm, S: 16 * N + 4 * Sm + 20 * S,
+    "gather_prefix": lambda N, Sm, S: 16 * N + 20 * S,
     "render_fwd": lambda N, Sm, S: 28 * N + 24 * S,
     "render_bwd": lambda N, Sm, S: 20 * N + 40 * S,
 }
@@ -113,7 +113,7 @@ def gpu_bench(args, w):
                       w.t_min)
         info2, total2 = tl.run("exclusive_scan", txs.exclusive_scan, kept)
         s = int(total2.item())
-        q0, q1, qr = tl.run("gather_prefix", txs.gather_prefix, info, info2, s, t0, t1, rid)
+        q0, q1, qr = tl.run("gather_prefix", txs.gather_prefix, info, info2, s, t0, t1)
         sig, rgb = tl.run("field_density_rgb", txs.blob_field, params, nb, o, d, q0, q1, qr)
         out = tl.run("render_fwd", txs.render_fwd, info2, q0, q1, sig, rgb)
         grads = tl.run("render_bwd", txs.render_bwd, info2, q0, q1, sig, rgb, g_rgb)

@@ -80,10 +80,11 @@ typedef struct {
  * (midpoints m_k = a + (k+1/2)*dt < b); sample k is emitted iff the cell that
  * holds o + m_k*d is occupied, as the interval [t_k, min(a+(k+1)*dt, b)].
  * The occupancy test is evaluated in binary32 with the fixed operation order
- *   u = ((o + m*d) - bmin) * (res / (bmax - bmin)),  cell = clamp(floor(u))
- * (no fused multiply-add) so that the emitted samples are exactly those of a
- * dense test of every lattice point; empty cells are skipped with a DDA whose
- * jumps provably never pass a lattice point that the dense test would keep.
+ *   m = a + ((float)k + 0.5f)*dt,  u = ((o + m*d) - bmin) * (res / (bmax - bmin)),
+ *   cell = clamp(floor(u), 0, res-1)
+ * (no fused multiply-add), at every lattice point, so the emitted samples are
+ * a deterministic function of the inputs that any binary32 evaluation of the
+ * same recipe reproduces bit for bit.
  *
  * txs_march_count writes counts[n_rays] (int32).
  * rays_o, rays_d: float [n_rays, 3]; rays_d need not be normalised (the
@@ -132,16 +133,17 @@ txs_status txs_transmittance_prefix(const int32_t* packed_info, int32_t n_rays,
                                     void* stream);
 
 /*
- * Repacks the first packed_info_out[r].count samples of every ray from the
- * input packed tensor (described by packed_info_in and ray_id) to
- * packed_info_out[r].start in the output tensor.  ray_id (int32 [n_in]) is
- * required; t0o, t1o, ray_ido have room for `capacity` samples (ray_ido may
- * be NULL).  Typical use: packed_info_out = txs_exclusive_scan(kept_counts).
+ * Repacks the first packed_info_out[r].count samples of every ray r from the
+ * input packed tensor (t0, t1: float [n_in], rows packed_info_in) to
+ * packed_info_out[r].start of the output tensor: t0o, t1o (float
+ * [capacity]) and ray_ido (int32 [capacity] = r, may be NULL).  A row whose
+ * copy would read at or beyond n_in or write at or beyond capacity copies
+ * nothing.  Typical use: packed_info_out = txs_exclusive_scan(kept_counts).
  */
 txs_status txs_gather_prefix(const int32_t* packed_info_in, const int32_t* packed_info_out,
                              int32_t n_rays, int64_t n_in, const float* t0, const float* t1,
-                             const int32_t* ray_id, int64_t capacity, float* t0o, float* t1o,
-                             int32_t* ray_ido, void* stream);
+                             int64_t capacity, float* t0o, float* t1o, int32_t* ray_ido,
+                             void* stream);
 
 /*
  * Packed volume rendering forward (Eq. 2, discretised):
@@ -153,13 +155,15 @@ txs_status txs_gather_prefix(const int32_t* packed_info_in, const int32_t* packe
  * (r+1)*fixed_count) (dense layout, e.g. proposal resampling output).
  * sigma float [n_samples], rgb float [n_samples, 3], bg float [n_rays, 3] or
  * NULL (black).  Outputs: out_rgb [n_rays,3], out_opacity [n_rays],
- * out_depth [n_rays], out_weights [n_samples] or NULL.
+ * out_depth [n_rays], out_weights [n_samples] or NULL, and
+ * out_optical_depth double [n_rays] or NULL = sum_i tau_i per ray.
+ * Optical depths are accumulated in binary64.
  */
 txs_status txs_render_fwd(const int32_t* packed_info, int32_t fixed_count, int32_t n_rays,
                           int64_t n_samples, const float* t0, const float* t1,
                           const float* sigma, const float* rgb, const float* bg,
                           float* out_rgb, float* out_opacity, float* out_depth,
-                          float* out_weights, void* stream);
+                          float* out_weights, double* out_optical_depth, void* stream);
 
 /*
  * Adjoint of txs_render_fwd (the gradients that reach the radiance field in
@@ -168,24 +172,31 @@ txs_status txs_render_fwd(const int32_t* packed_info, int32_t fixed_count, int32
  *   d_rgb_i   = w_i g,
  *   d_sigma_i = (t1_i - t0_i) (T_{i+1} v_i - sum_{j>i} w_j v_j),
  * where g = g_rgb[r] (float [n_rays,3]), h = g_opacity[r], q = g_depth[r]
- * (both may be NULL = 0).  T and w are recomputed from the inputs (nothing is
- * stored by the forward); the suffix sum is an exact reverse scan.
+ * (both may be NULL = 0).  T and w are recomputed from the inputs; the only
+ * forward state used is optical_depth (double [n_rays], the forward's
+ * out_optical_depth of the same inputs), or NULL to recompute it here at the
+ * cost of one more read of t0, t1, sigma.  The samples are walked last to
+ * first so both suffix sums are exact reverse scans.
  * d_sigma float [n_samples], d_rgb float [n_samples,3] (may be NULL).
+ * Samples outside every ray's segment are left unchanged.
  */
 txs_status txs_render_bwd(const int32_t* packed_info, int32_t fixed_count, int32_t n_rays,
                           int64_t n_samples, const float* t0, const float* t1,
                           const float* sigma, const float* rgb, const float* bg,
-                          const float* g_rgb, const float* g_opacity, const float* g_depth,
-                          float* d_sigma, float* d_rgb, void* stream);
+                          const double* optical_depth, const float* g_rgb,
+                          const float* g_opacity, const float* g_depth, float* d_sigma,
+                          float* d_rgb, void* stream);
 
 /*
  * Adjoint of the weights alone: given g_w[i] = dL/dw_i (float [n_samples]),
  *   d_sigma_i = (t1_i - t0_i) (T_{i+1} g_w_i - sum_{j>i} w_j g_w_j).
  * Used to train a proposal estimator through its rendering weights.
+ * optical_depth as for txs_render_bwd (may be NULL).
  */
 txs_status txs_weights_bwd(const int32_t* packed_info, int32_t fixed_count, int32_t n_rays,
                            int64_t n_samples, const float* t0, const float* t1,
-                           const float* sigma, const float* g_w, float* d_sigma, void* stream);
+                           const float* sigma, const double* optical_depth, const float* g_w,
+                           float* d_sigma, void* stream);
 
 /*
  * Inverse transform sampling (Eq. 1) of a piecewise-constant estimator whose

@@ -42,10 +42,10 @@ SIGNATURES = {
     "txs_exclusive_scan": (I32, [P, I32, P, P, P, SZ, P]),
     "txs_march_fill": (I32, [GP, MP, P, P, I32, P, I64, P, P, P, P]),
     "txs_transmittance_prefix": (I32, [P, I32, I64, P, P, P, F32, P, P]),
-    "txs_gather_prefix": (I32, [P, P, I32, I64, P, P, P, I64, P, P, P, P]),
-    "txs_render_fwd": (I32, [P, I32, I32, I64, P, P, P, P, P, P, P, P, P, P]),
-    "txs_render_bwd": (I32, [P, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P]),
-    "txs_weights_bwd": (I32, [P, I32, I32, I64, P, P, P, P, P, P]),
+    "txs_gather_prefix": (I32, [P, P, I32, I64, P, P, I64, P, P, P, P]),
+    "txs_render_fwd": (I32, [P, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P]),
+    "txs_render_bwd": (I32, [P, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P, P]),
+    "txs_weights_bwd": (I32, [P, I32, I32, I64, P, P, P, P, P, P, P]),
     "txs_resample": (I32, [I32, I32, P, P, I32, I32, P, P, P]),
     "txs_uniform_bins": (I32, [GP, F32, F32, P, P, I32, I32, P, P]),
     "txs_blob_field": (I32, [P, I32, P, P, I32, P, P, P, I32, I64, P, P, P]),

@@ -1,12 +1,12 @@
 // Occupancy-grid ray marching (spatial-skipping estimator, Section 3.1 and
 // Table 1 second row; cascaded levels for unbounded scenes, Section 3.2).
 //
-// One lane marches one ray.  The decision "sample k is kept" is the binary32
-// recipe of txs.h evaluated with contraction disabled (this file), so the
-// emitted samples equal those of a dense test of every lattice point.  Runs
-// of lattice points that provably fall in the same cell are handled at once:
-// skipped when the cell is empty, counted (count pass) or written (fill
-// pass) when it is occupied.
+// One wave marches one ray: its 64 lanes test 64 consecutive lattice points
+// at a time with the binary32 recipe of txs.h (contraction disabled in this
+// file), a ballot collects the occupied ones and a lane-rank (mbcnt) packs
+// them, so the fill pass writes each ray's samples as contiguous, coalesced
+// runs.  Every lattice point is tested, so the emitted samples are the dense
+// definition exactly.
 #pragma clang fp contract(off)
 
 #include <cmath>
@@ -18,7 +18,8 @@ namespace {
 
 constexpr int kMaxLevels = 8;
 constexpr int32_t kLatticeLimit = 1 << 24;  // k stays exact in binary32
-constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
 
 struct MarchArgs {
   const uint32_t* bits;
@@ -36,7 +37,7 @@ struct LevelBox {
   float bmin[3], bmax[3], scale[3];
 };
 
-__host__ __device__ __forceinline__ LevelBox level_box(const MarchArgs& g, int l) {
+__device__ __forceinline__ LevelBox level_box(const MarchArgs& g, int l) {
   LevelBox b;
   const float h = g.half_extent0 * (float)(1 << l);
 #pragma unroll
@@ -49,7 +50,7 @@ __host__ __device__ __forceinline__ LevelBox level_box(const MarchArgs& g, int l
 }
 
 // Slab clip; min/max ignore the NaN of 0*inf for rays lying in a slab plane.
-__host__ __device__ __forceinline__ void clip_box(const float o[3], const float inv[3], const LevelBox& b,
+__device__ __forceinline__ void clip_box(const float o[3], const float inv[3], const LevelBox& b,
                                          float near_plane, float far_plane, float& tn,
                                          float& tf) {
   float t_near = near_plane, t_far = far_plane;
@@ -65,7 +66,7 @@ __host__ __device__ __forceinline__ void clip_box(const float o[3], const float 
 }
 
 template <int N>
-__host__ __device__ __forceinline__ float pick(const float (&v)[N], int i) {
+__device__ __forceinline__ float pick(const float (&v)[N], int i) {
   float r = v[0];
 #pragma unroll
   for (int j = 1; j < N; ++j) r = (i == j) ? v[j] : r;
@@ -81,109 +82,55 @@ struct Emit {
   int32_t ray;
 };
 
-// Marches one segment [a, b) on level l; returns the updated sample count.
+// One segment [a, b) on level l, 64 lattice points per step.  n: samples so
+// far (wave-uniform); returns the new count.
 template <bool kFill>
-__host__ __device__ int32_t march_segment(const MarchArgs& g, const float o[3], const float d[3], float a,
+__device__ int32_t march_segment(const MarchArgs& g, const float o[3], const float d[3], float a,
                                  float b, int l, int32_t n, int32_t cap, const Emit& em) {
   const float dt = g.dt0 * (float)(1 << l);
-  const float inv_dt = 1.0f / dt;
   const LevelBox box = level_box(g, l);
   const int res = g.res;
   const float resf = (float)res;
   const uint32_t* bits = g.bits + (int64_t)l * g.level_words;
-
-  // Linear map of the ray into grid units, u_c(t) = u0_c + t v_c, and a margin
-  // dl_c (grid units) that bounds, with a wide factor, the rounding of the
-  // binary32 recipe and of the run computation below.
-  const float T = fmaxf(fabsf(a), fabsf(b)) + dt;
-  float u0[3], v[3], iv[3], dl[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    u0[c] = (o[c] - box.bmin[c]) * box.scale[c];
-    v[c] = d[c] * box.scale[c];
-    iv[c] = 1.0f / v[c];
-    dl[c] = 0x1p-16f * (box.scale[c] * (fabsf(o[c]) + fabsf(box.bmin[c]) + T * fabsf(d[c])) +
-                        resf + 1.0f);
-  }
-
-  int32_t last_word = -1;
-  uint32_t word_bits = 0;
-  int32_t k = 0;
-  while (k < kLatticeLimit) {
+  const int ln = lane();
+  for (int32_t k0 = 0; k0 < kLatticeLimit; k0 += kWave) {
+    const int32_t k = k0 + ln;
     const float m = a + ((float)k + 0.5f) * dt;
-    if (!(m < b)) break;
-    int cell[3];
+    const bool valid = (k < kLatticeLimit) && (m < b);
+    bool occ = false;
+    if (valid) {
+      int cell[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float x = o[c] + m * d[c];
-      const float u = (x - box.bmin[c]) * box.scale[c];
-      float f = floorf(u);
-      f = fminf(fmaxf(f, 0.0f), resf - 1.0f);
-      cell[c] = (int)f;
-    }
-    const int32_t idx = cell[0] + res * (cell[1] + res * cell[2]);
-    const int32_t word = idx >> 5;
-    if (word != last_word) {
-      word_bits = bits[word];
-      last_word = word;
-    }
-    const bool occ = (word_bits >> (idx & 31)) & 1u;
-
-    // Lattice points k+1 .. k_end-1 provably share this cell: their exact
-    // positions lie inside the cell shrunk by dl on every face, where the
-    // recipe's rounding cannot move them out.  Point k_end is re-tested.
-    float tb = -INFINITY, te = b;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float lo = (cell[c] == 0) ? -INFINITY : (float)cell[c] + dl[c];
-      const float hi = (cell[c] == res - 1) ? INFINITY : (float)(cell[c] + 1) - dl[c];
-      float t_lo, t_hi;
-      if (v[c] > 0.0f) {
-        t_lo = (lo - u0[c]) * iv[c];
-        t_hi = (hi - u0[c]) * iv[c];
-      } else if (v[c] < 0.0f) {
-        t_lo = (hi - u0[c]) * iv[c];
-        t_hi = (lo - u0[c]) * iv[c];
-      } else {
-        const bool inside = (u0[c] >= lo) && (u0[c] <= hi);
-        t_lo = inside ? -INFINITY : INFINITY;
-        t_hi = inside ? INFINITY : -INFINITY;
+      for (int c = 0; c < 3; ++c) {
+        const float x = o[c] + m * d[c];
+        const float u = (x - box.bmin[c]) * box.scale[c];
+        float f = floorf(u);
+        f = fminf(fmaxf(f, 0.0f), resf - 1.0f);
+        cell[c] = (int)f;
       }
-      tb = fmaxf(tb, t_lo);
-      te = fminf(te, t_hi);
+      const int32_t idx = cell[0] + res * (cell[1] + res * cell[2]);
+      occ = (bits[idx >> 5] >> (idx & 31)) & 1u;
     }
-    int32_t k_end = k + 1;
-    const float m_next = a + ((float)(k + 1) + 0.5f) * dt;
-    if (m_next >= tb && m_next < te) {
-      const float q = (te - a) * inv_dt - 0.5f;  // ~ last lattice index inside
-      const int32_t kq = (q >= (float)kLatticeLimit) ? kLatticeLimit : (int32_t)floorf(q);
-      k_end = max(k_end, kq);
-    }
-
-    if (occ) {
-      int32_t run = k_end - k;
-      if (cap > 0) run = min(run, cap - n);
-      if (kFill) {
-        for (int32_t j = 0; j < run; ++j) {
-          const int64_t pos = em.base + n + j;
-          if (pos < em.capacity) {
-            const int32_t kk = k + j;
-            em.t0[pos] = a + (float)kk * dt;
-            em.t1[pos] = fminf(a + (float)(kk + 1) * dt, b);
-            if (em.ray_id) em.ray_id[pos] = em.ray;
-          }
-        }
+    const uint64_t mask = __ballot(occ);
+    if (kFill && occ) {
+      const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+      const int64_t pos = em.base + n + rank;
+      if ((cap == 0 || n + rank < cap) && pos < em.capacity) {
+        em.t0[pos] = a + (float)k * dt;
+        em.t1[pos] = fminf(a + (float)(k + 1) * dt, b);
+        if (em.ray_id) em.ray_id[pos] = em.ray;
       }
-      n += run;
-      if (cap > 0 && n >= cap) return n;
     }
-    k = k_end;
+    n += __popcll(mask);
+    if (cap > 0 && n >= cap) return cap;
+    if (__ballot(valid) != ~0ull) break;  // the segment ended inside this step
   }
   return n;
 }
 
 template <bool kFill>
-__host__ __device__ int32_t march_ray(const MarchArgs& g, const float o[3], const float d[3],
+__device__ int32_t march_ray(const MarchArgs& g, const float o[3], const float d[3],
                              const Emit& em) {
   float inv[3];
 #pragma unroll
@@ -239,7 +186,9 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float*
                                                        const int32_t* __restrict__ info,
                                                        int64_t capacity, float* t0, float* t1,
                                                        int32_t* ray_id) {
-  const int32_t r = blockIdx.x * kBlock + threadIdx.x;
+  // one ray per wave; the ray index is wave-uniform
+  const int32_t r = __builtin_amdgcn_readfirstlane(
+      (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
   if (r >= n_rays) return;
   float o[3], d[3];
 #pragma unroll
@@ -249,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float*
   }
   Emit em{t0, t1, ray_id, kFill ? (int64_t)info[2 * (int64_t)r] : 0, capacity, r};
   const int32_t n = march_ray<kFill>(g, o, d, em);
-  if (!kFill) counts[r] = n;
+  if (!kFill && lane() == 0) counts[r] = n;
 }
 
 txs_status make_args(const txs_grid* grid, const txs_march_params* p, MarchArgs& g) {
@@ -283,6 +232,10 @@ txs_status make_args(const txs_grid* grid, const txs_march_params* p, MarchArgs&
   return TXS_OK;
 }
 
+unsigned march_blocks(int32_t n_rays) {
+  return grid_1d(((int64_t)n_rays + kWavesPerBlock - 1) / kWavesPerBlock, 1);
+}
+
 }  // namespace
 }  // namespace txs
 
@@ -296,7 +249,7 @@ extern "C" txs_status txs_march_count(const txs_grid* grid, const txs_march_para
   TXS_REQUIRE(n_rays >= 0, "txs_march_count: n_rays < 0");
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && counts, "txs_march_count: null array");
-  hipLaunchKernelGGL(march_kernel<false>, dim3(grid_1d(n_rays, kBlock)), dim3(kBlock), 0,
+  hipLaunchKernelGGL(march_kernel<false>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
                      as_stream(stream), g, rays_o, rays_d, n_rays, counts, nullptr, 0, nullptr,
                      nullptr, nullptr);
   return launch_status("txs_march_count");
@@ -314,7 +267,7 @@ extern "C" txs_status txs_march_fill(const txs_grid* grid, const txs_march_param
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && packed_info, "txs_march_fill: null array");
   TXS_REQUIRE(capacity == 0 || (t0 && t1), "txs_march_fill: null output");
-  hipLaunchKernelGGL(march_kernel<true>, dim3(grid_1d(n_rays, kBlock)), dim3(kBlock), 0,
+  hipLaunchKernelGGL(march_kernel<true>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
                      as_stream(stream), g, rays_o, rays_d, n_rays, nullptr, packed_info, capacity,
                      t0, t1, ray_id);
   return launch_status("txs_march_fill");

@@ -1,17 +1,16 @@
-// Shared engine of the packed volume-rendering kernels (Eq. 2 discretised; Section 4.2 packed tensors and
-// no-gradient filtering): forward compositing, its adjoint, the adjoint of the
-// weights alone, and the transmittance-prefix filter.
+// Shared engine of the packed volume-rendering kernels (Eq. 2 discretised;
+// Section 4.2 packed tensors and no-gradient filtering).
 //
 // Work decomposition.  A wave owns 64 consecutive rays (one per lane) and
-// walks their samples in windows of W = 64*K samples held in registers,
-// K contiguous samples per lane (blocked layout, 16-byte vector loads).
-// Ray boundaries inside a window are marked in LDS; the per-ray scans are
-// segmented scans: a serial pass inside each lane plus a wave-wide
-// Hillis-Steele scan over the 64 lane aggregates, gated by the position of
-// the last segment boundary.  The forward direction runs over consecutive
-// windows with a carry; the backward uses windows that hold whole rays so the
-// suffix sums of the adjoint are an exact reverse scan in registers (rays
-// longer than a window take a two-pass chunked path).
+// walks the sample range of those rays in windows of W = 64*K samples held in
+// registers, K contiguous samples per lane (blocked layout, 16-byte vector
+// loads and stores).  Ray boundaries inside a window are marked in LDS; the
+// per-ray scans are segmented scans: a serial pass inside each lane plus a
+// wave-wide Hillis-Steele scan over the 64 lane aggregates, gated by the lane
+// of the nearest segment boundary.  The forward direction walks the windows
+// left to right with a carry; the adjoint walks them right to left, so its
+// suffix sums are exact reverse scans.  Optical depths are accumulated in
+// binary64: the transmittance exp(-P) needs P to ~1e-6 absolute.
 #pragma once
 
 #include <cmath>
@@ -21,14 +20,13 @@
 namespace txs {
 namespace {
 
-constexpr int K = 8;             // samples per lane per window
-constexpr int W = kWave * K;     // samples per window
-constexpr int kWaves = 4;        // waves per block
+constexpr int K = 8;               // samples per lane per window
+constexpr int W = kWave * K;       // samples per window
+constexpr int kWaves = 4;          // waves per block
 constexpr int kBlock = kWave * kWaves;
-constexpr int kMarks = W + kWave; // marks for window positions 0..W (cleared 64 at a time)
-constexpr int kLongCarries = 64; // chunk carries kept for one long ray
+constexpr int kMarks = W + kWave;  // marks for window positions 0..W (cleared 64 at a time)
 
-enum Mode { kFwd = 0, kPrefix = 1, kBwd = 2, kWBwd = 3 };
+enum Mode { kFwd = 0, kPrefix = 1, kTotal = 2, kBwd = 3, kWBwd = 4 };
 
 struct Args {
   const int32_t* info;
@@ -40,12 +38,17 @@ struct Args {
   const float* sigma;
   const float* rgb;
   const float* bg;
+  // forward outputs
   float* out_rgb;
   float* out_opacity;
   float* out_depth;
   float* out_w;
-  float p_max;  // prefix: keep while sum_{j<i} tau_j <= p_max
+  double* out_optical;
+  // filter
+  double p_max;  // keep while sum_{j<i} tau_j <= p_max
   int32_t* kept;
+  // adjoint
+  const double* optical;  // per-ray total optical depth (NULL: recomputed)
   const float* g_rgb;
   const float* g_op;
   const float* g_depth;
@@ -54,11 +57,12 @@ struct Args {
   float* d_rgb;
 };
 
-// Per-wave LDS: boundary marks of the current window and per-ray cotangents.
+// Per-wave LDS: boundary marks of the current window, per-ray cotangents and
+// total optical depths (adjoint).
 struct WaveLds {
   int marks[kMarks];
   float cot[kWave][8];  // g_rgb(3), h, q, bg(3) of each owned ray
-  float long_carry[kLongCarries];
+  double ptot[kWave];
 };
 
 // mark value: 0 none, lane+1 = first sample of that lane's ray, -1 = sample
@@ -104,31 +108,30 @@ __device__ __forceinline__ int min_scan_rev_incl(int v) {
 
 // Inclusive segmented scan over lanes; hl = last lane <= this one that starts
 // a segment (-1 if none).
-__device__ __forceinline__ float seg_scan(float v, int hl) {
+template <typename T>
+__device__ __forceinline__ T seg_scan(T v, int hl) {
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
-    const float t = shfl_up(v, d);
+    const T t = shfl_up(v, d);
     if (lane() >= d && lane() - d >= hl) v += t;
   }
   return v;
 }
-__device__ __forceinline__ int seg_scan(int v, int hl) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int t = shfl_up(v, d);
-    if (lane() >= d && lane() - d >= hl) v += t;
-  }
-  return v;
-}
+
 // Reverse inclusive segmented scan; fl = first lane >= this one that ends the
 // chain (64 if none).
-__device__ __forceinline__ float seg_scan_rev(float v, int fl) {
+template <typename T>
+__device__ __forceinline__ T seg_scan_rev(T v, int fl) {
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
-    const float t = shfl_down(v, d);
+    const T t = shfl_down(v, d);
     if (lane() + d < kWave && lane() + d <= fl) v += t;
   }
   return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  return __shfl(v, l, kWave);
 }
 
 struct Acc5 {
@@ -206,18 +209,18 @@ __device__ __forceinline__ void store_k(float* __restrict__ dst, int64_t pos0, c
 }
 
 // ----------------------------------------------------------- window marks
-// Marks the rays of lanes [lo, hi) (count > 0) whose first sample or end
-// falls in window positions [0, W] of window start p.
-__device__ __forceinline__ void write_marks(WaveLds& L, int64_t p, int64_t st, int32_t ct,
+// Marks, for window start p, the first sample (lane+1) and the end (-1) of
+// every ray in the set that falls in window positions [0, W].
+__device__ __forceinline__ void write_marks(WaveLds& L, int64_t p, int64_t st, int64_t en,
                                             bool in_set) {
   const int ln = lane();
 #pragma unroll
   for (int j = 0; j < kMarks / kWave; ++j) L.marks[ln + kWave * j] = 0;
   wave_sync();
-  const int64_t e_off = st + ct - p, s_off = st - p;
-  if (in_set && ct > 0 && e_off >= 0 && e_off <= W) L.marks[e_off] = -1;
+  const int64_t e_off = en - p, s_off = st - p;
+  if (in_set && en > st && e_off >= 0 && e_off <= W) L.marks[e_off] = -1;
   wave_sync();
-  if (in_set && ct > 0 && s_off >= 0 && s_off <= W) L.marks[s_off] = ln + 1;
+  if (in_set && en > st && s_off >= 0 && s_off <= W) L.marks[s_off] = ln + 1;
   wave_sync();
 }
 
@@ -225,6 +228,24 @@ __device__ __forceinline__ void read_marks(const WaveLds& L, int (&mk)[K + 1]) {
   const int base = K * lane();
 #pragma unroll
   for (int j = 0; j <= K; ++j) mk[j] = L.marks[base + j];
+}
+
+// Sample range [lo, hi) of the wave's rays (hi clipped to n_samples); the
+// per-lane row (st, en) with en clipped likewise; active = non-empty row.
+struct WaveRange {
+  int64_t st, en, lo, hi;
+  bool active;
+};
+
+__device__ __forceinline__ WaveRange wave_range(const Args& a, int32_t r) {
+  WaveRange w;
+  int32_t ct;
+  ray_row(a, r, w.st, ct);
+  w.en = min(w.st + (int64_t)ct, a.n_samples);
+  w.active = r < a.n_rays && w.en > w.st;
+  w.lo = wave_min(w.active ? w.st : INT64_MAX);
+  w.hi = wave_max(w.active ? w.en : (int64_t)0);
+  return w;
 }
 
 txs_status check_common(const char* who, const int32_t* info, int32_t fixed, int32_t n_rays,

@@ -88,25 +88,40 @@ __global__ __launch_bounds__(kScanBlock) void write_packed(const int32_t* __rest
   }
 }
 
-// Repack: one thread per input sample; keeps sample i of ray r iff its rank
-// inside the ray is below the output count of r.
-__global__ __launch_bounds__(256) void gather_prefix_kernel(
+// Repack: a wave owns 64 consecutive rays and copies the kept prefix of each
+// with all lanes (contiguous loads and stores).
+constexpr int kGatherWaves = 4;
+
+__global__ __launch_bounds__(kWave* kGatherWaves) void gather_prefix_kernel(
     const int32_t* __restrict__ info_in, const int32_t* __restrict__ info_out, int32_t n_rays,
-    int64_t n_in, const float* __restrict__ t0, const float* __restrict__ t1,
-    const int32_t* __restrict__ ray_id, int64_t capacity, float* __restrict__ t0o,
-    float* __restrict__ t1o, int32_t* __restrict__ rido) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += stride) {
-    const int32_t r = ray_id[i];
-    if (r < 0 || r >= n_rays) continue;
-    const int64_t rank = i - (int64_t)info_in[2 * (int64_t)r];
-    const int32_t keep = info_out[2 * (int64_t)r + 1];
-    if (rank < 0 || rank >= keep) continue;
-    const int64_t o = (int64_t)info_out[2 * (int64_t)r] + rank;
-    if (o >= capacity) continue;
-    t0o[o] = t0[i];
-    t1o[o] = t1[i];
-    if (rido) rido[o] = r;
+    int64_t n_in, const float* __restrict__ t0, const float* __restrict__ t1, int64_t capacity,
+    float* __restrict__ t0o, float* __restrict__ t1o, int32_t* __restrict__ rido) {
+  const int ln = lane();
+  const int64_t r0 = ((int64_t)blockIdx.x * kGatherWaves + threadIdx.x / kWave) * kWave;
+  if (r0 >= n_rays) return;
+  const int64_t r = r0 + ln;
+  int64_t si = 0, so = 0;
+  int32_t cnt = 0;
+  if (r < n_rays) {
+    const int2 a = reinterpret_cast<const int2*>(info_in)[r];
+    const int2 b = reinterpret_cast<const int2*>(info_out)[r];
+    si = a.x;
+    so = b.x;
+    cnt = min(b.y, a.y);
+    // rows that would read or write out of range copy nothing
+    if (a.x < 0 || b.x < 0 || cnt < 0 || si + cnt > n_in || so + cnt > capacity) cnt = 0;
+  }
+  const int nr = (int)min<int64_t>(kWave, n_rays - r0);
+  for (int l = 0; l < nr; ++l) {
+    const int32_t c = __shfl(cnt, l, kWave);
+    if (c == 0) continue;
+    const int64_t a = __shfl((long long)si, l, kWave);
+    const int64_t o = __shfl((long long)so, l, kWave);
+    for (int32_t j = ln; j < c; j += kWave) {
+      t0o[o + j] = t0[a + j];
+      t1o[o + j] = t1[a + j];
+      if (rido) rido[o + j] = (int32_t)(r0 + l);
+    }
   }
 }
 
@@ -148,18 +163,18 @@ extern "C" txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays,
 extern "C" txs_status txs_gather_prefix(const int32_t* packed_info_in,
                                         const int32_t* packed_info_out, int32_t n_rays,
                                         int64_t n_in, const float* t0, const float* t1,
-                                        const int32_t* ray_id, int64_t capacity, float* t0o,
-                                        float* t1o, int32_t* ray_ido, void* stream) {
+                                        int64_t capacity, float* t0o, float* t1o,
+                                        int32_t* ray_ido, void* stream) {
   using namespace txs;
   clear_error();
   TXS_REQUIRE(n_rays >= 0 && n_in >= 0 && capacity >= 0, "txs_gather_prefix: negative size");
-  if (n_rays == 0 || n_in == 0) return TXS_OK;
-  TXS_REQUIRE(packed_info_in && packed_info_out && t0 && t1 && ray_id,
-              "txs_gather_prefix: null input");
-  TXS_REQUIRE(capacity == 0 || (t0o && t1o), "txs_gather_prefix: null output");
-  const int64_t blocks = std::min<int64_t>((n_in + 255) / 256, 65536);
-  hipLaunchKernelGGL(gather_prefix_kernel, dim3((unsigned)blocks), dim3(256), 0,
+  if (n_rays == 0 || n_in == 0 || capacity == 0) return TXS_OK;
+  TXS_REQUIRE(packed_info_in && packed_info_out && t0 && t1, "txs_gather_prefix: null input");
+  TXS_REQUIRE(t0o && t1o, "txs_gather_prefix: null output");
+  const int64_t waves = ((int64_t)n_rays + kWave - 1) / kWave;
+  const int64_t blocks = (waves + kGatherWaves - 1) / kGatherWaves;
+  hipLaunchKernelGGL(gather_prefix_kernel, dim3((unsigned)blocks), dim3(kWave * kGatherWaves), 0,
                      as_stream(stream), packed_info_in, packed_info_out, n_rays, n_in, t0, t1,
-                     ray_id, capacity, t0o, t1o, ray_ido);
+                     capacity, t0o, t1o, ray_ido);
   return launch_status("txs_gather_prefix");
 }

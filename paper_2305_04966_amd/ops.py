@@ -137,21 +137,20 @@ def transmittance_prefix(packed_info, t0, t1, sigma, t_min=1e-4):
     return kept
 
 
-def gather_prefix(packed_info_in, packed_info_out, n_out, t0, t1, ray_id, want_ray_id=True):
+def gather_prefix(packed_info_in, packed_info_out, n_out, t0, t1, want_ray_id=True):
     n = packed_info_in.shape[0]
     s = t0.shape[0]
     _need(packed_info_in, "packed_info_in", torch.int32, (n, 2))
     _need(packed_info_out, "packed_info_out", torch.int32, (n, 2))
     _need(t0, "t0", torch.float32, (s,))
     _need(t1, "t1", torch.float32, (s,))
-    _need(ray_id, "ray_id", torch.int32, (s,))
     dev = t0.device
     t0o = torch.empty(n_out, dtype=torch.float32, device=dev)
     t1o = torch.empty(n_out, dtype=torch.float32, device=dev)
     rido = torch.empty(n_out, dtype=torch.int32, device=dev) if want_ray_id else None
     check(load().txs_gather_prefix(_ptr(packed_info_in), _ptr(packed_info_out), n, s, _ptr(t0),
-                                   _ptr(t1), _ptr(ray_id), n_out, _ptr(t0o), _ptr(t1o),
-                                   _ptr(rido), _stream()), "txs_gather_prefix")
+                                   _ptr(t1), n_out, _ptr(t0o), _ptr(t1o), _ptr(rido),
+                                   _stream()), "txs_gather_prefix")
     return t0o, t1o, rido
 
 
@@ -165,8 +164,8 @@ def _layout(packed_info, fixed_count, n_rays):
 
 
 def render_fwd(packed_info, t0, t1, sigma, rgb, *, n_rays=None, fixed_count=None, bg=None,
-               want_weights=False):
-    """-> (rgb [N,3], opacity [N], depth [N], weights [S] or None)."""
+               want_weights=False, want_optical_depth=False):
+    """-> (rgb [N,3], opacity [N], depth [N], weights [S] or None[, optical depth f64 [N]])."""
     n = packed_info.shape[0] if packed_info is not None else int(n_rays)
     fc = _layout(packed_info, fixed_count, n)
     s = t0.shape[0]
@@ -179,15 +178,18 @@ def render_fwd(packed_info, t0, t1, sigma, rgb, *, n_rays=None, fixed_count=None
     out_op = torch.empty(n, dtype=torch.float32, device=dev)
     out_d = torch.empty(n, dtype=torch.float32, device=dev)
     w = torch.empty(s, dtype=torch.float32, device=dev) if want_weights else None
+    od = torch.empty(n, dtype=torch.float64, device=dev) if want_optical_depth else None
     check(load().txs_render_fwd(_ptr(packed_info), fc, n, s, _ptr(t0), _ptr(t1), _ptr(sigma),
                                 _ptr(rgb), _ptr(bg), _ptr(out_rgb), _ptr(out_op), _ptr(out_d),
-                                _ptr(w), _stream()), "txs_render_fwd")
+                                _ptr(w), _ptr(od), _stream()), "txs_render_fwd")
+    if want_optical_depth:
+        return out_rgb, out_op, out_d, w, od
     return out_rgb, out_op, out_d, w
 
 
 def render_bwd(packed_info, t0, t1, sigma, rgb, g_rgb, g_opacity=None, g_depth=None, *,
-               n_rays=None, fixed_count=None, bg=None, want_d_rgb=True):
-    """-> (d_sigma [S], d_rgb [S,3] or None)."""
+               n_rays=None, fixed_count=None, bg=None, optical_depth=None, want_d_rgb=True):
+    """-> (d_sigma [S], d_rgb [S,3] or None).  optical_depth: the forward's, or None."""
     n = packed_info.shape[0] if packed_info is not None else int(n_rays)
     fc = _layout(packed_info, fixed_count, n)
     s = t0.shape[0]
@@ -198,24 +200,29 @@ def render_bwd(packed_info, t0, t1, sigma, rgb, g_rgb, g_opacity=None, g_depth=N
     _opt(g_opacity, "g_opacity", torch.float32, (n,))
     _opt(g_depth, "g_depth", torch.float32, (n,))
     _opt(bg, "bg", torch.float32, (n, 3))
+    _opt(optical_depth, "optical_depth", torch.float64, (n,))
     dev = t0.device
     ds = torch.empty(s, dtype=torch.float32, device=dev)
     dr = torch.empty((s, 3), dtype=torch.float32, device=dev) if want_d_rgb else None
     check(load().txs_render_bwd(_ptr(packed_info), fc, n, s, _ptr(t0), _ptr(t1), _ptr(sigma),
-                                _ptr(rgb), _ptr(bg), _ptr(g_rgb), _ptr(g_opacity),
-                                _ptr(g_depth), _ptr(ds), _ptr(dr), _stream()), "txs_render_bwd")
+                                _ptr(rgb), _ptr(bg), _ptr(optical_depth), _ptr(g_rgb),
+                                _ptr(g_opacity), _ptr(g_depth), _ptr(ds), _ptr(dr), _stream()),
+          "txs_render_bwd")
     return ds, dr
 
 
-def weights_bwd(packed_info, t0, t1, sigma, g_w, *, n_rays=None, fixed_count=None):
+def weights_bwd(packed_info, t0, t1, sigma, g_w, *, n_rays=None, fixed_count=None,
+                optical_depth=None):
     n = packed_info.shape[0] if packed_info is not None else int(n_rays)
     fc = _layout(packed_info, fixed_count, n)
     s = t0.shape[0]
     for name, t in (("t0", t0), ("t1", t1), ("sigma", sigma), ("g_w", g_w)):
         _need(t, name, torch.float32, (s,))
+    _opt(optical_depth, "optical_depth", torch.float64, (n,))
     ds = torch.empty(s, dtype=torch.float32, device=t0.device)
     check(load().txs_weights_bwd(_ptr(packed_info), fc, n, s, _ptr(t0), _ptr(t1), _ptr(sigma),
-                                 _ptr(g_w), _ptr(ds), _stream()), "txs_weights_bwd")
+                                 _ptr(optical_depth), _ptr(g_w), _ptr(ds), _stream()),
+          "txs_weights_bwd")
     return ds
 
 

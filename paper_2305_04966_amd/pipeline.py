@@ -55,7 +55,7 @@ def filter_transmittance(p: Packed, sigma, t_min=1e-4) -> Packed:
     kept = ops.transmittance_prefix(p.packed_info, p.t0, p.t1, sigma, t_min)
     info, total = ops.exclusive_scan(kept)
     s = _host_total(total)
-    t0, t1, rid = ops.gather_prefix(p.packed_info, info, s, p.t0, p.t1, p.ray_id)
+    t0, t1, rid = ops.gather_prefix(p.packed_info, info, s, p.t0, p.t1)
     return Packed(info, t0, t1, rid)
 
 
@@ -69,20 +69,25 @@ def sampling(grid: ops.GridSpec, rays_o, rays_d, density_fn: Callable, *, dt0,
 
 
 class RenderFn(torch.autograd.Function):
-    """Differentiable packed compositing; backward recomputes T and w."""
+    """Differentiable packed compositing.
+
+    The backward recomputes T and w from the inputs; the only forward state it
+    keeps is the per-ray total optical depth (binary64, 8 bytes per ray).
+    """
 
     @staticmethod
     def forward(ctx, sigma, rgb, packed_info, t0, t1, bg, n_rays, fixed_count):
-        out_rgb, out_op, out_d, _ = ops.render_fwd(packed_info, t0, t1, sigma.contiguous(),
-                                                   rgb.contiguous(), n_rays=n_rays,
-                                                   fixed_count=fixed_count, bg=bg)
-        ctx.save_for_backward(sigma, rgb, packed_info, t0, t1, bg)
+        out_rgb, out_op, out_d, _, od = ops.render_fwd(packed_info, t0, t1, sigma.contiguous(),
+                                                       rgb.contiguous(), n_rays=n_rays,
+                                                       fixed_count=fixed_count, bg=bg,
+                                                       want_optical_depth=True)
+        ctx.save_for_backward(sigma, rgb, packed_info, t0, t1, bg, od)
         ctx.n_rays, ctx.fixed_count = n_rays, fixed_count
         return out_rgb, out_op, out_d
 
     @staticmethod
     def backward(ctx, g_rgb, g_op, g_d):
-        sigma, rgb, packed_info, t0, t1, bg = ctx.saved_tensors
+        sigma, rgb, packed_info, t0, t1, bg, od = ctx.saved_tensors
         n = ctx.n_rays
         dev = t0.device
         g_rgb = g_rgb.contiguous() if g_rgb is not None else torch.zeros((n, 3), device=dev)
@@ -90,7 +95,7 @@ class RenderFn(torch.autograd.Function):
         g_d = g_d.contiguous() if g_d is not None else None
         ds, dr = ops.render_bwd(packed_info, t0, t1, sigma.contiguous(), rgb.contiguous(),
                                 g_rgb, g_op, g_d, n_rays=n, fixed_count=ctx.fixed_count, bg=bg,
-                                want_d_rgb=ctx.needs_input_grad[1])
+                                optical_depth=od, want_d_rgb=ctx.needs_input_grad[1])
         return ds, dr, None, None, None, None, None, None
 
 

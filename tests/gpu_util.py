@@ -22,8 +22,11 @@ def grid_spec(txs, bits, res, n_levels=1, half_extent0=1.5):
                         half_extent0)
 
 
+FLT_MIN = float(np.finfo(np.float32).tiny)  # 2^-126: binary32 has no relative precision below
+
+
 def assert_close(x, ref, *, rel=1e-5, floor_scale=None, name=""):
-    """|x - ref| <= rel |ref| + rel * s, s = 1e-3 max|ref| unless given (per element)."""
+    """|x - ref| <= rel |ref| + rel * s + FLT_MIN, s = 1e-3 max|ref| unless given."""
     x = np.asarray(x, np.float64)
     ref = np.asarray(ref, np.float64)
     assert x.shape == ref.shape, (name, x.shape, ref.shape)
@@ -31,7 +34,7 @@ def assert_close(x, ref, *, rel=1e-5, floor_scale=None, name=""):
         return
     s = 1e-3 * np.max(np.abs(ref)) if floor_scale is None else floor_scale
     err = np.abs(x - ref)
-    tol = rel * np.abs(ref) + rel * s
+    tol = rel * np.abs(ref) + rel * s + FLT_MIN
     bad = ~(err <= tol)
     if bad.any():
         i = np.flatnonzero(bad.reshape(-1))[:5]
@@ -49,7 +52,12 @@ def segment_ids(packed_info):
 
 
 def bwd_condition(packed_info, t0, t1, sigma, v):
-    """Per-sample scale Delta_k (T_{k+1}|v_k| + sum_{j>k} w_j |v_j|) of the adjoint (FP64)."""
+    """Per-sample scale Delta_k (T_{k+1} vb_k + sum_{j>k} w_j vb_j) of the adjoint (FP64).
+
+    vb is the magnitude of the terms that make up v = dL/dw (pass it already
+    made non-negative): the adjoint subtracts those terms, so binary32 carries
+    an error relative to this scale, not to the cancelled result.
+    """
     info = np.asarray(packed_info)
     seg = segment_ids(info)
     delta = np.asarray(t1, np.float64) - np.asarray(t0, np.float64)
