@@ -32,8 +32,8 @@ BYTES = {
     "march_fill": lambda N, Sm, S: 32 * N + 12 * Sm,
     "transmittance_prefix": lambda N, Sm, S: 12 * N + 12 * Sm,
     "gather_prefix": lambda N, Sm, S: 16 * N + 20 * S,
-    "render_fwd": lambda N, Sm, S: 28 * N + 24 * S,
-    "render_bwd": lambda N, Sm, S: 20 * N + 40 * S,
+    "render_fwd": lambda N, Sm, S: 36 * N + 24 * S,
+    "render_bwd": lambda N, Sm, S: 28 * N + 40 * S,
 }
 
 
@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--workload", default="image", choices=["image", "tiny", "unbounded"])
     ap.add_argument("--cpu-sample", type=int, default=16,
                     help="oracle baseline runs on every k-th ray (0 = skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after timing, run a plain device copy of this many MiB (counter "
+                         "calibration for profiler byte counts)")
     return ap.parse_args()
 
 
@@ -115,8 +118,10 @@ def gpu_bench(args, w):
         s = int(total2.item())
         q0, q1, qr = tl.run("gather_prefix", txs.gather_prefix, info, info2, s, t0, t1)
         sig, rgb = tl.run("field_density_rgb", txs.blob_field, params, nb, o, d, q0, q1, qr)
-        out = tl.run("render_fwd", txs.render_fwd, info2, q0, q1, sig, rgb)
-        grads = tl.run("render_bwd", txs.render_bwd, info2, q0, q1, sig, rgb, g_rgb)
+        out = tl.run("render_fwd", txs.render_fwd, info2, q0, q1, sig, rgb,
+                     want_optical_depth=True)
+        grads = tl.run("render_bwd", txs.render_bwd, info2, q0, q1, sig, rgb, g_rgb,
+                       optical_depth=out[4])
         stats["Sm"], stats["S"] = sm, s
         return out, grads
 
@@ -129,6 +134,11 @@ def gpu_bench(args, w):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    if args.copy_mib > 0:  # known-size copy: reads and writes copy_mib MiB once each
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     return elapsed, tl.summary(), stats
 
 

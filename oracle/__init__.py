@@ -20,7 +20,7 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "txs_oracle.c")
+_SRCS = [os.path.join(_HERE, "txs_oracle.c"), os.path.join(_HERE, "learned.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
     """Compile txs_oracle.c into liboracle.so next to it (gcc)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -43,7 +43,7 @@ def lib():
     with _lock:
         if _lib is None:
             if not os.path.exists(_LIB_PATH) or (os.path.getmtime(_LIB_PATH)
-                                                 < os.path.getmtime(_SRC)):
+                                                 < max(map(os.path.getmtime, _SRCS))):
                 build(force=True)
             _lib = C.CDLL(_LIB_PATH)
     return _lib
@@ -231,3 +231,64 @@ def field_at_samples(o, d, t0, t1, ray_id, params):
     rid = np.asarray(ray_id, np.int64)
     x = o[rid] + tm[:, None] * d[rid]
     return field(x, params)
+
+
+# ----------------------------------------------------------------------------
+# learned estimator (learned.c)
+# ----------------------------------------------------------------------------
+def mlp_param_count(H: int) -> int:
+    """W1 [H,39], b1 [H], W2 [H,H], b2 [H], w3 [H], b3."""
+    return H * H + 42 * H + 1
+
+
+def bin_midpoints(o, d, edges):
+    """FP64 points x = o + (e_j + e_{j+1})/2 d for dense bins -> [N*n_bins, 3]."""
+    e = np.asarray(edges, np.float64)
+    tm = 0.5 * (e[:, :-1] + e[:, 1:])
+    x = np.asarray(o, np.float64)[:, None, :] + tm[..., None] * np.asarray(d, np.float64)[:, None, :]
+    return x.reshape(-1, 3)
+
+
+def mlp_fwd(x, params, H, scale=1.5, contract=False, emulate_bf16=False, want_z=False):
+    """Proposal MLP at points x [n,3] -> sigma [n] (FP64 or bf16-emulated)."""
+    x = _f64(x).reshape(-1, 3)
+    p = _f32(params)
+    assert p.size == mlp_param_count(H)
+    n = x.shape[0]
+    s = np.zeros(n, np.float64)
+    z = np.zeros(n, np.float64) if want_z else None
+    lib().oracle_mlp_fwd(C.c_int64(n), _p(x), _p(p), C.c_int32(H), C.c_double(scale),
+                         C.c_int32(int(contract)), C.c_int32(int(emulate_bf16)), _p(s), _p(z))
+    return (s, z) if want_z else s
+
+
+def mlp_bwd(x, params, H, d_sigma, scale=1.5, contract=False, emulate_bf16=False):
+    """Gradient of sum_i d_sigma_i sigma(x_i) w.r.t. the parameter vector (FP64)."""
+    x = _f64(x).reshape(-1, 3)
+    p = _f32(params)
+    g = np.zeros(mlp_param_count(H), np.float64)
+    lib().oracle_mlp_bwd(C.c_int64(x.shape[0]), _p(x), _p(p), C.c_int32(H), C.c_double(scale),
+                         C.c_int32(int(contract)), C.c_int32(int(emulate_bf16)),
+                         _p(_f64(d_sigma)), _p(g))
+    return g
+
+
+def hist_loss(packed_info, t0, t1, w, edges, wp, eps=1e-7, want_grad=True):
+    """Per-ray proposal loss and d(mean loss)/d(proposal weights)."""
+    info = _i32(packed_info)
+    n = info.shape[0]
+    edges, wp = _f32(edges), _f32(wp)
+    nb = wp.shape[1]
+    loss = np.zeros(n, np.float64)
+    d = np.zeros((n, nb), np.float64) if want_grad else None
+    lib().oracle_hist_loss(C.c_int32(n), _p(info), _p(_f32(t0)), _p(_f32(t1)), _p(_f32(w)),
+                           C.c_int32(nb), _p(edges), _p(wp), C.c_double(eps), _p(loss), _p(d))
+    return loss, d
+
+
+def adam(p, m, v, g, lr, b1=0.9, b2=0.99, eps=1e-15, step=1):
+    """One Adam step in FP64, in place on copies -> (p, m, v)."""
+    p, m, v = _f64(p).copy(), _f64(m).copy(), _f64(v).copy()
+    lib().oracle_adam(C.c_int64(p.size), _p(p), _p(m), _p(v), _p(_f64(g)), C.c_double(lr),
+                      C.c_double(b1), C.c_double(b2), C.c_double(eps), C.c_int32(step))
+    return p, m, v

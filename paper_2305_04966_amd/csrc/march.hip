@@ -65,14 +65,6 @@ __device__ __forceinline__ void clip_box(const float o[3], const float inv[3], c
   tf = t_far;
 }
 
-template <int N>
-__device__ __forceinline__ float pick(const float (&v)[N], int i) {
-  float r = v[0];
-#pragma unroll
-  for (int j = 1; j < N; ++j) r = (i == j) ? v[j] : r;
-  return r;
-}
-
 struct Emit {
   float* t0;
   float* t1;
@@ -85,7 +77,8 @@ struct Emit {
 // One segment [a, b) on level l, 64 lattice points per step.  n: samples so
 // far (wave-uniform); returns the new count.
 template <bool kFill>
-__device__ int32_t march_segment(const MarchArgs& g, const float o[3], const float d[3], float a,
+__device__ __forceinline__ int32_t march_segment(const MarchArgs& g, const float o[3],
+                                                 const float d[3], float a,
                                  float b, int l, int32_t n, int32_t cap, const Emit& em) {
   const float dt = g.dt0 * (float)(1 << l);
   const LevelBox box = level_box(g, l);
@@ -130,31 +123,28 @@ __device__ int32_t march_segment(const MarchArgs& g, const float o[3], const flo
 }
 
 template <bool kFill>
-__device__ int32_t march_ray(const MarchArgs& g, const float o[3], const float d[3],
+__device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const float o[3], const float d[3],
                              const Emit& em) {
   float inv[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) inv[c] = 1.0f / d[c];
   const int L = g.n_levels;
-  float tn[kMaxLevels], tf[kMaxLevels];
+  // lane l holds the chord of level l's cube
+  const int ln = lane();
+  float tn_l = INFINITY, tf_l = -INFINITY;
+  if (ln < L) clip_box(o, inv, level_box(g, ln), g.near_plane, g.far_plane, tn_l, tf_l);
+  // an inner cube's chord lies inside the next outer one: max / min over l' >= l
 #pragma unroll
-  for (int l = 0; l < kMaxLevels; ++l) {
-    tn[l] = INFINITY;
-    tf[l] = -INFINITY;
-    if (l < L) clip_box(o, inv, level_box(g, l), g.near_plane, g.far_plane, tn[l], tf[l]);
-  }
-  // an inner cube's chord lies inside the next outer one
-#pragma unroll
-  for (int l = kMaxLevels - 2; l >= 0; --l) {
-    if (l + 1 < L) {
-      tn[l] = fmaxf(tn[l], tn[l + 1]);
-      tf[l] = fminf(tf[l], tf[l + 1]);
+  for (int s = 1; s < kMaxLevels; s <<= 1) {
+    const float a_n = shfl_down(tn_l, s), a_f = shfl_down(tf_l, s);
+    if (ln + s < L) {
+      tn_l = fmaxf(tn_l, a_n);
+      tf_l = fminf(tf_l, a_f);
     }
   }
-  uint32_t hit = 0;
-#pragma unroll
-  for (int l = 0; l < kMaxLevels; ++l)
-    if (l < L && tn[l] < tf[l]) hit |= 1u << l;
+  const uint32_t hit = (uint32_t)__ballot(ln < L && tn_l < tf_l);
+  auto tn = [&](int l) { return readlane(tn_l, l); };
+  auto tf = [&](int l) { return readlane(tf_l, l); };
 
   const int32_t cap = g.max_per_ray;
   int32_t n = 0;
@@ -165,13 +155,13 @@ __device__ int32_t march_ray(const MarchArgs& g, const float o[3], const float d
     if (s < L) {
       l = L - 1 - s;
       if (!((hit >> l) & 1u)) continue;
-      a = pick(tn, l);
-      b = (l > 0 && ((hit >> (l - 1)) & 1u)) ? pick(tn, l - 1) : pick(tf, l);
+      a = tn(l);
+      b = (l > 0 && ((hit >> (l - 1)) & 1u)) ? tn(l - 1) : tf(l);
     } else {
       l = s - L + 1;
       if (!((hit >> l) & 1u) || !((hit >> (l - 1)) & 1u)) continue;
-      a = pick(tf, l - 1);
-      b = pick(tf, l);
+      a = tf(l - 1);
+      b = tf(l);
     }
     n = march_segment<kFill>(g, o, d, a, b, l, n, cap, em);
     if (cap > 0 && n >= cap) break;

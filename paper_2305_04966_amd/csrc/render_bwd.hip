@@ -52,8 +52,7 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
     }
     if (!has_mark) Bq += (double)tau[j];
   }
-  int cp = shfl_up(max_scan_incl(lastm), 1);
-  if (ln == 0) cp = -1;
+  const int cp = lane_prev(max_scan_incl(lastm), -1);
   const int seg_lane = (cp >= 0) ? decode_mark(L.marks[cp]) : seg_in;
   int cur_[K];
   bool own[K];
@@ -73,8 +72,7 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
   const int fl = min_scan_rev_incl(has_mark ? ln : kWave);
   double Rq = seg_scan_rev(Bq, fl);
   if (fl == kWave) Rq += cQ;
-  double q = shfl_down(Rq, 1);
-  if (ln == kWave - 1) q = cQ;
+  double q = lane_next(Rq, cQ);
 
   // right to left: P_i = P_total - Q_i; weights, v, u = w v, T_{i+1} v; d_rgb
   float u[K], tv[K];
@@ -84,15 +82,17 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
     float gwv[K];
     if (kMode == kBwd) load_rgb(a.rgb, pos0, lim, c);
     else load_k(a.g_w, pos0, lim, gwv);
-    float dr[K][3];
+    float T_right = 0.0f;  // T of element j+1 (same lane)
 #pragma unroll
     for (int j = K - 1; j >= 0; --j) {
       q += (double)tau[j];  // Q_j, inclusive
       const int cs = cur_[j] < 0 ? 0 : cur_[j];
       const double P = L.ptot[cs] - q;
-      const float T = expf(-(float)P);
-      const float Tn = expf(-(float)(P + (double)tau[j]));
-      const float w = T * -expm1f(-tau[j]);
+      const float T = exp_neg(P);
+      // T_{j+1} is the next element's T unless j ends its lane or its ray
+      const float Tn = (j == K - 1 || mk[j + 1] != 0) ? exp_neg(P + (double)tau[j]) : T_right;
+      T_right = T;
+      const float w = T * one_minus_exp_neg(tau[j]);
       float v;
       if (kMode == kBwd) {
         const float4 g4 = *reinterpret_cast<const float4*>(&L.cot[cs][0]);
@@ -100,9 +100,11 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
         // cot row: g0 g1 g2 h | q bg0 bg1 bg2
         v = g4.x * (c[j][0] - b4.y) + g4.y * (c[j][1] - b4.z) + g4.z * (c[j][2] - b4.w) + g4.w +
             b4.x * mid[j];
-        dr[j][0] = w * g4.x;
-        dr[j][1] = w * g4.y;
-        dr[j][2] = w * g4.z;
+        if (a.d_rgb && own[j]) {
+          a.d_rgb[3 * (pos0 + j)] = w * g4.x;
+          a.d_rgb[3 * (pos0 + j) + 1] = w * g4.y;
+          a.d_rgb[3 * (pos0 + j) + 2] = w * g4.z;
+        }
       } else {
         v = gwv[j];
       }
@@ -116,33 +118,12 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
       if (mk[j] != 0) before_first = false;
       if (before_first) Bs += (double)u[j];
     }
-    if (kMode == kBwd && a.d_rgb) {
-      const int64_t base = 3 * pos0;
-      if (all_own) {
-        float4* o4 = reinterpret_cast<float4*>(a.d_rgb + base);
-#pragma unroll
-        for (int i = 0; i < 3 * K / 4; ++i) {
-          const int e = 4 * i;
-          o4[i] = make_float4(dr[e / 3][e % 3], dr[(e + 1) / 3][(e + 1) % 3],
-                              dr[(e + 2) / 3][(e + 2) % 3], dr[(e + 3) / 3][(e + 3) % 3]);
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-          if (own[j]) {
-            a.d_rgb[base + 3 * j] = dr[j][0];
-            a.d_rgb[base + 3 * j + 1] = dr[j][1];
-            a.d_rgb[base + 3 * j + 2] = dr[j][2];
-          }
-      }
-    }
   }
 
   // reverse scan of u: the suffix sum entering each lane from the right
   double Rs = seg_scan_rev(Bs, fl);
   if (fl == kWave) Rs += cS;
-  double s = shfl_down(Rs, 1);
-  if (ln == kWave - 1) s = cS;
+  double s = lane_next(Rs, cS);
   float ds[K];
 #pragma unroll
   for (int j = K - 1; j >= 0; --j) {

@@ -88,50 +88,117 @@ __device__ __forceinline__ void ray_row(const Args& a, int32_t r, int64_t& st, i
 }
 
 // ----------------------------------------------------------- wave scans
+// Lane scans run inside each 16-lane row with DPP row shifts (VALU latency),
+// then the three row-end values are read into scalars and carried into the
+// later rows.  They must be called with all 64 lanes active.
+
+// Inclusive max over lanes <= this one.
 __device__ __forceinline__ int max_scan_incl(int v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int t = shfl_up(v, d);
-    if (lane() >= d) v = max(v, t);
-  }
-  return v;
+  const int ri = lane() & 15, row = lane() >> 4;
+  int t;
+  t = dpp<kRowShr1>(v, v); if (ri >= 1) v = max(v, t);
+  t = dpp<kRowShr2>(v, v); if (ri >= 2) v = max(v, t);
+  t = dpp<kRowShr4>(v, v); if (ri >= 4) v = max(v, t);
+  t = dpp<kRowShr8>(v, v); if (ri >= 8) v = max(v, t);
+  const int e0 = readlane(v, 15), e1 = readlane(v, 31), e2 = readlane(v, 47);
+  const int c1 = e0, c2 = max(c1, e1), c3 = max(c2, e2);
+  const int c = row == 1 ? c1 : row == 2 ? c2 : row == 3 ? c3 : v;
+  return max(v, c);
 }
 
+// Inclusive min over lanes >= this one.
 __device__ __forceinline__ int min_scan_rev_incl(int v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int t = shfl_down(v, d);
-    if (lane() + d < kWave) v = min(v, t);
-  }
-  return v;
+  const int ri = lane() & 15, row = lane() >> 4;
+  int t;
+  t = dpp<kRowShl1>(v, v); if (ri + 1 < 16) v = min(v, t);
+  t = dpp<kRowShl2>(v, v); if (ri + 2 < 16) v = min(v, t);
+  t = dpp<kRowShl4>(v, v); if (ri + 4 < 16) v = min(v, t);
+  t = dpp<kRowShl8>(v, v); if (ri + 8 < 16) v = min(v, t);
+  const int e1 = readlane(v, 16), e2 = readlane(v, 32), e3 = readlane(v, 48);
+  const int c2 = e3, c1 = min(e2, c2), c0 = min(e1, c1);
+  const int c = row == 0 ? c0 : row == 1 ? c1 : row == 2 ? c2 : v;
+  return min(v, c);
 }
 
 // Inclusive segmented scan over lanes; hl = last lane <= this one that starts
-// a segment (-1 if none).
+// a segment (-1 if none): the sum over lanes [max(hl, 0), lane].
 template <typename T>
 __device__ __forceinline__ T seg_scan(T v, int hl) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const T t = shfl_up(v, d);
-    if (lane() >= d && lane() - d >= hl) v += t;
-  }
+  const int ln = lane(), ri = ln & 15, row = ln >> 4;
+  const T z = T(0);
+  T t;
+  t = dpp<kRowShr1>(z, v); if (ri >= 1 && ln - 1 >= hl) v += t;
+  t = dpp<kRowShr2>(z, v); if (ri >= 2 && ln - 2 >= hl) v += t;
+  t = dpp<kRowShr4>(z, v); if (ri >= 4 && ln - 4 >= hl) v += t;
+  t = dpp<kRowShr8>(z, v); if (ri >= 8 && ln - 8 >= hl) v += t;
+  // carry of row r = value at the end of row r-1, chained while that row
+  // holds no segment start
+  const T e0 = readlane(v, 15), e1 = readlane(v, 31), e2 = readlane(v, 47);
+  const int h1 = readlane(hl, 31), h2 = readlane(hl, 47);
+  const T c1 = e0;
+  const T c2 = e1 + (h1 < 16 ? c1 : z);
+  const T c3 = e2 + (h2 < 32 ? c2 : z);
+  const T c = row == 1 ? c1 : row == 2 ? c2 : c3;
+  if (row > 0 && hl < 16 * row) v += c;
   return v;
 }
 
 // Reverse inclusive segmented scan; fl = first lane >= this one that ends the
-// chain (64 if none).
+// chain (64 if none): the sum over lanes [lane, min(fl, 63)].
 template <typename T>
 __device__ __forceinline__ T seg_scan_rev(T v, int fl) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const T t = shfl_down(v, d);
-    if (lane() + d < kWave && lane() + d <= fl) v += t;
-  }
+  const int ln = lane(), ri = ln & 15, row = ln >> 4;
+  const T z = T(0);
+  T t;
+  t = dpp<kRowShl1>(z, v); if (ri + 1 < 16 && ln + 1 <= fl) v += t;
+  t = dpp<kRowShl2>(z, v); if (ri + 2 < 16 && ln + 2 <= fl) v += t;
+  t = dpp<kRowShl4>(z, v); if (ri + 4 < 16 && ln + 4 <= fl) v += t;
+  t = dpp<kRowShl8>(z, v); if (ri + 8 < 16 && ln + 8 <= fl) v += t;
+  // carry of row r = value at the start of row r+1, chained while that row
+  // holds no chain end
+  const T e1 = readlane(v, 16), e2 = readlane(v, 32), e3 = readlane(v, 48);
+  const int f1 = readlane(fl, 16), f2 = readlane(fl, 32);
+  const T c2 = e3;
+  const T c1 = e2 + (f2 > 47 ? c2 : z);
+  const T c0 = e1 + (f1 > 31 ? c1 : z);
+  const T c = row == 0 ? c0 : row == 1 ? c1 : c2;
+  if (row < 3 && fl > 16 * row + 15) v += c;
   return v;
 }
 
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  return __shfl(v, l, kWave);
+// Value of the previous / next lane (lane 0 / 63 receive `fill`).
+template <typename T>
+__device__ __forceinline__ T lane_prev(T v, T fill) { return dpp<kWaveShr1>(fill, v); }
+template <typename T>
+__device__ __forceinline__ T lane_next(T v, T fill) { return dpp<kWaveShl1>(fill, v); }
+
+__device__ __forceinline__ double readlane_d(double v, int l) { return readlane(v, l); }
+
+// exp(-x) from a binary64 argument: -x log2(e) = n + f with n an integer and
+// f in [0,1), so exp(-x) = 2^f 2^n; 2^f comes from the hardware exp2 on a
+// binary32 f, whose rounding (2^-24 absolute) is the only error besides the
+// exp2 itself, for any x.  Results below 2^-250 flush to zero.
+__device__ __forceinline__ float exp_neg(double x) {
+  const double y = -x * 1.4426950408889634;
+  if (!(y > -250.0)) return 0.0f;
+  const double n = floor(y);
+  return ldexpf(__builtin_amdgcn_exp2f((float)(y - n)), (int)n);
+}
+
+// 1 - exp(-t) for t >= 0 without cancellation: for t < 1/4 the nested Taylor
+// form t (1 - t/2 (1 - t/3 (1 - ... (1 - t/7)))) (truncation < 1e-9
+// relative), otherwise 1 - exp(-t) with exp(-t) <= 0.78.
+__device__ __forceinline__ float one_minus_exp_neg(float t) {
+  if (t < 0.25f) {
+    float r = 1.0f - t * (1.0f / 7.0f);
+    r = 1.0f - t * (1.0f / 6.0f) * r;
+    r = 1.0f - t * (1.0f / 5.0f) * r;
+    r = 1.0f - t * 0.25f * r;
+    r = 1.0f - t * (1.0f / 3.0f) * r;
+    r = 1.0f - t * 0.5f * r;
+    return t * r;
+  }
+  return 1.0f - exp_neg((double)t);
 }
 
 struct Acc5 {
@@ -142,7 +209,8 @@ __device__ __forceinline__ Acc5 seg_scan(Acc5 v, int hl) {
           seg_scan(v.d, hl)};
 }
 __device__ __forceinline__ Acc5 shfl_up1(Acc5 v) {
-  return {shfl_up(v.r, 1), shfl_up(v.g, 1), shfl_up(v.b, 1), shfl_up(v.o, 1), shfl_up(v.d, 1)};
+  return {lane_prev(v.r, 0.0f), lane_prev(v.g, 0.0f), lane_prev(v.b, 0.0f), lane_prev(v.o, 0.0f),
+          lane_prev(v.d, 0.0f)};
 }
 
 // ----------------------------------------------------------- loads / stores

@@ -65,10 +65,8 @@ __device__ FwdCarry fwd_window(const Args& a, WaveLds& L, int32_t r0, int64_t p,
   }
   const int hl = max_scan_incl(has_mark ? ln : -1);
   const double incl_tau = seg_scan(run, hl);
-  double P = shfl_up(incl_tau, 1);
-  if (ln == 0) P = cin.P;
-  int cp = shfl_up(max_scan_incl(lastm), 1);
-  if (ln == 0) cp = -1;
+  double P = lane_prev(incl_tau, cin.P);
+  const int cp = lane_prev(max_scan_incl(lastm), -1);
   int cur = (cp >= 0) ? decode_mark(L.marks[cp]) : cin.seg;
 
   // pass 2: transmittance, weights, per-ray sums
@@ -93,8 +91,8 @@ __device__ FwdCarry fwd_window(const Args& a, WaveLds& L, int32_t r0, int64_t p,
     const bool live = cur >= 0 && (pos0 + j) < lim;
     own[j] = live;
     if (kMode == kFwd) {
-      const float T = expf(-(float)P);
-      const float alpha = -expm1f(-tau[j]);
+      const float T = exp_neg(P);
+      const float alpha = one_minus_exp_neg(tau[j]);
       const float w = live ? T * alpha : 0.0f;
       wv[j] = w;
       const float mid = 0.5f * (t0v[j] + t1v[j]);
@@ -144,7 +142,7 @@ __device__ FwdCarry fwd_window(const Args& a, WaveLds& L, int32_t r0, int64_t p,
                     readlane(incl.d, kWave - 1)};
   } else if (kMode == kPrefix) {
     const int incl = seg_scan(cnt, hl);
-    const int carry = shfl_up(incl, 1);
+    const int carry = lane_prev(incl, 0);
     if (first_ray >= 0)
       emit_ray<kMode>(a, r0 + first_ray, Acc5{}, first_cnt + (ln > 0 ? carry : 0));
     cout.cnt = readlane(incl, kWave - 1);

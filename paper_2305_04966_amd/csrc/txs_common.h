@@ -68,6 +68,36 @@ __device__ __forceinline__ int64_t wave_min(int64_t v) {
   return v;
 }
 
+// ---- DPP lane moves (data-parallel primitives of the GFX9 family) ----------
+// A VALU move that reads another lane of the same wave: no LDS round trip.
+// Lanes whose source lane is outside the row (row_*) or the wave (wave_*)
+// receive `old`.
+enum DppCtrl : int {
+  kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108,
+  kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118,
+  kWaveShl1 = 0x130, kWaveShr1 = 0x138,
+};
+
+template <int kCtrl>
+__device__ __forceinline__ int dpp(int old, int src) {
+  return __builtin_amdgcn_update_dpp(old, src, kCtrl, 0xf, 0xf, false);
+}
+template <int kCtrl>
+__device__ __forceinline__ float dpp(float old, float src) {
+  return __int_as_float(dpp<kCtrl>(__float_as_int(old), __float_as_int(src)));
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp(double old, double src) {
+  const int lo = dpp<kCtrl>(__double2loint(old), __double2loint(src));
+  const int hi = dpp<kCtrl>(__double2hiint(old), __double2hiint(src));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
 // Keeps the compiler from moving memory operations across this point; the
 // hardware already executes one wave's LDS operations in order.
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
