@@ -153,8 +153,9 @@ txs_status txs_gather_prefix(const int32_t* packed_info_in, const int32_t* packe
  *   out_depth = sum w_i (t0_i + t1_i)/2   (unnormalised expected depth).
  * packed_info may be NULL: then ray r owns samples [r*fixed_count,
  * (r+1)*fixed_count) (dense layout, e.g. proposal resampling output).
- * sigma float [n_samples], rgb float [n_samples, 3], bg float [n_rays, 3] or
- * NULL (black).  Outputs: out_rgb [n_rays,3], out_opacity [n_rays],
+ * sigma float [n_samples], rgb float [n_samples, 3] or NULL (colour taken as
+ * zero: weights, opacity and depth only), bg float [n_rays, 3] or NULL
+ * (black).  Outputs: out_rgb [n_rays,3], out_opacity [n_rays],
  * out_depth [n_rays], out_weights [n_samples] or NULL, and
  * out_optical_depth double [n_rays] or NULL = sum_i tau_i per ray.
  * Optical depths are accumulated in binary64.
@@ -227,6 +228,69 @@ txs_status txs_resample(int32_t n_rays, int32_t n_bins, const float* edges, cons
 txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, float far_plane,
                             const float* rays_o, const float* rays_d, int32_t n_rays,
                             int32_t n_bins, float* out_edges, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned transmittance estimator: the proposal network (Section 3.1 "PDF
+ * Approaches", Table 1 third row; Section 3.2 "Choice of Representations").
+ *   x_hat = x / scale, or contract(x / scale) / 2 with contract(y) = y for
+ *           |y| <= 1 and (2 - 1/|y|) y/|y| beyond (unbounded scenes)
+ *   gamma = [x_hat, sin(2^k pi x_hat_a), cos(2^k pi x_hat_a)], a = 0..2, k = 0..5
+ *   h1 = relu(W1 gamma + b1), h2 = relu(W2 h1 + b2), sigma = softplus(w3.h2 + b3)
+ * Parameters: one float vector W1 [H,39], b1 [H], W2 [H,H], b2 [H], w3 [H], b3
+ * (txs_mlp_param_count(H) values, row-major).  The matrix cores read bf16
+ * operand tiles made from it by txs_mlp_pack (gamma, h1, h2 and the weights
+ * are rounded to bf16, round-to-nearest-even; accumulation is fp32; biases
+ * stay fp32).  H is 64 or 128.                                              */
+typedef struct {
+  const void* packed;  /* device, txs_mlp_packed_bytes(hidden), from txs_mlp_pack */
+  const float* params; /* device, the float parameter vector (biases read here) */
+  int32_t hidden;      /* 64 or 128 */
+  float scale;         /* > 0 */
+  int32_t contract;    /* 0: bounded scene, 1: contracted unbounded scene */
+} txs_mlp;
+
+size_t txs_mlp_param_count(int32_t hidden);
+size_t txs_mlp_packed_bytes(int32_t hidden);
+txs_status txs_mlp_pack(const float* params, int32_t hidden, void* packed, void* stream);
+
+/*
+ * Proposal density at the midpoints of n_bins bins per ray:
+ * x = o + (e_j + e_{j+1})/2 d with edges float [n_rays, n_bins+1];
+ * sigma float [n_rays, n_bins].
+ */
+txs_status txs_prop_mlp_fwd(const txs_mlp* mlp, const float* rays_o, const float* rays_d,
+                            int32_t n_rays, int32_t n_bins, const float* edges, float* sigma,
+                            void* stream);
+
+/*
+ * PDF-matching loss of the proposal estimator (its update by gradient descent,
+ * Eq. 4 and Section 3.1 "PDF Approaches"; the proposal loss of Mip-NeRF 360,
+ * on which the paper's proposal network rests).  Targets are the radiance
+ * field's rendering weights on its own intervals, packed per ray
+ * (packed_info, t0, t1, w; n_targets samples, sorted and disjoint per ray);
+ * the proposal has n_bins dense bins per ray (edges [n_rays, n_bins+1],
+ * weights prop_w [n_rays, n_bins]).  For each target interval,
+ *   bound_i = sum of prop_w over the bins overlapping (t0_i, t1_i)
+ *             (e_j < t1_i and e_{j+1} > t0_i),
+ *   loss[r] = sum_i max(0, w_i - bound_i)^2 / (w_i + eps).
+ * d_prop (may be NULL) = d(mean_r loss[r]) / d prop_w, float [n_rays, n_bins];
+ * each bin sums its overlapping targets in target order (deterministic).
+ * n_bins <= 1024.
+ */
+txs_status txs_hist_loss(const int32_t* packed_info, int32_t n_rays, int64_t n_targets,
+                         const float* t0, const float* t1, const float* w, int32_t n_bins,
+                         const float* edges, const float* prop_w, float eps, float* loss,
+                         float* d_prop, void* stream);
+
+/*
+ * One Adam step (Kingma & Ba 2015) on n fp32 parameters, in place:
+ *   m = b1 m + (1-b1) g,  v = b2 v + (1-b2) g^2,
+ *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),  step >= 1.
+ * Re-run txs_mlp_pack afterwards to refresh the bf16 operand tiles.
+ */
+txs_status txs_adam_step(float* params, float* m, float* v, const float* grad, int64_t n,
+                         float lr, float beta1, float beta2, float eps, int32_t step,
+                         void* stream);
 
 /*
  * Support (not part of the method): an analytic radiance field standing in for

@@ -31,8 +31,13 @@ class MarchParams(C.Structure):
                 ("max_per_ray", C.c_int32)]
 
 
+class Mlp(C.Structure):
+    _fields_ = [("packed", C.c_void_p), ("params", C.c_void_p), ("hidden", C.c_int32),
+                ("scale", C.c_float), ("contract", C.c_int32)]
+
+
 P, I32, I64, F32, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
-GP, MP = C.POINTER(Grid), C.POINTER(MarchParams)
+GP, MP, MLP = C.POINTER(Grid), C.POINTER(MarchParams), C.POINTER(Mlp)
 
 SIGNATURES = {
     "txs_last_error": (C.c_char_p, []),
@@ -49,6 +54,12 @@ SIGNATURES = {
     "txs_resample": (I32, [I32, I32, P, P, I32, I32, P, P, P]),
     "txs_uniform_bins": (I32, [GP, F32, F32, P, P, I32, I32, P, P]),
     "txs_blob_field": (I32, [P, I32, P, P, I32, P, P, P, I32, I64, P, P, P]),
+    "txs_mlp_param_count": (SZ, [I32]),
+    "txs_mlp_packed_bytes": (SZ, [I32]),
+    "txs_mlp_pack": (I32, [P, I32, P, P]),
+    "txs_prop_mlp_fwd": (I32, [MLP, P, P, I32, I32, P, P, P]),
+    "txs_hist_loss": (I32, [P, I32, I64, P, P, P, I32, P, P, F32, P, P, P]),
+    "txs_adam_step": (I32, [P, P, P, P, I64, F32, F32, F32, F32, I32, P]),
 }
 
 _lock = threading.Lock()

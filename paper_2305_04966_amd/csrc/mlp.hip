@@ -1,0 +1,316 @@
+// Proposal network of the learned transmittance estimator (Section 3.1 "PDF
+// Approaches", Table 1 third row; Section 3.2 "Choice of Representations"):
+// x -> Fourier features -> H ReLU -> H ReLU -> 1 -> softplus, evaluated at the
+// midpoints of each ray's bins, on the bf16 matrix cores with fp32 accumulation.
+//
+// MFMA formulation (v_mfma_f32_16x16x32_bf16, wave64).  Every layer computes
+// its output transposed: rows = hidden units (M), columns = 16 points (N),
+// K = input units.  In that form the 16x16 fp32 fragment a lane holds after a
+// layer (one point column, four consecutive unit rows per 16-lane group) is,
+// once rounded to bf16, exactly the lane's share of the next layer's B operand,
+// provided the next layer's K order is the matching permutation of its input
+// units; that permutation is applied once, when the weights are packed into
+// operand tiles (txs_mlp_pack), so no activation moves between lanes.  The
+// three 16-lane groups g = 0,1,2 each encode the 13 features of axis g.
+#include <cmath>
+
+#include "txs_common.h"
+
+namespace txs {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int kNF = 39;  // x_hat (3) + 3 axes x 6 octaves x (sin, cos)
+
+// ---------------------------------------------------------------- layout
+// Parameter vector: W1 [H,39], b1 [H], W2 [H,H], b2 [H], w3 [H], b3.
+struct ParamOffsets {
+  int64_t W1, b1, W2, b2, w3, b3, total;
+  __host__ __device__ explicit ParamOffsets(int H)
+      : W1(0), b1(39 * H), W2(40 * H), b2(40 * H + (int64_t)H * H), w3(41 * H + (int64_t)H * H),
+        b3(42 * H + (int64_t)H * H), total(42 * H + (int64_t)H * H + 1) {}
+};
+
+// Packed operand tiles (bf16), each tile = 64 lanes x 8 values:
+//   A1[m][s]  layer 1 (W1), m < H/16, s < 2
+//   A2[m][s]  layer 2 (W2), s < H/32
+//   A2t[m][s] layer 2 transposed (W2^T, for the adjoint), s < H/32
+//   w3 (H values, unit order)
+struct PackOffsets {
+  int64_t A1, A2, A2t, w3, total;  // in bf16 elements
+  __host__ __device__ explicit PackOffsets(int H)
+      : A1(0), A2((int64_t)(H / 16) * 2 * 512), A2t(A2 + (int64_t)(H / 16) * (H / 32) * 512),
+        w3(A2t + (int64_t)(H / 16) * (H / 32) * 512), total(w3 + H) {}
+};
+
+// Feature slot q (0..15) of lane group g: q < 12 -> sin/cos of octave q/2 of
+// axis g, q = 12 -> x_hat_g, otherwise unused.  Canonical feature index or -1.
+__host__ __device__ inline int feature_of(int g, int q) {
+  if (g > 2) return -1;
+  if (q < 12) return 3 + 12 * g + q;
+  return q == 12 ? g : -1;
+}
+
+// K position i (0..7) of K-step s for lane group g of a layer whose input is a
+// previous layer's fragments: input unit 16 (2s + i/4) + 4g + i%4.
+__host__ __device__ inline int unit_of(int s, int g, int i) {
+  return 16 * (2 * s + i / 4) + 4 * g + (i % 4);
+}
+
+__global__ void pack_kernel(const float* __restrict__ p, int H, __bf16* __restrict__ out) {
+  const ParamOffsets po(H);
+  const PackOffsets ko(H);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ko.total) return;
+  float v = 0.0f;
+  if (e < ko.A2) {  // A1[m][s][lane][i]
+    const int64_t t = e / 512, r = e % 512;
+    const int m = (int)(t / 2), s = (int)(t % 2), l = (int)(r / 8), i = (int)(r % 8);
+    const int f = feature_of(l / 16, 8 * s + i);
+    v = f >= 0 ? p[po.W1 + (int64_t)(16 * m + l % 16) * kNF + f] : 0.0f;
+  } else if (e < ko.A2t) {  // A2[m][s][lane][i] = W2[out][in]
+    const int64_t t = (e - ko.A2) / 512, r = (e - ko.A2) % 512;
+    const int m = (int)(t / (H / 32)), s = (int)(t % (H / 32)), l = (int)(r / 8), i = (int)(r % 8);
+    v = p[po.W2 + (int64_t)(16 * m + l % 16) * H + unit_of(s, l / 16, i)];
+  } else if (e < ko.w3) {  // A2t[m][s][lane][i] = W2[out = permuted K][in = row]
+    const int64_t t = (e - ko.A2t) / 512, r = (e - ko.A2t) % 512;
+    const int m = (int)(t / (H / 32)), s = (int)(t % (H / 32)), l = (int)(r / 8), i = (int)(r % 8);
+    v = p[po.W2 + (int64_t)unit_of(s, l / 16, i) * H + (16 * m + l % 16)];
+  } else {  // w3 in unit order
+    v = p[po.w3 + (e - ko.w3)];
+  }
+  out[e] = (__bf16)v;
+}
+
+// ---------------------------------------------------------------- forward
+struct FwdArgs {
+  const __bf16* packed;
+  const float* params;
+  float scale;
+  int32_t contract;
+  const float* ro;
+  const float* rd;
+  int32_t n_rays, n_bins;
+  const float* edges;
+  float* sigma;
+};
+
+__device__ __forceinline__ bf16x8 pack8(const float (&v)[8]) {
+  bf16x8 r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = (__bf16)v[i];
+  return r;
+}
+
+__device__ __forceinline__ float softplus(float z) {
+  return z > 20.0f ? z : log1pf(expf(z));
+}
+
+// x_hat of a bin midpoint: x / scale, optionally contracted into the unit ball
+__device__ __forceinline__ void encode_point(const FwdArgs& a, int64_t p, float (&y)[3]) {
+  const int64_t r = p / a.n_bins, j = p - r * a.n_bins;
+  const float* e = a.edges + r * (a.n_bins + 1) + j;
+  const float tm = 0.5f * (e[0] + e[1]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) y[c] = (a.ro[3 * r + c] + tm * a.rd[3 * r + c]) / a.scale;
+  if (a.contract) {
+    const float n = sqrtf(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    const float f = n <= 1.0f ? 0.5f : 0.5f * (2.0f - 1.0f / n) / n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c] *= f;
+  }
+}
+
+// Lane group g's 16 feature slots of a point, as the two K-steps of layer 1.
+__device__ __forceinline__ void features(float xa, bool in_range, bf16x8& b0, bf16x8& b1) {
+  float f[16];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    // sin(2^k pi x) = sin(2 pi * 2^(k-1) x); cos adds a quarter turn
+    const float rev = xa * (float)(1 << (q / 2)) * 0.5f + ((q & 1) ? 0.25f : 0.0f);
+    f[q] = __builtin_amdgcn_sinf(rev);
+  }
+  f[12] = xa;
+  f[13] = f[14] = f[15] = 0.0f;
+  if (!in_range) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) f[q] = 0.0f;
+  }
+  float lo[8], hi[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    lo[i] = f[i];
+    hi[i] = f[8 + i];
+  }
+  b0 = pack8(lo);
+  b1 = pack8(hi);
+}
+
+template <int H, int NT>
+__global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
+  constexpr int MT = H / 16, KS = H / 32;
+  const PackOffsets ko(H);
+  const ParamOffsets po(H);
+  __shared__ bf16x8 sA1[MT * 2 * 64];
+  __shared__ bf16x8 sA2[MT * KS * 64];
+  __shared__ float sb1[H], sb2[H], sw3[H];
+  // weights to LDS once per block
+  {
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(a.packed);
+    for (int i = threadIdx.x; i < MT * 2 * 64; i += blockDim.x) sA1[i] = src[i];
+    const bf16x8* src2 = reinterpret_cast<const bf16x8*>(a.packed + ko.A2);
+    for (int i = threadIdx.x; i < MT * KS * 64; i += blockDim.x) sA2[i] = src2[i];
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+      sb1[i] = a.params[po.b1 + i];
+      sb2[i] = a.params[po.b2 + i];
+      sw3[i] = (float)a.packed[ko.w3 + i];
+    }
+    __syncthreads();
+  }
+  const float b3 = a.params[po.b3];
+  const int ln = lane(), g = ln >> 4, col = ln & 15;
+  const int64_t n_points = (int64_t)a.n_rays * a.n_bins;
+  const int64_t n_tiles = (n_points + 15) / 16;
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t t0 = wave * NT; t0 < n_tiles; t0 += n_waves * NT) {
+    bf16x8 B1[NT][2];
+    bool valid[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int64_t p = (t0 + t) * 16 + col;
+      valid[t] = p < n_points;
+      float y[3] = {0.0f, 0.0f, 0.0f};
+      if (valid[t]) encode_point(a, p, y);
+      const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
+      features(xa, g < 3, B1[t][0], B1[t][1]);
+    }
+    // layer 1
+    f32x4 h1[NT][MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const bf16x8 w0 = sA1[(m * 2 + 0) * 64 + ln], w1 = sA1[(m * 2 + 1) * 64 + ln];
+      const f32x4 bias = {sb1[16 * m + 4 * g], sb1[16 * m + 4 * g + 1], sb1[16 * m + 4 * g + 2],
+                          sb1[16 * m + 4 * g + 3]};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, B1[t][0], bias, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, B1[t][1], c, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = fmaxf(c[i], 0.0f);
+        h1[t][m] = c;
+      }
+    }
+    // layer 2: B operand of K-step s = fragments 2s and 2s+1 of layer 1
+    bf16x8 B2[NT][KS];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const float v[8] = {h1[t][2 * s][0], h1[t][2 * s][1], h1[t][2 * s][2], h1[t][2 * s][3],
+                            h1[t][2 * s + 1][0], h1[t][2 * s + 1][1], h1[t][2 * s + 1][2],
+                            h1[t][2 * s + 1][3]};
+        B2[t][s] = pack8(v);
+      }
+    float z[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) z[t] = 0.0f;
+    // not unrolled: keeps one row of W2 tiles in registers at a time
+#pragma unroll 1
+    for (int m = 0; m < MT; ++m) {
+      const f32x4 bias = {sb2[16 * m + 4 * g], sb2[16 * m + 4 * g + 1], sb2[16 * m + 4 * g + 2],
+                          sb2[16 * m + 4 * g + 3]};
+      f32x4 c[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) c[t] = bias;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const bf16x8 w = sA2[(m * KS + s) * 64 + ln];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, B2[t][s], c[t], 0, 0, 0);
+      }
+      // layer 3 partial dot: relu, round to bf16, times bf16 w3
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float h2 = (float)(__bf16)fmaxf(c[t][i], 0.0f);
+          z[t] = fmaf(h2, sw3[16 * m + 4 * g + i], z[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      float zz = z[t];
+      zz += __shfl_xor(zz, 16, kWave);
+      zz += __shfl_xor(zz, 32, kWave);
+      const int64_t p = (t0 + t) * 16 + col;
+      if (g == 0 && valid[t]) a.sigma[p] = softplus(zz + b3);
+    }
+  }
+}
+
+txs_status check_mlp(const txs_mlp* m) {
+  TXS_REQUIRE(m, "txs_mlp: null descriptor");
+  TXS_REQUIRE(m->hidden == 64 || m->hidden == 128, "txs_mlp: hidden must be 64 or 128, got %d",
+              m->hidden);
+  TXS_REQUIRE(m->packed && m->params, "txs_mlp: null packed weights or params");
+  TXS_REQUIRE(std::isfinite(m->scale) && m->scale > 0.0f, "txs_mlp: scale must be > 0");
+  return TXS_OK;
+}
+
+}  // namespace
+}  // namespace txs
+
+extern "C" size_t txs_mlp_param_count(int32_t hidden) {
+  return (size_t)txs::ParamOffsets(hidden).total;
+}
+
+extern "C" size_t txs_mlp_packed_bytes(int32_t hidden) {
+  return (size_t)txs::PackOffsets(hidden).total * 2;
+}
+
+extern "C" txs_status txs_mlp_pack(const float* params, int32_t hidden, void* packed,
+                                   void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(hidden == 64 || hidden == 128, "txs_mlp_pack: hidden must be 64 or 128");
+  TXS_REQUIRE(params && packed, "txs_mlp_pack: null pointer");
+  const int64_t n = PackOffsets(hidden).total;
+  hipLaunchKernelGGL(pack_kernel, dim3(grid_1d(n, 256)), dim3(256), 0, as_stream(stream), params,
+                     (int)hidden, static_cast<__bf16*>(packed));
+  return launch_status("txs_mlp_pack");
+}
+
+extern "C" txs_status txs_prop_mlp_fwd(const txs_mlp* mlp, const float* rays_o,
+                                       const float* rays_d, int32_t n_rays, int32_t n_bins,
+                                       const float* edges, float* sigma, void* stream) {
+  using namespace txs;
+  clear_error();
+  if (txs_status s = check_mlp(mlp)) return s;
+  TXS_REQUIRE(n_rays >= 0 && n_bins >= 1, "txs_prop_mlp_fwd: bad size");
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(rays_o && rays_d && edges && sigma, "txs_prop_mlp_fwd: null array");
+  FwdArgs a{static_cast<const __bf16*>(mlp->packed), mlp->params, mlp->scale, mlp->contract,
+            rays_o, rays_d, n_rays, n_bins, edges, sigma};
+  const int64_t n_tiles = ((int64_t)n_rays * n_bins + 15) / 16;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  if (mlp->hidden == 64) {
+    constexpr int NT = 4;
+    const int64_t blocks = std::min<int64_t>((n_tiles + 4 * NT - 1) / (4 * NT), (int64_t)cus * 8);
+    hipLaunchKernelGGL((mlp_fwd_kernel<64, NT>), dim3((unsigned)blocks), dim3(256), 0,
+                       as_stream(stream), a);
+  } else {
+    constexpr int NT = 2;
+    const int64_t blocks = std::min<int64_t>((n_tiles + 4 * NT - 1) / (4 * NT), (int64_t)cus * 8);
+    hipLaunchKernelGGL((mlp_fwd_kernel<128, NT>), dim3((unsigned)blocks), dim3(256), 0,
+                       as_stream(stream), a);
+  }
+  return launch_status("txs_prop_mlp_fwd");
+}

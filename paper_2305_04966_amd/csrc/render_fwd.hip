@@ -41,7 +41,6 @@ extern "C" txs_status txs_render_fwd(const int32_t* packed_info, int32_t fixed_c
     return s;
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(out_rgb && out_opacity && out_depth, "txs_render_fwd: null output");
-  TXS_REQUIRE(n_samples == 0 || rgb, "txs_render_fwd: null rgb");
   Args a{};
   a.info = packed_info;
   a.fixed = fixed_count;

@@ -78,7 +78,14 @@ __device__ FwdCarry fwd_window(const Args& a, WaveLds& L, int32_t r0, int64_t p,
   float wv[K];
   bool own[K];
   float c[K][3];
-  if (kMode == kFwd) load_rgb(a.rgb, pos0, lim, c);
+  if (kMode == kFwd) {
+    if (a.rgb) {
+      load_rgb(a.rgb, pos0, lim, c);
+    } else {  // colourless: weights, opacity and depth only
+#pragma unroll
+      for (int j = 0; j < K; ++j) c[j][0] = c[j][1] = c[j][2] = 0.0f;
+    }
+  }
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     if (mk[j] != 0) {

@@ -171,7 +171,7 @@ def render_fwd(packed_info, t0, t1, sigma, rgb, *, n_rays=None, fixed_count=None
     s = t0.shape[0]
     for name, t in (("t0", t0), ("t1", t1), ("sigma", sigma)):
         _need(t, name, torch.float32, (s,))
-    _need(rgb, "rgb", torch.float32, (s, 3))
+    _opt(rgb, "rgb", torch.float32, (s, 3))  # None: weights / opacity / depth only
     _opt(bg, "bg", torch.float32, (n, 3))
     dev = t0.device
     out_rgb = torch.empty((n, 3), dtype=torch.float32, device=dev)
@@ -263,3 +263,79 @@ def blob_field(params, n_blobs, rays_o, rays_d, t0, t1, ray_id=None, fixed_count
                                 _ptr(t1), _ptr(ray_id), int(fixed_count), s, _ptr(sigma),
                                 _ptr(rgb), _stream()), "txs_blob_field")
     return sigma, rgb
+
+
+# ---------------------------------------------------------------- proposal MLP
+@dataclass
+class MlpSpec:
+    """Proposal network: fp32 parameter vector + its packed bf16 operand tiles."""
+    params: torch.Tensor  # float32 [txs_mlp_param_count(hidden)]
+    hidden: int
+    scale: float = 1.5
+    contract: bool = False
+    packed: torch.Tensor = None  # uint8 [txs_mlp_packed_bytes(hidden)]
+
+    def repack(self):
+        """Refresh the bf16 operand tiles from the fp32 parameters (after an update)."""
+        L = load()
+        n = int(L.txs_mlp_param_count(self.hidden))
+        _need(self.params, "mlp.params", torch.float32, (n,))
+        nbytes = int(L.txs_mlp_packed_bytes(self.hidden))
+        if self.packed is None or self.packed.numel() != nbytes:
+            self.packed = torch.empty(nbytes, dtype=torch.uint8, device=self.params.device)
+        check(L.txs_mlp_pack(_ptr(self.params), self.hidden, _ptr(self.packed), _stream()),
+              "txs_mlp_pack")
+        return self
+
+    def struct(self):
+        from ._lib import Mlp
+        if self.packed is None:
+            self.repack()
+        m = Mlp()
+        m.packed, m.params = self.packed.data_ptr(), self.params.data_ptr()
+        m.hidden, m.scale, m.contract = self.hidden, float(self.scale), int(self.contract)
+        return m
+
+
+def mlp_param_count(hidden):
+    return int(load().txs_mlp_param_count(hidden))
+
+
+def hist_loss(packed_info, t0, t1, w, edges, prop_w, eps=1e-7, want_grad=True):
+    """Proposal loss per ray and d(mean loss)/d prop_w ([N, n_bins] or None)."""
+    n = packed_info.shape[0]
+    s = t0.shape[0]
+    _need(packed_info, "packed_info", torch.int32, (n, 2))
+    for name, t in (("t0", t0), ("t1", t1), ("w", w)):
+        _need(t, name, torch.float32, (s,))
+    nb1 = edges.shape[1]
+    _need(edges, "edges", torch.float32, (n, nb1))
+    _need(prop_w, "prop_w", torch.float32, (n, nb1 - 1))
+    loss = torch.empty(n, dtype=torch.float32, device=edges.device)
+    d = torch.empty((n, nb1 - 1), dtype=torch.float32, device=edges.device) if want_grad else None
+    check(load().txs_hist_loss(_ptr(packed_info), n, s, _ptr(t0), _ptr(t1), _ptr(w), nb1 - 1,
+                               _ptr(edges), _ptr(prop_w), float(eps), _ptr(loss), _ptr(d),
+                               _stream()), "txs_hist_loss")
+    return loss, d
+
+
+def adam_step(params, m, v, grad, lr, step, beta1=0.9, beta2=0.99, eps=1e-15):
+    """In-place Adam step on fp32 parameter / moment tensors."""
+    n = params.numel()
+    for name, t in (("params", params), ("m", m), ("v", v), ("grad", grad)):
+        _need(t, name, torch.float32, (n,))
+    check(load().txs_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), n, float(lr),
+                               float(beta1), float(beta2), float(eps), int(step), _stream()),
+          "txs_adam_step")
+
+
+def prop_mlp_fwd(mlp: MlpSpec, rays_o, rays_d, edges):
+    """Proposal density at bin midpoints -> float32 [N, n_bins]."""
+    n = _rays(rays_o, rays_d)
+    nb1 = edges.shape[1]
+    _need(edges, "edges", torch.float32, (n, nb1))
+    out = torch.empty((n, nb1 - 1), dtype=torch.float32, device=edges.device)
+    m = mlp.struct()
+    check(load().txs_prop_mlp_fwd(C.byref(m), _ptr(rays_o), _ptr(rays_d), n, nb1 - 1,
+                                  _ptr(edges), _ptr(out), _stream()), "txs_prop_mlp_fwd")
+    return out

@@ -230,6 +230,21 @@ def uniform_jitter(shape, seed: int = SEED_JITTER) -> np.ndarray:
     return rng(seed).random(shape).astype(np.float32)
 
 
+def mlp_init(hidden: int, seed: int = SEED_MLP) -> np.ndarray:
+    """Seeded He-uniform initial parameters of the proposal network.
+
+    Layout W1 [H,39], b1 [H], W2 [H,H], b2 [H], w3 [H], b3 (float32); weight
+    matrices ~ U(-sqrt(6/fan_in), sqrt(6/fan_in)), biases zero.
+    """
+    g = rng(seed)
+    H = hidden
+    W1 = g.uniform(-1, 1, (H, 39)) * np.sqrt(6.0 / 39)
+    W2 = g.uniform(-1, 1, (H, H)) * np.sqrt(6.0 / H)
+    w3 = g.uniform(-1, 1, H) * np.sqrt(6.0 / H)
+    z = np.zeros
+    return np.concatenate([W1.ravel(), z(H), W2.ravel(), z(H), w3, z(1)]).astype(np.float32)
+
+
 # ----------------------------------------------------------------------------
 # workload configurations
 # ----------------------------------------------------------------------------

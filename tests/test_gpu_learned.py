@@ -1,0 +1,158 @@
+"""GPU parity of the learned estimator's kernels against the oracle.
+
+The proposal MLP runs on bf16 matrix cores with fp32 accumulation, so it is
+compared with the oracle's bf16-emulating reference (same rounding points,
+fp64 sums): the accumulation order may flip one bf16 rounding, so the bar is
+2 bf16 ulps of the emulated value for at least 99.9% of points and 16 ulps for
+all of them.  Pinned special cases (zero network, one-feature networks) must
+match exactly what the encoding defines.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+from gpu_util import dev, grid_spec, host
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_ulp(x):
+    x = np.abs(np.asarray(x, np.float64))
+    e = np.floor(np.log2(np.maximum(x, 2.0 ** -126)))
+    return 2.0 ** (e - 7)
+
+
+def mlp_spec(txs, params, H, scale=1.5, contract=False):
+    return txs.MlpSpec(dev(params), H, scale, contract).repack()
+
+
+def rays_and_edges(txs, n, n_bins=128, seed=2, radius=3.0):
+    o, d = scenes.sphere_rays(n, radius=radius, seed=seed)
+    w = scenes.tiny()
+    g = grid_spec(txs, w.bits, 64)
+    edges = txs.uniform_bins(g, dev(o), dev(d), n_bins)
+    return o, d, edges
+
+
+def assert_bf16_close(got, ref, name):
+    ulps = np.abs(got.astype(np.float64) - ref) / bf16_ulp(ref)
+    frac2 = np.mean(ulps <= 2.0)
+    assert frac2 >= 0.999, (name, frac2, np.max(ulps))
+    assert np.max(ulps) <= 16.0, (name, np.max(ulps))
+
+
+@pytest.mark.parametrize("H", [64, 128])
+def test_mlp_zero_network(gpu_lib, H):
+    p = np.zeros(oracle.mlp_param_count(H), np.float32)
+    p[-1] = 0.75
+    o, d, edges = rays_and_edges(gpu_lib, 300)
+    s = host(gpu_lib.prop_mlp_fwd(mlp_spec(gpu_lib, p, H), dev(o), dev(d), edges))
+    np.testing.assert_allclose(s, math.log1p(math.exp(0.75)), rtol=2e-7)
+
+
+@pytest.mark.parametrize("H", [64, 128])
+def test_mlp_one_feature_networks(gpu_lib, H):
+    # each of the 39 features routed alone to the output: pins the packing of W1
+    # into operand tiles and every feature of the encoding
+    o, d, edges = rays_and_edges(gpu_lib, 64, n_bins=32)
+    x = oracle.bin_midpoints(o, d, host(edges))
+    for f in range(39):
+        p = np.zeros(oracle.mlp_param_count(H), np.float32)
+        W1 = p[:39 * H].reshape(H, 39)
+        W1[3, f] = 1.0
+        W2 = p[40 * H:40 * H + H * H].reshape(H, H)
+        W2[5, 3] = 1.0
+        p[41 * H + H * H + 5] = 1.0  # w3
+        got = host(gpu_lib.prop_mlp_fwd(mlp_spec(gpu_lib, p, H), dev(o), dev(d), edges))
+        ref = oracle.mlp_fwd(x, p, H, emulate_bf16=True).reshape(got.shape)
+        assert_bf16_close(got, ref, f"feature {f}")
+
+
+@pytest.mark.parametrize("H,contract", [(64, False), (128, False), (128, True)])
+def test_mlp_random_network(gpu_lib, H, contract):
+    params = scenes.mlp_init(H)
+    g = scenes.rng(7)
+    params[39 * H:40 * H] = g.normal(0, 0.3, H)  # nonzero biases
+    params[40 * H + H * H:41 * H + H * H] = g.normal(0, 0.3, H)
+    params[-1] = -0.5
+    radius = 6.0 if contract else 3.0
+    o, d, edges = rays_and_edges(gpu_lib, 2000, radius=radius)
+    got = host(gpu_lib.prop_mlp_fwd(mlp_spec(gpu_lib, params, H, contract=contract), dev(o),
+                                    dev(d), edges))
+    x = oracle.bin_midpoints(o, d, host(edges))
+    ref = oracle.mlp_fwd(x, params, H, contract=contract, emulate_bf16=True).reshape(got.shape)
+    assert_bf16_close(got, ref, f"H={H}")
+    # and the bf16 network is close to the fp64 one (quantisation, not a bug)
+    ref64 = oracle.mlp_fwd(x, params, H, contract=contract).reshape(got.shape)
+    assert np.median(np.abs(got - ref64) / np.maximum(ref64, 1e-3)) < 0.02
+
+
+# ----------------------------------------------------------------------------
+# histogram loss, weights-only render, Adam
+# ----------------------------------------------------------------------------
+def target_histograms(n_rays, seed):
+    """Sorted disjoint target intervals with weights (a stand-in grid render)."""
+    g = scenes.rng(seed)
+    counts = g.integers(0, 40, n_rays).astype(np.int32)
+    info, S = oracle.exclusive_scan(counts)
+    t0 = np.zeros(S, np.float32)
+    t1 = np.zeros(S, np.float32)
+    for r in range(n_rays):
+        s, c = info[r]
+        cuts = np.sort(g.uniform(1.5, 4.5, 2 * c))
+        t0[s:s + c], t1[s:s + c] = cuts[0::2], cuts[1::2]
+    w = (g.exponential(0.05, S) * (g.random(S) < 0.8)).astype(np.float32)
+    return info, t0, t1, w
+
+
+@pytest.mark.parametrize("nb", [16, 128])
+def test_hist_loss(gpu_lib, nb):
+    n = 1500
+    info, t0, t1, w = target_histograms(n, 3 + nb)
+    g = scenes.rng(30)
+    edges = (1.5 + np.concatenate([np.zeros((n, 1)), np.cumsum(g.uniform(0, 1, (n, nb)), 1)],
+                                  1) * (3.0 / nb)).astype(np.float32)
+    pw = (g.exponential(1.0, (n, nb)) / nb * g.choice([0.2, 1.0], (n, 1))).astype(np.float32)
+    loss, d = gpu_lib.hist_loss(dev(info), dev(t0), dev(t1), dev(w), dev(edges), dev(pw))
+    rl, rd = oracle.hist_loss(info, t0, t1, w, edges, pw)
+    # fp32 sums of at most a few hundred terms
+    np.testing.assert_allclose(host(loss), rl, rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(host(d), rd, rtol=2e-5, atol=1e-9)
+    assert (rl > 0).mean() > 0.3
+
+
+def test_weights_only_render(gpu_lib):
+    n, F = 500, 128
+    g = scenes.rng(31)
+    e = np.sort(g.uniform(1.0, 4.0, (n, F + 1)), 1).astype(np.float32)
+    t0, t1 = e[:, :-1].reshape(-1).copy(), e[:, 1:].reshape(-1).copy()
+    sig = g.exponential(2.0, n * F).astype(np.float32)
+    out = gpu_lib.render_fwd(None, dev(t0), dev(t1), dev(sig), None, n_rays=n, fixed_count=F,
+                             want_weights=True)
+    info = np.stack([np.arange(n) * F, np.full(n, F)], 1).astype(np.int32)
+    ref = oracle.render_fwd(info, t0, t1, sig, np.zeros((n * F, 3), np.float32),
+                            want_weights=True)
+    np.testing.assert_allclose(host(out[3]), ref["weights"], rtol=1e-5,
+                               atol=1e-8 * ref["weights"].max())
+    np.testing.assert_allclose(host(out[1]), ref["opacity"], rtol=1e-5)
+    assert np.all(host(out[0]) == 0.0)
+
+
+def test_adam_step(gpu_lib):
+    g = scenes.rng(32)
+    n = 5000
+    p = g.standard_normal(n).astype(np.float32)
+    m = np.zeros(n, np.float32)
+    v = np.zeros(n, np.float32)
+    P, M, V = dev(p), dev(m), dev(v)
+    rp, rm, rv = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for step in range(1, 6):
+        grad = g.standard_normal(n).astype(np.float32)
+        gpu_lib.adam_step(P, M, V, dev(grad), lr=1e-2, step=step)
+        rp, rm, rv = oracle.adam(rp, rm, rv, grad, lr=1e-2, step=step)
+    np.testing.assert_allclose(host(P), rp, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(host(M), rm, rtol=1e-5, atol=1e-7)
