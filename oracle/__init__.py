@@ -262,15 +262,20 @@ def mlp_fwd(x, params, H, scale=1.5, contract=False, emulate_bf16=False, want_z=
     return (s, z) if want_z else s
 
 
-def mlp_bwd(x, params, H, d_sigma, scale=1.5, contract=False, emulate_bf16=False):
-    """Gradient of sum_i d_sigma_i sigma(x_i) w.r.t. the parameter vector (FP64)."""
+def mlp_bwd(x, params, H, d_sigma, scale=1.5, contract=False, emulate_bf16=False,
+            want_abs=False):
+    """Gradient of sum_i d_sigma_i sigma(x_i) w.r.t. the parameter vector (FP64).
+
+    With want_abs, returns (grad, grad_abs): grad_abs sums |term| instead of term.
+    """
     x = _f64(x).reshape(-1, 3)
     p = _f32(params)
     g = np.zeros(mlp_param_count(H), np.float64)
+    ga = np.zeros_like(g) if want_abs else None
     lib().oracle_mlp_bwd(C.c_int64(x.shape[0]), _p(x), _p(p), C.c_int32(H), C.c_double(scale),
                          C.c_int32(int(contract)), C.c_int32(int(emulate_bf16)),
-                         _p(_f64(d_sigma)), _p(g))
-    return g
+                         _p(_f64(d_sigma)), _p(g), _p(ga))
+    return (g, ga) if want_abs else g
 
 
 def hist_loss(packed_info, t0, t1, w, edges, wp, eps=1e-7, want_grad=True):

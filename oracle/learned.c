@@ -114,19 +114,21 @@ EXPORT void oracle_mlp_fwd(int64_t n, const double* x, const float* params, int3
 }
 
 /* Gradient of sum_i d_sigma[i] * sigma(x_i) w.r.t. the parameter vector
- * (same layout); binary64 reverse mode, per point then summed in point order. */
+ * (same layout); binary64 reverse mode, per point then summed in point order.
+ * With emulate set, the adjoint operands of the two hidden layers
+ * (d2 = dL/da2 and d1 = dL/da1) are rounded to bfloat16 as well, since a
+ * matrix-core backward multiplies them in bfloat16; the bias gradients sum the
+ * rounded values.  Optional grad_abs receives the same sums taken over the
+ * absolute values of every term (the scale against which a reordered fp32
+ * summation is judged). */
 EXPORT void oracle_mlp_bwd(int64_t n, const double* x, const float* params, int32_t H,
                            double scale, int32_t contract, int32_t emulate, const double* d_sigma,
-                           double* grad) {
+                           double* grad, double* grad_abs) {
   const mlp_view m = view(params, H);
   const int64_t P = (int64_t)H * H + 42 * H + 1;
-  memset(grad, 0, (size_t)P * sizeof(double));
-  double* gW1 = grad;
-  double* gb1 = gW1 + H * NF;
-  double* gW2 = gb1 + H;
-  double* gb2 = gW2 + H * H;
-  double* gw3 = gb2 + H;
-  double* gb3 = gw3 + H;
+  double* out[2] = {grad, grad_abs};
+  for (int k = 0; k < 2; ++k)
+    if (out[k]) memset(out[k], 0, (size_t)P * sizeof(double));
   for (int64_t i = 0; i < n; ++i) {
     double g[NF], a1[512], h1[512], a2[512], h2[512], d2[512], d1[512];
     encode(x + 3 * i, scale, contract, g, emulate);
@@ -147,23 +149,37 @@ EXPORT void oracle_mlp_bwd(int64_t n, const double* x, const float* params, int3
     double z = m.b3[0];
     for (int f = 0; f < H; ++f) z += wt(m.w3[f], emulate) * h2[f];
     const double dz = d_sigma[i] * sigm(z);
-    gb3[0] += dz;
     for (int f = 0; f < H; ++f) {
-      gw3[f] += dz * h2[f];
       d2[f] = a2[f] > 0.0 ? dz * wt(m.w3[f], emulate) : 0.0;
-    }
-    for (int o = 0; o < H; ++o) {
-      gb2[o] += d2[o];
-      for (int f = 0; f < H; ++f) gW2[o * H + f] += d2[o] * h1[f];
+      if (emulate) d2[f] = bf16(d2[f]);
     }
     for (int f = 0; f < H; ++f) {
       double acc = 0.0;
       for (int o = 0; o < H; ++o) acc += wt(m.W2[o * H + f], emulate) * d2[o];
       d1[f] = a1[f] > 0.0 ? acc : 0.0;
+      if (emulate) d1[f] = bf16(d1[f]);
     }
-    for (int o = 0; o < H; ++o) {
-      gb1[o] += d1[o];
-      for (int f = 0; f < NF; ++f) gW1[o * NF + f] += d1[o] * g[f];
+    for (int k = 0; k < 2; ++k) {
+      if (!out[k]) continue;
+      /* k = 0: the gradient; k = 1: the same sums of |term| */
+#define T(v) (k ? fabs(v) : (v))
+      double* gW1 = out[k];
+      double* gb1 = gW1 + H * NF;
+      double* gW2 = gb1 + H;
+      double* gb2 = gW2 + H * H;
+      double* gw3 = gb2 + H;
+      double* gb3 = gw3 + H;
+      gb3[0] += T(dz);
+      for (int f = 0; f < H; ++f) gw3[f] += T(dz * h2[f]);
+      for (int o = 0; o < H; ++o) {
+        gb2[o] += T(d2[o]);
+        for (int f = 0; f < H; ++f) gW2[o * H + f] += T(d2[o] * h1[f]);
+      }
+      for (int o = 0; o < H; ++o) {
+        gb1[o] += T(d1[o]);
+        for (int f = 0; f < NF; ++f) gW1[o * NF + f] += T(d1[o] * g[f]);
+      }
+#undef T
     }
   }
 }

@@ -108,6 +108,68 @@ def test_mlp_gradient_matches_finite_differences():
         assert grad[i] == pytest.approx(fd, rel=2e-4, abs=2e-6), i
 
 
+def _bf16_rne(v):
+    # independent bfloat16 round-to-nearest-even through the float32 bit pattern
+    u = np.array([v], np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return float(u.astype(np.uint32).view(np.float32)[0])
+
+
+def test_emulated_adjoint_rounds_hidden_adjoints():
+    # one point, one active path: x_hat_0 = 1 -> a1 = 1 -> a2 = 1 -> z = w3 + b3.
+    # d2 = dz w3 and d1 = W2 d2 are rounded to bfloat16 in the emulated adjoint;
+    # the bias gradients expose them directly.
+    p = zero_params(H)
+    W1, b1, W2, b2, w3, b3 = views(p, H)
+    W1[0, 0] = 1.0
+    W2[0, 0] = 1.5
+    w3[0] = 0.75
+    b2[0] = -0.5
+    x = np.array([[1.5, 0.0, 0.0]])
+    ds = np.array([0.3])
+    z = 0.75 * (1.5 * 1.0 - 0.5)
+    dz = 0.3 / (1.0 + math.exp(-z))
+    g = oracle.mlp_bwd(x, p, H, ds, scale=1.5, emulate_bf16=True)
+    gb1 = g[39 * H:40 * H]
+    gb2 = g[40 * H + H * H:41 * H + H * H]
+    d2 = _bf16_rne(dz * 0.75)
+    assert d2 != dz * 0.75  # the case does exercise a rounding
+    assert gb2[0] == d2
+    assert gb1[0] == _bf16_rne(1.5 * d2)
+    assert np.count_nonzero(gb2) == 1 and np.count_nonzero(gb1) == 1
+    # unrounded in the binary64 adjoint
+    g64 = oracle.mlp_bwd(x, p, H, ds, scale=1.5)
+    assert g64[40 * H + H * H] == pytest.approx(dz * 0.75, rel=1e-15)
+
+
+def test_adjoint_term_magnitudes():
+    # the same point with opposite upstream gradients: the gradient cancels to
+    # exactly zero while the magnitude doubles that of one point
+    g = scenes.rng(8)
+    p = (g.standard_normal(oracle.mlp_param_count(H)) * 0.3).astype(np.float32)
+    x1 = g.uniform(-1.4, 1.4, (1, 3))
+    one, one_abs = oracle.mlp_bwd(x1, p, H, [0.7], emulate_bf16=True, want_abs=True)
+    np.testing.assert_array_equal(one_abs, np.abs(one))
+    two, two_abs = oracle.mlp_bwd(np.concatenate([x1, x1]), p, H, [0.7, -0.7],
+                                  emulate_bf16=True, want_abs=True)
+    assert np.all(two == 0.0)
+    np.testing.assert_array_equal(two_abs, 2 * np.abs(one))
+    assert np.count_nonzero(one) > p.size // 4
+
+
+def test_emulated_adjoint_near_binary64():
+    # bfloat16 quantisation (weights, features, activations, adjoints, and the
+    # ReLU masks of units that sit near zero) moves the gradient by a few percent
+    g = scenes.rng(9)
+    p = scenes.mlp_init(H, seed=4)
+    x = g.uniform(-1.4, 1.4, (64, 3))
+    ds = g.standard_normal(64)
+    ge = oracle.mlp_bwd(x, p, H, ds, emulate_bf16=True)
+    g64 = oracle.mlp_bwd(x, p, H, ds)
+    assert np.linalg.norm(ge - g64) / np.linalg.norm(g64) < 0.1
+    assert np.dot(ge, g64) / (np.linalg.norm(ge) * np.linalg.norm(g64)) > 0.995
+
+
 def test_hist_loss_zero_when_proposal_bounds_target():
     # proposal = target on the same bins: every bound equals its weight
     n_bins = 8
