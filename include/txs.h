@@ -263,6 +263,24 @@ txs_status txs_prop_mlp_fwd(const txs_mlp* mlp, const float* rays_o, const float
                             void* stream);
 
 /*
+ * Adjoint of txs_prop_mlp_fwd for the estimator's update (Eq. 4): given
+ * d_sigma float [n_rays, n_bins] = dL/dsigma at the same points, writes
+ * grad float [txs_mlp_param_count(hidden)] = dL/dparams (overwritten, same
+ * layout as params).  The forward is recomputed, not stored.  Besides the
+ * forward's rounding points, dL/da2 and dL/da1 (the pre-activation adjoints of
+ * the two hidden layers) are rounded to bf16 before the matrix-core products
+ * that consume them; bias gradients sum those rounded values; all sums are
+ * fp32, reduced in a fixed order (bitwise deterministic).
+ * workspace: device, >= txs_mlp_bwd_workspace_size(hidden) bytes, caller-owned
+ * scratch (per-block partial gradients); EINVAL if smaller.
+ */
+size_t txs_mlp_bwd_workspace_size(int32_t hidden);
+txs_status txs_prop_mlp_bwd(const txs_mlp* mlp, const float* rays_o, const float* rays_d,
+                            int32_t n_rays, int32_t n_bins, const float* edges,
+                            const float* d_sigma, float* grad, void* workspace,
+                            size_t workspace_bytes, void* stream);
+
+/*
  * PDF-matching loss of the proposal estimator (its update by gradient descent,
  * Eq. 4 and Section 3.1 "PDF Approaches"; the proposal loss of Mip-NeRF 360,
  * on which the paper's proposal network rests).  Targets are the radiance

@@ -58,27 +58,36 @@ static void encode(const double x[3], double s, int contract, double* g, int emu
     for (int f = 0; f < NF; ++f) g[f] = bf16(g[f]);
 }
 
+/* The parameters as binary64, the weight matrices and w3 rounded to bf16 when
+ * emulating (biases stay exact: the matrix-core path adds them in fp32). */
 typedef struct {
-  const float* W1;
-  const float* b1;
-  const float* W2;
-  const float* b2;
-  const float* w3;
-  const float* b3;
+  double* buf;
+  const double* W1;
+  const double* b1;
+  const double* W2;
+  const double* b2;
+  const double* w3;
+  const double* b3;
 } mlp_view;
 
-static mlp_view view(const float* p, int H) {
+static mlp_view view(const float* p, int H, int emulate) {
+  const int64_t P = (int64_t)H * H + 42 * H + 1;
   mlp_view m;
-  m.W1 = p;
+  m.buf = (double*)malloc((size_t)P * sizeof(double));
+  for (int64_t i = 0; i < P; ++i) m.buf[i] = (double)p[i];
+  m.W1 = m.buf;
   m.b1 = m.W1 + H * NF;
   m.W2 = m.b1 + H;
   m.b2 = m.W2 + H * H;
   m.w3 = m.b2 + H;
   m.b3 = m.w3 + H;
+  if (emulate) {
+    for (int64_t i = 0; i < H * NF; ++i) m.buf[i] = bf16(m.buf[i]);
+    for (int64_t i = 0; i < (int64_t)H * H; ++i) m.buf[40 * H + i] = bf16(m.buf[40 * H + i]);
+    for (int64_t i = 0; i < H; ++i) m.buf[41 * H + (int64_t)H * H + i] = bf16(m.buf[41 * H + (int64_t)H * H + i]);
+  }
   return m;
 }
-
-static double wt(float v, int emulate) { return emulate ? bf16((double)v) : (double)v; }
 
 static double softplus(double z) { return z > 30.0 ? z + log1p(exp(-z)) : log1p(exp(z)); }
 static double sigm(double z) { return 1.0 / (1.0 + exp(-z)); }
@@ -87,30 +96,31 @@ static double sigm(double z) { return 1.0 / (1.0 + exp(-z)); }
 EXPORT void oracle_mlp_fwd(int64_t n, const double* x, const float* params, int32_t H,
                            double scale, int32_t contract, int32_t emulate, double* sigma,
                            double* zout) {
-  const mlp_view m = view(params, H);
+  const mlp_view m = view(params, H, emulate);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double g[NF], h1[512], h2[512];
     encode(x + 3 * i, scale, contract, g, emulate);
     for (int o = 0; o < H; ++o) {
       double acc = 0.0;
-      for (int f = 0; f < NF; ++f) acc += wt(m.W1[o * NF + f], emulate) * g[f];
+      for (int f = 0; f < NF; ++f) acc += m.W1[o * NF + f] * g[f];
       acc += m.b1[o];
       h1[o] = acc > 0.0 ? acc : 0.0;
       if (emulate) h1[o] = bf16(h1[o]);
     }
     for (int o = 0; o < H; ++o) {
       double acc = 0.0;
-      for (int f = 0; f < H; ++f) acc += wt(m.W2[o * H + f], emulate) * h1[f];
+      for (int f = 0; f < H; ++f) acc += m.W2[o * H + f] * h1[f];
       acc += m.b2[o];
       h2[o] = acc > 0.0 ? acc : 0.0;
       if (emulate) h2[o] = bf16(h2[o]);
     }
     double z = m.b3[0];
-    for (int f = 0; f < H; ++f) z += wt(m.w3[f], emulate) * h2[f];
+    for (int f = 0; f < H; ++f) z += m.w3[f] * h2[f];
     sigma[i] = softplus(z);
     if (zout) zout[i] = z;
   }
+  free(m.buf);
 }
 
 /* Gradient of sum_i d_sigma[i] * sigma(x_i) w.r.t. the parameter vector
@@ -124,7 +134,7 @@ EXPORT void oracle_mlp_fwd(int64_t n, const double* x, const float* params, int3
 EXPORT void oracle_mlp_bwd(int64_t n, const double* x, const float* params, int32_t H,
                            double scale, int32_t contract, int32_t emulate, const double* d_sigma,
                            double* grad, double* grad_abs) {
-  const mlp_view m = view(params, H);
+  const mlp_view m = view(params, H, emulate);
   const int64_t P = (int64_t)H * H + 42 * H + 1;
   double* out[2] = {grad, grad_abs};
   for (int k = 0; k < 2; ++k)
@@ -134,28 +144,28 @@ EXPORT void oracle_mlp_bwd(int64_t n, const double* x, const float* params, int3
     encode(x + 3 * i, scale, contract, g, emulate);
     for (int o = 0; o < H; ++o) {
       double acc = m.b1[o];
-      for (int f = 0; f < NF; ++f) acc += wt(m.W1[o * NF + f], emulate) * g[f];
+      for (int f = 0; f < NF; ++f) acc += m.W1[o * NF + f] * g[f];
       a1[o] = acc;
       h1[o] = acc > 0.0 ? acc : 0.0;
       if (emulate) h1[o] = bf16(h1[o]);
     }
     for (int o = 0; o < H; ++o) {
       double acc = m.b2[o];
-      for (int f = 0; f < H; ++f) acc += wt(m.W2[o * H + f], emulate) * h1[f];
+      for (int f = 0; f < H; ++f) acc += m.W2[o * H + f] * h1[f];
       a2[o] = acc;
       h2[o] = acc > 0.0 ? acc : 0.0;
       if (emulate) h2[o] = bf16(h2[o]);
     }
     double z = m.b3[0];
-    for (int f = 0; f < H; ++f) z += wt(m.w3[f], emulate) * h2[f];
+    for (int f = 0; f < H; ++f) z += m.w3[f] * h2[f];
     const double dz = d_sigma[i] * sigm(z);
     for (int f = 0; f < H; ++f) {
-      d2[f] = a2[f] > 0.0 ? dz * wt(m.w3[f], emulate) : 0.0;
+      d2[f] = a2[f] > 0.0 ? dz * m.w3[f] : 0.0;
       if (emulate) d2[f] = bf16(d2[f]);
     }
     for (int f = 0; f < H; ++f) {
       double acc = 0.0;
-      for (int o = 0; o < H; ++o) acc += wt(m.W2[o * H + f], emulate) * d2[o];
+      for (int o = 0; o < H; ++o) acc += m.W2[o * H + f] * d2[o];
       d1[f] = a1[f] > 0.0 ? acc : 0.0;
       if (emulate) d1[f] = bf16(d1[f]);
     }
@@ -182,6 +192,7 @@ EXPORT void oracle_mlp_bwd(int64_t n, const double* x, const float* params, int3
 #undef T
     }
   }
+  free(m.buf);
 }
 
 /*

@@ -58,6 +58,8 @@ SIGNATURES = {
     "txs_mlp_packed_bytes": (SZ, [I32]),
     "txs_mlp_pack": (I32, [P, I32, P, P]),
     "txs_prop_mlp_fwd": (I32, [MLP, P, P, I32, I32, P, P, P]),
+    "txs_mlp_bwd_workspace_size": (SZ, [I32]),
+    "txs_prop_mlp_bwd": (I32, [MLP, P, P, I32, I32, P, P, P, P, SZ, P]),
     "txs_hist_loss": (I32, [P, I32, I64, P, P, P, I32, P, P, F32, P, P, P]),
     "txs_adam_step": (I32, [P, P, P, P, I64, F32, F32, F32, F32, I32, P]),
 }

@@ -109,7 +109,8 @@ __device__ __forceinline__ float softplus(float z) {
 }
 
 // x_hat of a bin midpoint: x / scale, optionally contracted into the unit ball
-__device__ __forceinline__ void encode_point(const FwdArgs& a, int64_t p, float (&y)[3]) {
+template <class Args>
+__device__ __forceinline__ void encode_point(const Args& a, int64_t p, float (&y)[3]) {
   const int64_t r = p / a.n_bins, j = p - r * a.n_bins;
   const float* e = a.edges + r * (a.n_bins + 1) + j;
   const float tm = 0.5f * (e[0] + e[1]);
@@ -251,6 +252,273 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- adjoint
+// Gradient of sum_p d_sigma[p] sigma(x_p) w.r.t. the parameters.  Rounding
+// points: gamma, h1, h2, the weights, and the adjoints d2 = dL/da2 and
+// d1 = dL/da1 are bf16 (matrix-core operands); every sum is fp32.
+//
+// A block of 4 waves takes 64 points at a time, 16 per wave.  Phase A: each
+// wave recomputes its tile's forward in the transposed orientation (rows =
+// units, columns = points), forms dz, d2 = [a2 > 0] dz w3 and
+// d1 = [a1 > 0] W2^T d2 (W2^T from the A2t tiles, whose K order matches the
+// fragments of d2), and stores bf16 gamma, h1, d2, d1 into LDS as
+// [unit][point] rows.  Phase B: the weight gradients contract over points, so
+// each operand lane needs 8 consecutive points of one unit -- one 16-byte LDS
+// read from those rows; wave w owns rows [RO w, RO w + RO) of the 16-unit row
+// tiles of dW2 and dW1 and accumulates them over every batch in registers.
+// Per-block partial gradients go to a workspace; a second kernel sums the
+// blocks in a fixed order (deterministic, no float atomics).
+constexpr int kBwdBlocks = 256;  // one block per CU (LDS-limited)
+constexpr int kBwdBatch = 64;    // points per block iteration
+constexpr int kRowStride = kBwdBatch + 8;  // bf16 elements per staged row (144 B)
+
+struct BwdArgs {
+  const __bf16* packed;
+  const float* params;
+  float scale;
+  int32_t contract;
+  const float* ro;
+  const float* rd;
+  int32_t n_rays, n_bins;
+  const float* edges;
+  const float* d_sigma;
+  float* partial;  // [gridDim.x][param count]
+};
+
+__device__ __forceinline__ float bf16_round(float v) { return (float)(__bf16)v; }
+
+template <int H>
+__global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
+  constexpr int MT = H / 16, KS = H / 32, RO = MT / 4, RS = kRowStride;
+  const PackOffsets ko(H);
+  const ParamOffsets po(H);
+  __shared__ bf16x8 sA1[MT * 2 * 64];
+  __shared__ bf16x8 sA2[MT * KS * 64];
+  __shared__ bf16x8 sA2t[MT * KS * 64];
+  __shared__ float sb1[H], sb2[H], sw3[H];
+  __shared__ __attribute__((aligned(16))) __bf16 sH1[H * RS];
+  __shared__ __attribute__((aligned(16))) __bf16 sD2[H * RS];
+  __shared__ __attribute__((aligned(16))) __bf16 sD1[H * RS];
+  __shared__ __attribute__((aligned(16))) __bf16 sG[48 * RS];
+  __shared__ float sRed[4][H + 1];
+  {
+    const bf16x8* src = reinterpret_cast<const bf16x8*>(a.packed);
+    for (int i = threadIdx.x; i < MT * 2 * 64; i += blockDim.x) sA1[i] = src[i];
+    const bf16x8* src2 = reinterpret_cast<const bf16x8*>(a.packed + ko.A2);
+    for (int i = threadIdx.x; i < MT * KS * 64; i += blockDim.x) sA2[i] = src2[i];
+    const bf16x8* src3 = reinterpret_cast<const bf16x8*>(a.packed + ko.A2t);
+    for (int i = threadIdx.x; i < MT * KS * 64; i += blockDim.x) sA2t[i] = src3[i];
+    for (int i = threadIdx.x; i < H; i += blockDim.x) {
+      sb1[i] = a.params[po.b1 + i];
+      sb2[i] = a.params[po.b2 + i];
+      sw3[i] = (float)a.packed[ko.w3 + i];
+    }
+    __syncthreads();
+  }
+  const float b3 = a.params[po.b3];
+  const int ln = lane(), g = ln >> 4, col = ln & 15, w = threadIdx.x / kWave;
+  const int64_t n_points = (int64_t)a.n_rays * a.n_bins;
+  const int64_t n_batches = (n_points + kBwdBatch - 1) / kBwdBatch;
+
+  f32x4 acc2[RO][MT], acc1[RO][3];
+#pragma unroll
+  for (int r = 0; r < RO; ++r) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc2[r][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc1[r][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  float db2p[RO], db1p[RO];
+#pragma unroll
+  for (int r = 0; r < RO; ++r) db2p[r] = db1p[r] = 0.0f;
+  float acc3[MT][4];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc3[m][i] = 0.0f;
+  float acc_b3 = 0.0f;
+
+  for (int64_t batch = blockIdx.x; batch < n_batches; batch += gridDim.x) {
+    // ---------------- phase A: this wave's 16 points
+    const int pc = 16 * w + col;  // column of this lane's point in the staged rows
+    const int64_t p = batch * kBwdBatch + pc;
+    const bool valid = p < n_points;
+    bf16x8 B1[2];
+    {
+      float y[3] = {0.0f, 0.0f, 0.0f};
+      if (valid) encode_point(a, p, y);
+      const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
+      features(xa, g < 3 && valid, B1[0], B1[1]);
+      if (g < 3) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sG[(16 * g + q) * RS + pc] = B1[q / 8][q % 8];
+      }
+    }
+    bf16x8 B2[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      f32x4 hh[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int m = 2 * s + h;
+        const f32x4 bias = {sb1[16 * m + 4 * g], sb1[16 * m + 4 * g + 1], sb1[16 * m + 4 * g + 2],
+                            sb1[16 * m + 4 * g + 3]};
+        f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA1[(m * 2 + 0) * 64 + ln], B1[0], bias,
+                                                           0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA1[(m * 2 + 1) * 64 + ln], B1[1], c, 0, 0, 0);
+        hh[h] = c;
+      }
+      const float v[8] = {fmaxf(hh[0][0], 0.0f), fmaxf(hh[0][1], 0.0f), fmaxf(hh[0][2], 0.0f),
+                          fmaxf(hh[0][3], 0.0f), fmaxf(hh[1][0], 0.0f), fmaxf(hh[1][1], 0.0f),
+                          fmaxf(hh[1][2], 0.0f), fmaxf(hh[1][3], 0.0f)};
+      B2[s] = pack8(v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sH1[(16 * (2 * s + j / 4) + 4 * g + j % 4) * RS + pc] = B2[s][j];
+    }
+    // layer 2, all row tiles kept for the masks
+    f32x4 a2[MT];
+    float z = 0.0f;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      f32x4 c = {sb2[16 * m + 4 * g], sb2[16 * m + 4 * g + 1], sb2[16 * m + 4 * g + 2],
+                 sb2[16 * m + 4 * g + 3]};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA2[(m * KS + s) * 64 + ln], B2[s], c, 0, 0, 0);
+      a2[m] = c;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z = fmaf(bf16_round(fmaxf(c[i], 0.0f)), sw3[16 * m + 4 * g + i], z);
+    }
+    z += __shfl_xor(z, 16, kWave);
+    z += __shfl_xor(z, 32, kWave);
+    const float dz = valid ? a.d_sigma[p] / (1.0f + expf(-(z + b3))) : 0.0f;
+    if (g == 0) acc_b3 += dz;
+    bf16x8 D2B[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int m = 2 * s + j / 4, i = j % 4, u = 16 * m + 4 * g + i;
+        const float h2 = bf16_round(fmaxf(a2[m][i], 0.0f));
+        acc3[m][i] = fmaf(dz, h2, acc3[m][i]);
+        v[j] = a2[m][i] > 0.0f ? dz * sw3[u] : 0.0f;
+      }
+      D2B[s] = pack8(v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sD2[(16 * (2 * s + j / 4) + 4 * g + j % 4) * RS + pc] = D2B[s][j];
+    }
+    // d1 = [a1 > 0] W2^T d2, K over layer-2 units in the fragments' order
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA2t[(m * KS + s) * 64 + ln], D2B[s], c, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool on = (float)B2[m / 2][4 * (m % 2) + i] > 0.0f;
+        sD1[(16 * m + 4 * g + i) * RS + pc] = (__bf16)(on ? c[i] : 0.0f);
+      }
+    }
+    __syncthreads();
+    // ---------------- phase B: contract over the batch's 64 points
+#pragma unroll
+    for (int ks = 0; ks < kBwdBatch / 32; ++ks) {
+      const int kp = 32 * ks + 8 * g;
+      bf16x8 AD2[RO], AD1[RO];
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        const int row = 16 * (RO * w + r) + col;
+        AD2[r] = *reinterpret_cast<const bf16x8*>(&sD2[row * RS + kp]);
+        AD1[r] = *reinterpret_cast<const bf16x8*>(&sD1[row * RS + kp]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          db2p[r] += (float)AD2[r][j];
+          db1p[r] += (float)AD1[r][j];
+        }
+      }
+#pragma unroll
+      for (int mf = 0; mf < MT; ++mf) {
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sH1[(16 * mf + col) * RS + kp]);
+#pragma unroll
+        for (int r = 0; r < RO; ++r)
+          acc2[r][mf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AD2[r], bh, acc2[r][mf], 0, 0, 0);
+      }
+#pragma unroll
+      for (int gf = 0; gf < 3; ++gf) {
+        const bf16x8 bg = *reinterpret_cast<const bf16x8*>(&sG[(16 * gf + col) * RS + kp]);
+#pragma unroll
+        for (int r = 0; r < RO; ++r)
+          acc1[r][gf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AD1[r], bg, acc1[r][gf], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---------------- per-block partial gradients
+  const int64_t P = po.total;
+  float* out = a.partial + (int64_t)blockIdx.x * P;
+#pragma unroll
+  for (int r = 0; r < RO; ++r) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int o = 16 * (RO * w + r) + 4 * g + i;
+#pragma unroll
+      for (int mf = 0; mf < MT; ++mf) out[po.W2 + (int64_t)o * H + 16 * mf + col] = acc2[r][mf][i];
+#pragma unroll
+      for (int gf = 0; gf < 3; ++gf) {
+        const int f = feature_of(gf, col);
+        if (f >= 0) out[po.W1 + (int64_t)o * kNF + f] = acc1[r][gf][i];
+      }
+    }
+    float s2 = db2p[r], s1 = db1p[r];
+    s2 += __shfl_xor(s2, 16, kWave);
+    s2 += __shfl_xor(s2, 32, kWave);
+    s1 += __shfl_xor(s1, 16, kWave);
+    s1 += __shfl_xor(s1, 32, kWave);
+    if (g == 0) {
+      out[po.b2 + 16 * (RO * w + r) + col] = s2;
+      out[po.b1 + 16 * (RO * w + r) + col] = s1;
+    }
+  }
+  // dw3, db3: sum over the 16 point columns, then over the 4 waves in order
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = acc3[m][i];
+      v += __shfl_xor(v, 1, kWave);
+      v += __shfl_xor(v, 2, kWave);
+      v += __shfl_xor(v, 4, kWave);
+      v += __shfl_xor(v, 8, kWave);
+      if (col == 0) sRed[w][16 * m + 4 * g + i] = v;
+    }
+  {
+    float v = acc_b3;
+    v += __shfl_xor(v, 1, kWave);
+    v += __shfl_xor(v, 2, kWave);
+    v += __shfl_xor(v, 4, kWave);
+    v += __shfl_xor(v, 8, kWave);
+    if (ln == 0) sRed[w][H] = v;
+  }
+  __syncthreads();
+  for (int u = threadIdx.x; u <= H; u += blockDim.x) {
+    const float v = ((sRed[0][u] + sRed[1][u]) + sRed[2][u]) + sRed[3][u];
+    out[u < H ? po.w3 + u : po.b3] = v;
+  }
+}
+
+// grad[i] = sum over blocks of partial[b][i], blocks in index order
+__global__ void sum_partials_kernel(const float* __restrict__ partial, int n_blocks, int64_t P,
+                                    float* __restrict__ grad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  double s = 0.0;
+  for (int b = 0; b < n_blocks; ++b) s += (double)partial[(int64_t)b * P + i];
+  grad[i] = (float)s;
+}
+
 txs_status check_mlp(const txs_mlp* m) {
   TXS_REQUIRE(m, "txs_mlp: null descriptor");
   TXS_REQUIRE(m->hidden == 64 || m->hidden == 128, "txs_mlp: hidden must be 64 or 128, got %d",
@@ -313,4 +581,42 @@ extern "C" txs_status txs_prop_mlp_fwd(const txs_mlp* mlp, const float* rays_o,
                        as_stream(stream), a);
   }
   return launch_status("txs_prop_mlp_fwd");
+}
+
+extern "C" size_t txs_mlp_bwd_workspace_size(int32_t hidden) {
+  if (hidden != 64 && hidden != 128) return 0;
+  return (size_t)txs::kBwdBlocks * (size_t)txs::ParamOffsets(hidden).total * sizeof(float);
+}
+
+extern "C" txs_status txs_prop_mlp_bwd(const txs_mlp* mlp, const float* rays_o,
+                                       const float* rays_d, int32_t n_rays, int32_t n_bins,
+                                       const float* edges, const float* d_sigma, float* grad,
+                                       void* workspace, size_t workspace_bytes, void* stream) {
+  using namespace txs;
+  clear_error();
+  if (txs_status s = check_mlp(mlp)) return s;
+  TXS_REQUIRE(n_rays >= 0 && n_bins >= 1, "txs_prop_mlp_bwd: bad size");
+  TXS_REQUIRE(grad, "txs_prop_mlp_bwd: null grad");
+  const int H = mlp->hidden;
+  const int64_t P = ParamOffsets(H).total;
+  const int64_t n_points = (int64_t)n_rays * n_bins;
+  const int64_t n_batches = (n_points + kBwdBatch - 1) / kBwdBatch;
+  const int blocks = (int)std::min<int64_t>(n_batches, kBwdBlocks);
+  if (blocks > 0) {
+    TXS_REQUIRE(rays_o && rays_d && edges && d_sigma, "txs_prop_mlp_bwd: null array");
+    TXS_REQUIRE(workspace, "txs_prop_mlp_bwd: null workspace");
+    TXS_REQUIRE(workspace_bytes >= txs_mlp_bwd_workspace_size(H),
+                "txs_prop_mlp_bwd: workspace of %zu bytes, need %zu", workspace_bytes,
+                txs_mlp_bwd_workspace_size(H));
+    BwdArgs a{static_cast<const __bf16*>(mlp->packed), mlp->params, mlp->scale, mlp->contract,
+              rays_o, rays_d, n_rays, n_bins, edges, d_sigma, static_cast<float*>(workspace)};
+    if (H == 64)
+      hipLaunchKernelGGL(mlp_bwd_kernel<64>, dim3(blocks), dim3(256), 0, as_stream(stream), a);
+    else
+      hipLaunchKernelGGL(mlp_bwd_kernel<128>, dim3(blocks), dim3(256), 0, as_stream(stream), a);
+    if (txs_status s = launch_status("txs_prop_mlp_bwd")) return s;
+  }
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(grid_1d(P, 256)), dim3(256), 0, as_stream(stream),
+                     static_cast<const float*>(workspace), blocks, P, grad);
+  return launch_status("txs_prop_mlp_bwd");
 }

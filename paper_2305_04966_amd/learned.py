@@ -1,0 +1,125 @@
+"""Learned transmittance estimator: the proposal network and its update.
+
+Section 3.1 ("PDF Approaches"), Table 1 third row and Eq. 4: a small network
+predicts density along each ray; its rendering weights on uniform bins are
+fitted by gradient descent to the weights the radiance field renders (a
+PDF-matching loss), and sampling draws the final intervals from its
+transmittance by inverse CDF (Eq. 3).  One update step, all in the HIP
+library:
+
+    uniform bins (fixed per ray set) -> prop_mlp_fwd -> render_fwd (weights
+    only, dense bins) -> hist_loss -> weights_bwd -> prop_mlp_bwd -> adam_step
+    -> mlp_pack
+
+Targets come from the plain occupancy-grid renderer (march, filter, field,
+render with weights), computed by `grid_targets`.  Only argument plumbing
+lives here.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import torch
+
+from . import ops
+from .pipeline import Packed, march, filter_transmittance
+
+
+@dataclass
+class GridRender:
+    """Plain grid renderer output on a ray set: samples, weights, colours."""
+    samples: Packed
+    weights: torch.Tensor   # float32 [S]
+    rgb: torch.Tensor       # float32 [N, 3]
+    opacity: torch.Tensor   # float32 [N]
+
+
+def grid_render(grid: ops.GridSpec, rays_o, rays_d, field_params, n_blobs, *, dt0,
+                t_min=1e-4, near=0.0, far=float("inf")) -> GridRender:
+    """Occupancy-grid sampling + filter + field + render (no gradient)."""
+    p = march(grid, rays_o, rays_d, dt0=dt0, near=near, far=far)
+    sig, _ = ops.blob_field(field_params, n_blobs, rays_o, rays_d, p.t0, p.t1, p.ray_id,
+                            want_rgb=False)
+    q = filter_transmittance(p, sig, t_min)
+    sig, rgb = ops.blob_field(field_params, n_blobs, rays_o, rays_d, q.t0, q.t1, q.ray_id)
+    out = ops.render_fwd(q.packed_info, q.t0, q.t1, sig, rgb, want_weights=True)
+    return GridRender(q, out[3], out[0], out[1])
+
+
+def cosine_lr(step, total, lr0=1e-2, lr1=1e-4):
+    """Cosine decay from lr0 (step 1) to lr1 (step total)."""
+    if total <= 1:
+        return lr0
+    c = 0.5 * (1.0 + math.cos(math.pi * (step - 1) / (total - 1)))
+    return lr1 + (lr0 - lr1) * c
+
+
+@dataclass
+class ProposalEstimator:
+    """Proposal network with fp32 master weights, bf16 operand tiles and Adam state."""
+    params: torch.Tensor            # float32 [param count]
+    hidden: int
+    scale: float = 1.5
+    contract: bool = False
+    betas: tuple = (0.9, 0.99)
+    eps: float = 1e-15
+    step_count: int = 0
+    spec: Optional[ops.MlpSpec] = None
+    m: Optional[torch.Tensor] = None
+    v: Optional[torch.Tensor] = None
+    workspace: Optional[torch.Tensor] = None
+    _bins: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        self.spec = ops.MlpSpec(self.params, self.hidden, self.scale, self.contract).repack()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        nbytes = int(ops.load().txs_mlp_bwd_workspace_size(self.hidden))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.params.device)
+
+    # ------------------------------------------------------------ sampling
+    def density(self, rays_o, rays_d, edges):
+        """Proposal density at the bin midpoints -> float32 [N, n_bins]."""
+        return ops.prop_mlp_fwd(self.spec, rays_o, rays_d, edges)
+
+    def sample(self, rays_o, rays_d, edges, n_out, u=None):
+        """Inverse-CDF intervals from the proposal transmittance -> edges [N, n_out+1]."""
+        sig = self.density(rays_o, rays_d, edges)
+        return ops.resample(edges, sig, n_out, mode=ops.TXS_PDF_SIGMA, u=u)
+
+    # ------------------------------------------------------------ update
+    @staticmethod
+    def dense_intervals(edges):
+        """(t0, t1) [N*n_bins] of dense bins."""
+        return edges[:, :-1].contiguous().view(-1), edges[:, 1:].contiguous().view(-1)
+
+    def loss_and_grad(self, rays_o, rays_d, edges, target: GridRender, t0=None, t1=None):
+        """Mean PDF-matching loss and its gradient w.r.t. the parameters."""
+        n, nb = edges.shape[0], edges.shape[1] - 1
+        if t0 is None:
+            t0, t1 = self.dense_intervals(edges)
+        sig = self.density(rays_o, rays_d, edges).view(-1)
+        out = ops.render_fwd(None, t0, t1, sig, None, n_rays=n, fixed_count=nb,
+                             want_weights=True, want_optical_depth=True)
+        w_hat = out[3].view(n, nb)
+        q = target.samples
+        loss, d_prop = ops.hist_loss(q.packed_info, q.t0, q.t1, target.weights, edges, w_hat)
+        d_sig = ops.weights_bwd(None, t0, t1, sig, d_prop.view(-1), n_rays=n, fixed_count=nb,
+                                optical_depth=out[4])
+        grad = ops.prop_mlp_bwd(self.spec, rays_o, rays_d, edges, d_sig.view(n, nb),
+                                workspace=self.workspace)
+        return loss, grad
+
+    def apply(self, grad, lr):
+        """One Adam step on the fp32 master weights, then refresh the bf16 tiles."""
+        self.step_count += 1
+        ops.adam_step(self.params, self.m, self.v, grad, lr=lr, beta1=self.betas[0],
+                      beta2=self.betas[1], eps=self.eps, step=self.step_count)
+        self.spec.repack()
+
+    def train_step(self, rays_o, rays_d, edges, target: GridRender, lr, t0=None, t1=None):
+        loss, grad = self.loss_and_grad(rays_o, rays_d, edges, target, t0, t1)
+        self.apply(grad, lr)
+        return loss

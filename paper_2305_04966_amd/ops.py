@@ -301,6 +301,29 @@ def mlp_param_count(hidden):
     return int(load().txs_mlp_param_count(hidden))
 
 
+def prop_mlp_bwd(mlp: MlpSpec, rays_o, rays_d, edges, d_sigma, workspace=None):
+    """dL/dparams (float32 [param count]) given dL/dsigma at the bin midpoints.
+
+    workspace: optional uint8 device tensor of txs_mlp_bwd_workspace_size bytes,
+    reused across calls; allocated here when None.
+    """
+    n = _rays(rays_o, rays_d)
+    nb1 = edges.shape[1]
+    _need(edges, "edges", torch.float32, (n, nb1))
+    _need(d_sigma, "d_sigma", torch.float32, (n, nb1 - 1))
+    L = load()
+    need = int(L.txs_mlp_bwd_workspace_size(mlp.hidden))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=edges.device)
+    grad = torch.empty(mlp.params.numel(), dtype=torch.float32, device=edges.device)
+    m = mlp.struct()
+    check(L.txs_prop_mlp_bwd(C.byref(m), _ptr(rays_o), _ptr(rays_d), n, nb1 - 1, _ptr(edges),
+                             _ptr(d_sigma), _ptr(grad), _ptr(workspace),
+                             workspace.numel() * workspace.element_size(), _stream()),
+          "txs_prop_mlp_bwd")
+    return grad
+
+
 def hist_loss(packed_info, t0, t1, w, edges, prop_w, eps=1e-7, want_grad=True):
     """Proposal loss per ray and d(mean loss)/d prop_w ([N, n_bins] or None)."""
     n = packed_info.shape[0]

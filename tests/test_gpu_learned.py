@@ -92,6 +92,74 @@ def test_mlp_random_network(gpu_lib, H, contract):
 
 
 # ----------------------------------------------------------------------------
+# MLP adjoint
+# ----------------------------------------------------------------------------
+def mlp_case(txs, H, n_rays, n_bins, contract, seed):
+    params = scenes.mlp_init(H)
+    g = scenes.rng(seed)
+    params[39 * H:40 * H] = g.normal(0, 0.3, H)
+    params[40 * H + H * H:41 * H + H * H] = g.normal(0, 0.3, H)
+    params[-1] = -0.5
+    radius = 6.0 if contract else 3.0
+    o, d, edges = rays_and_edges(txs, n_rays, n_bins=n_bins, radius=radius, seed=seed)
+    ds = g.standard_normal((n_rays, n_bins)).astype(np.float32)
+    return params, o, d, edges, ds
+
+
+def assert_grad_close(got, ref, mag, name):
+    # The two sides round the same operands to bf16 but sum in different orders
+    # (fp32 matrix cores vs binary64); a flipped bf16 rounding or ReLU mask moves
+    # one term by about one bf16 ulp.  Scale: the sum of |term| per parameter.
+    err = np.abs(got.astype(np.float64) - ref) / (mag + 1e-30)
+    q = np.quantile(err, 0.999)
+    assert q <= 2.0 ** -8, (name, q, err.max())
+    assert err.max() <= 2.0 ** -4, (name, int(err.argmax()), err.max())
+    # global: against the magnitudes, not |grad| -- with random-sign upstream
+    # gradients over N points the gradient itself is ~sqrt(N) times smaller
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(mag)
+    assert rel <= 2.0 ** -12, (name, rel, q)
+
+
+@pytest.mark.parametrize("H,n_rays,n_bins,contract", [
+    (64, 3, 13, False),      # one partial batch
+    (64, 300, 64, False),    # 300 batches: some blocks take two
+    (128, 400, 48, False),
+    (128, 300, 40, True),
+])
+def test_mlp_bwd_matches_emulated_oracle(gpu_lib, H, n_rays, n_bins, contract):
+    params, o, d, edges, ds = mlp_case(gpu_lib, H, n_rays, n_bins, contract, seed=11 + H)
+    spec = mlp_spec(gpu_lib, params, H, contract=contract)
+    got = host(gpu_lib.prop_mlp_bwd(spec, dev(o), dev(d), edges, dev(ds)))
+    x = oracle.bin_midpoints(o, d, host(edges))
+    ref, mag = oracle.mlp_bwd(x, params, H, ds.reshape(-1), contract=contract, emulate_bf16=True,
+                              want_abs=True)
+    assert_grad_close(got, ref, mag, f"H={H} n={n_rays}x{n_bins}")
+    # and the bf16 gradient points where the binary64 one does
+    g64 = oracle.mlp_bwd(x, params, H, ds.reshape(-1), contract=contract)
+    cos = np.dot(got, g64) / (np.linalg.norm(got) * np.linalg.norm(g64))
+    assert cos > 0.99, cos
+
+
+def test_mlp_bwd_deterministic_and_empty(gpu_lib):
+    H = 128
+    params, o, d, edges, ds = mlp_case(gpu_lib, H, 500, 64, False, seed=5)
+    spec = mlp_spec(gpu_lib, params, H)
+    ws = torch.empty(gpu_lib.load().txs_mlp_bwd_workspace_size(H), dtype=torch.uint8,
+                     device="cuda")
+    a = host(gpu_lib.prop_mlp_bwd(spec, dev(o), dev(d), edges, dev(ds), workspace=ws))
+    b = host(gpu_lib.prop_mlp_bwd(spec, dev(o), dev(d), edges, dev(ds), workspace=ws))
+    assert np.array_equal(a, b)
+    # zero upstream gradient, and no rays at all, both give an exact zero
+    z = host(gpu_lib.prop_mlp_bwd(spec, dev(o), dev(d), edges, dev(np.zeros_like(ds))))
+    assert np.all(z == 0.0)
+    e = host(gpu_lib.prop_mlp_bwd(spec, dev(o[:0]), dev(d[:0]), edges[:0],
+                                  dev(np.zeros((0, 64), np.float32))))
+    assert e.shape == (params.size,) and np.all(e == 0.0)
+    with pytest.raises(gpu_lib.TxsError):
+        gpu_lib.prop_mlp_bwd(spec, dev(o), dev(d), edges, dev(ds), workspace=ws[:100])
+
+
+# ----------------------------------------------------------------------------
 # histogram loss, weights-only render, Adam
 # ----------------------------------------------------------------------------
 def target_histograms(n_rays, seed):

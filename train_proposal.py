@@ -1,0 +1,171 @@
+"""Learned transmittance estimator versus the occupancy grid, on one MI355X.
+
+The unbounded scene (64 blobs and a background shell, 4 nested 128^3 grids,
+8 cameras of 512x256 = 2^20 rays).  Steps:
+
+1. Judge and targets: the plain grid renderer (march, no-gradient filter at
+   T < 1e-4, field, render with weights) on every ray.  Its colours judge the
+   learned sampler; its weights are the PDF-matching targets.
+2. Train the proposal network (hidden 128, contracted Fourier encoding) for
+   --steps Adam steps on all rays (full batch), lr cosine 1e-2 -> 1e-4, on
+   128 uniform bins per ray over the chord through the outermost grid cube.
+3. Sweep the number of final samples drawn from the proposal by inverse CDF;
+   render the field on them; mean |rgb - judge| over all rays and channels,
+   for the trained and the untrained network.
+4. Time both samplers end to end (fwd + bwd, field stand-in included on both
+   sides) at the smallest sample count within the error bar.
+
+Prints one JSON line; --save writes the trained parameters (.npy).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--hidden", type=int, default=128)
+    ap.add_argument("--bins", type=int, default=128)
+    ap.add_argument("--ray-stride", type=int, default=1, help="train/evaluate every k-th ray")
+    ap.add_argument("--sweep", default="32,48,64,96,128,192,256")
+    ap.add_argument("--err-bar", type=float, default=1e-3)
+    ap.add_argument("--lr0", type=float, default=1e-2)
+    ap.add_argument("--lr1", type=float, default=1e-4)
+    ap.add_argument("--log-every", type=int, default=50)
+    ap.add_argument("--time-reps", type=int, default=5)
+    ap.add_argument("--oracle-every", type=int, default=0,
+                    help="check the judge against the FP64 oracle on every k-th ray (0 = skip)")
+    ap.add_argument("--save", default="")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    import torch
+
+    import paper_2305_04966_amd as txs
+    import scenes
+    from paper_2305_04966_amd.learned import ProposalEstimator, cosine_lr, grid_render
+
+    txs.load()
+    w = scenes.unbounded()
+    idx = np.arange(0, w.n_rays, args.ray_stride)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    o, d = dev(w.rays_o[idx]), dev(w.rays_d[idx])
+    N = len(idx)
+    grid = txs.GridSpec(dev(w.bits.view(np.int32)), w.res, w.n_levels, (0.0, 0.0, 0.0),
+                        w.half_extent0)
+    fp = dev(w.fld.packed_params().astype(np.float32))
+    nb = w.fld.n_blobs
+    rec = {"workload": f"unbounded: 64 blobs + shell, 4x128^3 cascade, {N} rays",
+           "hidden": args.hidden, "bins": args.bins, "steps": args.steps}
+
+    # 1. judge + targets
+    judge = grid_render(grid, o, d, fp, nb, dt0=w.dt0, t_min=w.t_min)
+    torch.cuda.synchronize()
+    rec["grid_samples"] = judge.samples.n_samples
+    print(f"[judge] {N} rays, {judge.samples.n_samples} grid samples", flush=True)
+    if args.oracle_every > 0:
+        import oracle
+        k = np.arange(0, N, args.oracle_every)
+        oo, od_ = w.rays_o[idx][k], w.rays_d[idx][k]
+        m = oracle.march(oo, od_, w.bits, w.res, n_levels=w.n_levels,
+                         half_extent0=w.half_extent0, dt0=w.dt0)
+        s_ng, _ = oracle.field_at_samples(oo, od_, m["t0"], m["t1"], m["ray_id"],
+                                          w.fld.packed_params())
+        kept, _ = oracle.transmittance_prefix(m["packed_info"], m["t0"], m["t1"],
+                                              s_ng.astype(np.float32), w.t_min)
+        info, t0o, t1o, rido = oracle.gather_prefix(m["packed_info"], kept, m["t0"], m["t1"],
+                                                    m["ray_id"])
+        s, c = oracle.field_at_samples(oo, od_, t0o, t1o, rido, w.fld.packed_params())
+        ref = oracle.render_fwd(info, t0o, t1o, s.astype(np.float32), c.astype(np.float32))
+        rec["judge_vs_oracle_max_abs"] = float(np.abs(judge.rgb.cpu().numpy()[k]
+                                                      - ref["rgb"]).max())
+
+    # 2. train
+    edges = txs.uniform_bins(grid, o, d, args.bins)
+    est = ProposalEstimator(dev(scenes.mlp_init(args.hidden)), args.hidden, scale=1.5,
+                            contract=True)
+    t0d, t1d = est.dense_intervals(edges)
+
+    def evaluate(n_out):
+        e = est.sample(o, d, edges, n_out)
+        a, b = est.dense_intervals(e)
+        sig, rgb = txs.blob_field(fp, nb, o, d, a, b, fixed_count=n_out)
+        out = txs.render_fwd(None, a, b, sig, rgb, n_rays=N, fixed_count=n_out)
+        return float((out[0] - judge.rgb).abs().mean())
+
+    sweep = [int(s) for s in args.sweep.split(",")]
+    rec["untrained_err"] = {n: evaluate(n) for n in sweep}
+    losses = []
+    torch.cuda.synchronize()
+    t_train = time.perf_counter()
+    for step in range(1, args.steps + 1):
+        loss = est.train_step(o, d, edges, judge, cosine_lr(step, args.steps, args.lr0, args.lr1),
+                              t0d, t1d)
+        if step == 1 or step % args.log_every == 0 or step == args.steps:
+            lm = float(loss.mean())
+            losses.append((step, lm))
+            print(f"[train] step {step} loss {lm:.6g} {time.perf_counter() - t_train:.1f} s",
+                  flush=True)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t_train
+    rec["train_s"] = train_s
+    rec["ms_per_train_step"] = 1000.0 * train_s / max(args.steps, 1)
+    rec["loss"] = losses
+    rec["trained_err"] = {n: evaluate(n) for n in sweep}
+    print(f"[eval] untrained {rec['untrained_err']} trained {rec['trained_err']}", flush=True)
+    ok = [n for n in sweep if rec["trained_err"][n] <= args.err_bar]
+    n_star = min(ok) if ok else max(sweep)
+    rec["n_final"] = n_star
+    rec["within_err_bar"] = bool(ok)
+
+    # 4. timing, fwd + bwd, field included on both sides
+    g_rgb = dev(w.grads[idx])
+
+    def grid_step():
+        p = txs.march(grid, o, d, dt0=w.dt0)
+        sg, _ = txs.blob_field(fp, nb, o, d, p.t0, p.t1, p.ray_id, want_rgb=False)
+        q = txs.filter_transmittance(p, sg, w.t_min)
+        sg, rgb = txs.blob_field(fp, nb, o, d, q.t0, q.t1, q.ray_id)
+        out = txs.render_fwd(q.packed_info, q.t0, q.t1, sg, rgb, want_optical_depth=True)
+        txs.render_bwd(q.packed_info, q.t0, q.t1, sg, rgb, g_rgb, optical_depth=out[4])
+
+    def learned_step():
+        e0 = txs.uniform_bins(grid, o, d, args.bins)
+        e = est.sample(o, d, e0, n_star)
+        a, b = est.dense_intervals(e)
+        sg, rgb = txs.blob_field(fp, nb, o, d, a, b, fixed_count=n_star)
+        out = txs.render_fwd(None, a, b, sg, rgb, n_rays=N, fixed_count=n_star,
+                             want_optical_depth=True)
+        txs.render_bwd(None, a, b, sg, rgb, g_rgb, n_rays=N, fixed_count=n_star,
+                       optical_depth=out[4])
+
+    for name, fn in (("grid", grid_step), ("learned", learned_step)):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.time_reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.time_reps
+        rec[f"{name}_ms"] = 1000.0 * dt
+        rec[f"{name}_rays_per_s"] = N / dt
+    rec["learned_over_grid"] = rec["learned_rays_per_s"] / rec["grid_rays_per_s"]
+    if args.save:
+        np.save(args.save, est.params.cpu().numpy())
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()
