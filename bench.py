@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
 
 # algorithmic HBM bytes of each library entry point (N rays, Sm marched, S kept)
 BYTES = {
@@ -43,8 +44,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="image", choices=["image", "tiny", "unbounded"])
-    ap.add_argument("--cpu-sample", type=int, default=16,
+    ap.add_argument("--cpu-sample", type=int, default=2,
                     help="oracle baseline runs on every k-th ray (0 = skip)")
+    ap.add_argument("--learned-steps", type=int, default=300,
+                    help="train the proposal network this many steps on the unbounded scene and "
+                         "report learned vs grid sampling (0 = skip)")
+    ap.add_argument("--learned-train-stride", type=int, default=4)
+    ap.add_argument("--learned-sweep", default="128,160,192,224,256")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run a plain device copy of this many MiB (counter "
                          "calibration for profiler byte counts)")
@@ -142,6 +148,49 @@ def gpu_bench(args, w):
     return elapsed, tl.summary(), stats
 
 
+def learned_vs_grid(args):
+    """The learned estimator against the occupancy grid on the unbounded scene:
+    train the proposal network (untimed), then time both samplers end to end
+    (fwd + bwd, the field stand-in on both sides) on all 2^20 rays, the learned
+    one at the fewest final samples within 1e-3 mean rgb error of the grid."""
+    from train_proposal import run
+    rec, _ = run(steps=args.learned_steps, train_stride=args.learned_train_stride,
+                 sweep=[int(s) for s in args.learned_sweep.split(",")], untrained=False,
+                 log_every=max(args.learned_steps, 1), time_reps=3,
+                 log=lambda s: print(s, file=sys.stderr, flush=True))
+    keep = ("workload", "hidden", "bins", "train_steps", "ms_per_train_step", "err_bar",
+            "n_final", "within_err_bar", "trained_err", "grid_samples", "grid_ms",
+            "learned_ms", "grid_rays_per_s", "learned_rays_per_s", "learned_over_grid")
+    out = {k: rec[k] for k in keep}
+    out["final_loss"] = rec["loss"][-1][1]
+    return out
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed profiler record
+    (FETCH_SIZE and WRITE_SIZE, calibrated by a device copy of known size), or
+    None when the record is absent, is for another kernel, or its sources have
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        try:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        except OSError:
+            return None
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def cpu_baseline(w, every):
     """The oracle on every `every`-th ray of the same workload (same steps)."""
     import oracle
@@ -210,8 +259,10 @@ def main():
         "kernels_ms": {k: round(v[0], 4) for k, v in ker.items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": measured_traffic(dom), "alg_bytes_per_launch": bytes_launch},
     }
+    if args.learned_steps > 0:
+        rec["learned_vs_grid"] = learned_vs_grid(args)
     if rank == 0 and args.cpu_sample > 0:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     if rank == 0:

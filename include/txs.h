@@ -229,6 +229,15 @@ txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, float far_pl
                             const float* rays_o, const float* rays_d, int32_t n_rays,
                             int32_t n_bins, float* out_edges, void* stream);
 
+/*
+ * Dense interval layout of per-ray edges (the input layout of the renderer
+ * and the field for a fixed number of samples per ray): for edges float
+ * [n_rays, n+1], writes t0[r*n + k] = e_k and t1[r*n + k] = e_{k+1}
+ * (float [n_rays*n] each).
+ */
+txs_status txs_edges_to_intervals(const float* edges, int32_t n_rays, int32_t n, float* t0,
+                                  float* t1, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Learned transmittance estimator: the proposal network (Section 3.1 "PDF
  * Approaches", Table 1 third row; Section 3.2 "Choice of Representations").

@@ -6,7 +6,8 @@ Importing it does not touch the GPU; `load()` raises if the library is absent.
 """
 from ._lib import (TXS_EHIP, TXS_EINVAL, TXS_ECAPACITY, TXS_EOVERFLOW, TXS_OK,
                    TXS_PDF_SIGMA, TXS_PDF_WEIGHTS, LIB_PATH, TxsError, exported_symbols, load)
-from .ops import (GridSpec, MlpSpec, adam_step, blob_field, exclusive_scan, gather_prefix,
+from .ops import (GridSpec, MlpSpec, adam_step, blob_field, edges_to_intervals,
+                  exclusive_scan, gather_prefix,
                   hist_loss, march_count, march_fill, mlp_param_count, prop_mlp_bwd,
                   prop_mlp_fwd, render_bwd,
                   render_fwd, resample, transmittance_prefix, uniform_bins, weights_bwd)

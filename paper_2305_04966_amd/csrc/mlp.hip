@@ -88,7 +88,7 @@ __global__ void pack_kernel(const float* __restrict__ p, int H, __bf16* __restri
 struct FwdArgs {
   const __bf16* packed;
   const float* params;
-  float scale;
+  float inv_scale;  // 1 / scale
   int32_t contract;
   const float* ro;
   const float* rd;
@@ -115,23 +115,35 @@ __device__ __forceinline__ void encode_point(const Args& a, int64_t p, float (&y
   const float* e = a.edges + r * (a.n_bins + 1) + j;
   const float tm = 0.5f * (e[0] + e[1]);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) y[c] = (a.ro[3 * r + c] + tm * a.rd[3 * r + c]) / a.scale;
+  for (int c = 0; c < 3; ++c) y[c] = (a.ro[3 * r + c] + tm * a.rd[3 * r + c]) * a.inv_scale;
   if (a.contract) {
     const float n = sqrtf(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-    const float f = n <= 1.0f ? 0.5f : 0.5f * (2.0f - 1.0f / n) / n;
+    const float rn = 1.0f / n;
+    const float f = n <= 1.0f ? 0.5f : 0.5f * (2.0f - rn) * rn;
 #pragma unroll
     for (int c = 0; c < 3; ++c) y[c] *= f;
   }
 }
 
 // Lane group g's 16 feature slots of a point, as the two K-steps of layer 1.
+// Octave 0 from the hardware sine (argument in revolutions: sin(pi x) at x/2,
+// cos at x/2 + 1/4); each further octave by the double-angle identities
+// sin 2a = 2 sin a cos a, cos 2a = 1 - 2 sin^2 a (absolute error grows about
+// 2x per octave: ~1e-6 at octave 5, far below a bf16 step).
 __device__ __forceinline__ void features(float xa, bool in_range, bf16x8& b0, bf16x8& b1) {
   float f[16];
+  float sn = __builtin_amdgcn_sinf(0.5f * xa);
+  float cs = __builtin_amdgcn_sinf(0.5f * xa + 0.25f);
+  f[0] = sn;
+  f[1] = cs;
 #pragma unroll
-  for (int q = 0; q < 12; ++q) {
-    // sin(2^k pi x) = sin(2 pi * 2^(k-1) x); cos adds a quarter turn
-    const float rev = xa * (float)(1 << (q / 2)) * 0.5f + ((q & 1) ? 0.25f : 0.0f);
-    f[q] = __builtin_amdgcn_sinf(rev);
+  for (int k = 1; k < 6; ++k) {
+    const float s2 = 2.0f * sn * cs;
+    const float c2 = 1.0f - 2.0f * sn * sn;
+    sn = s2;
+    cs = c2;
+    f[2 * k] = sn;
+    f[2 * k + 1] = cs;
   }
   f[12] = xa;
   f[13] = f[14] = f[15] = 0.0f;
@@ -149,6 +161,10 @@ __device__ __forceinline__ void features(float xa, bool in_range, bf16x8& b0, bf
   b1 = pack8(hi);
 }
 
+// Layer 3 (w3 . h2) also runs on the matrix cores: an A operand whose row 0
+// is w3 (in the K order of the h2 fragments) and whose other rows are zero,
+// times the bf16 h2 fragments as B, accumulates z in row 0 of a 16x16 tile
+// (lanes 0..15, element 0), one point per column.
 template <int H, int NT>
 __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
   constexpr int MT = H / 16, KS = H / 32;
@@ -156,17 +172,25 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
   const ParamOffsets po(H);
   __shared__ bf16x8 sA1[MT * 2 * 64];
   __shared__ bf16x8 sA2[MT * KS * 64];
-  __shared__ float sb1[H], sb2[H], sw3[H];
+  __shared__ bf16x8 sA3[KS * 64];
+  __shared__ float sb1[H], sb2[H];
   // weights to LDS once per block
   {
     const bf16x8* src = reinterpret_cast<const bf16x8*>(a.packed);
     for (int i = threadIdx.x; i < MT * 2 * 64; i += blockDim.x) sA1[i] = src[i];
     const bf16x8* src2 = reinterpret_cast<const bf16x8*>(a.packed + ko.A2);
     for (int i = threadIdx.x; i < MT * KS * 64; i += blockDim.x) sA2[i] = src2[i];
+    for (int i = threadIdx.x; i < KS * 64; i += blockDim.x) {
+      const int s3 = i / 64, l = i % 64;
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        v[e] = (l % 16 == 0) ? a.packed[ko.w3 + unit_of(s3, l / 16, e)] : (__bf16)0.0f;
+      sA3[i] = v;
+    }
     for (int i = threadIdx.x; i < H; i += blockDim.x) {
       sb1[i] = a.params[po.b1 + i];
       sb2[i] = a.params[po.b2 + i];
-      sw3[i] = (float)a.packed[ko.w3 + i];
     }
     __syncthreads();
   }
@@ -188,66 +212,68 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
       const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
       features(xa, g < 3, B1[t][0], B1[t][1]);
     }
-    // layer 1
-    f32x4 h1[NT][MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const bf16x8 w0 = sA1[(m * 2 + 0) * 64 + ln], w1 = sA1[(m * 2 + 1) * 64 + ln];
-      const f32x4 bias = {sb1[16 * m + 4 * g], sb1[16 * m + 4 * g + 1], sb1[16 * m + 4 * g + 2],
-                          sb1[16 * m + 4 * g + 3]};
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, B1[t][0], bias, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, B1[t][1], c, 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) c[i] = fmaxf(c[i], 0.0f);
-        h1[t][m] = c;
-      }
-    }
-    // layer 2: B operand of K-step s = fragments 2s and 2s+1 of layer 1
+    // layer 1; B operand of layer 2's K-step s = fragments 2s and 2s+1
     bf16x8 B2[NT][KS];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int s = 0; s < KS; ++s) {
+      f32x4 hh[NT][2];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const float v[8] = {h1[t][2 * s][0], h1[t][2 * s][1], h1[t][2 * s][2], h1[t][2 * s][3],
-                            h1[t][2 * s + 1][0], h1[t][2 * s + 1][1], h1[t][2 * s + 1][2],
-                            h1[t][2 * s + 1][3]};
+      for (int h = 0; h < 2; ++h) {
+        const int m = 2 * s + h;
+        const bf16x8 w0 = sA1[(m * 2 + 0) * 64 + ln], w1 = sA1[(m * 2 + 1) * 64 + ln];
+        const f32x4 bias = {sb1[16 * m + 4 * g], sb1[16 * m + 4 * g + 1], sb1[16 * m + 4 * g + 2],
+                            sb1[16 * m + 4 * g + 3]};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, B1[t][0], bias, 0, 0, 0);
+          hh[t][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, B1[t][1], c, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const float v[8] = {fmaxf(hh[t][0][0], 0.0f), fmaxf(hh[t][0][1], 0.0f),
+                            fmaxf(hh[t][0][2], 0.0f), fmaxf(hh[t][0][3], 0.0f),
+                            fmaxf(hh[t][1][0], 0.0f), fmaxf(hh[t][1][1], 0.0f),
+                            fmaxf(hh[t][1][2], 0.0f), fmaxf(hh[t][1][3], 0.0f)};
         B2[t][s] = pack8(v);
       }
-    float z[NT];
+    }
+    // layers 2 and 3: two row tiles of h2 at a time make one K-step of layer 3
+    f32x4 zt[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) z[t] = 0.0f;
-    // not unrolled: keeps one row of W2 tiles in registers at a time
+    for (int t = 0; t < NT; ++t) zt[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 1
-    for (int m = 0; m < MT; ++m) {
-      const f32x4 bias = {sb2[16 * m + 4 * g], sb2[16 * m + 4 * g + 1], sb2[16 * m + 4 * g + 2],
-                          sb2[16 * m + 4 * g + 3]};
-      f32x4 c[NT];
+    for (int s3 = 0; s3 < KS; ++s3) {
+      f32x4 c[NT][2];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) c[t] = bias;
+      for (int h = 0; h < 2; ++h) {
+        const int m = 2 * s3 + h;
+        const f32x4 bias = {sb2[16 * m + 4 * g], sb2[16 * m + 4 * g + 1], sb2[16 * m + 4 * g + 2],
+                            sb2[16 * m + 4 * g + 3]};
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const bf16x8 w = sA2[(m * KS + s) * 64 + ln];
+        for (int t = 0; t < NT; ++t) c[t][h] = bias;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, B2[t][s], c[t], 0, 0, 0);
-      }
-      // layer 3 partial dot: relu, round to bf16, times bf16 w3
+        for (int s = 0; s < KS; ++s) {
+          const bf16x8 w = sA2[(m * KS + s) * 64 + ln];
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float h2 = (float)(__bf16)fmaxf(c[t][i], 0.0f);
-          z[t] = fmaf(h2, sw3[16 * m + 4 * g + i], z[t]);
+          for (int t = 0; t < NT; ++t)
+            c[t][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, B2[t][s], c[t][h], 0, 0, 0);
         }
+      }
+      const bf16x8 w3 = sA3[s3 * 64 + ln];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const float v[8] = {fmaxf(c[t][0][0], 0.0f), fmaxf(c[t][0][1], 0.0f),
+                            fmaxf(c[t][0][2], 0.0f), fmaxf(c[t][0][3], 0.0f),
+                            fmaxf(c[t][1][0], 0.0f), fmaxf(c[t][1][1], 0.0f),
+                            fmaxf(c[t][1][2], 0.0f), fmaxf(c[t][1][3], 0.0f)};
+        zt[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, pack8(v), zt[t], 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      float zz = z[t];
-      zz += __shfl_xor(zz, 16, kWave);
-      zz += __shfl_xor(zz, 32, kWave);
       const int64_t p = (t0 + t) * 16 + col;
-      if (g == 0 && valid[t]) a.sigma[p] = softplus(zz + b3);
+      if (g == 0 && valid[t]) a.sigma[p] = softplus(zt[t][0] + b3);
     }
   }
 }
@@ -275,7 +301,7 @@ constexpr int kRowStride = kBwdBatch + 8;  // bf16 elements per staged row (144 
 struct BwdArgs {
   const __bf16* packed;
   const float* params;
-  float scale;
+  float inv_scale;  // 1 / scale
   int32_t contract;
   const float* ro;
   const float* rd;
@@ -560,8 +586,8 @@ extern "C" txs_status txs_prop_mlp_fwd(const txs_mlp* mlp, const float* rays_o,
   TXS_REQUIRE(n_rays >= 0 && n_bins >= 1, "txs_prop_mlp_fwd: bad size");
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && edges && sigma, "txs_prop_mlp_fwd: null array");
-  FwdArgs a{static_cast<const __bf16*>(mlp->packed), mlp->params, mlp->scale, mlp->contract,
-            rays_o, rays_d, n_rays, n_bins, edges, sigma};
+  FwdArgs a{static_cast<const __bf16*>(mlp->packed), mlp->params, 1.0f / mlp->scale,
+            mlp->contract, rays_o, rays_d, n_rays, n_bins, edges, sigma};
   const int64_t n_tiles = ((int64_t)n_rays * n_bins + 15) / 16;
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -608,8 +634,9 @@ extern "C" txs_status txs_prop_mlp_bwd(const txs_mlp* mlp, const float* rays_o,
     TXS_REQUIRE(workspace_bytes >= txs_mlp_bwd_workspace_size(H),
                 "txs_prop_mlp_bwd: workspace of %zu bytes, need %zu", workspace_bytes,
                 txs_mlp_bwd_workspace_size(H));
-    BwdArgs a{static_cast<const __bf16*>(mlp->packed), mlp->params, mlp->scale, mlp->contract,
-              rays_o, rays_d, n_rays, n_bins, edges, d_sigma, static_cast<float*>(workspace)};
+    BwdArgs a{static_cast<const __bf16*>(mlp->packed), mlp->params, 1.0f / mlp->scale,
+              mlp->contract, rays_o, rays_d, n_rays, n_bins, edges, d_sigma,
+              static_cast<float*>(workspace)};
     if (H == 64)
       hipLaunchKernelGGL(mlp_bwd_kernel<64>, dim3(blocks), dim3(256), 0, as_stream(stream), a);
     else

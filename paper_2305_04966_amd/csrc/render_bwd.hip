@@ -20,7 +20,8 @@ namespace {
 // sums entering from the right for the chain that crosses the window end;
 // replaced by the sums leaving to the left.
 template <int kMode>
-__device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, int seg_in,
+__device__ void bwd_window(const Args& a, WaveLds& L, float4* stage, int64_t p, int64_t lim,
+                           int seg_in,
                            double& cQ, double& cS) {
   const int ln = lane();
   const int64_t pos0 = p + (int64_t)K * ln;
@@ -80,14 +81,37 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
   {
     float c[K][3];
     float gwv[K];
-    if (kMode == kBwd) load_rgb(a.rgb, pos0, lim, c);
-    else load_k(a.g_w, pos0, lim, gwv);
+    if (kMode == kBwd) {
+      if (p + W <= lim) load_rgb_staged(a.rgb, p, stage, c);  // wave-uniform
+      else load_rgb(a.rgb, pos0, lim, c);
+    } else {
+      load_k(a.g_w, pos0, lim, gwv);
+    }
+    // whole window owned by this wave's rays: colour gradients leave through LDS
+    const bool staged = kMode == kBwd && a.d_rgb && __ballot(!all_own) == 0;
+    float* st = reinterpret_cast<float*>(stage) + 3 * K * ln;
     float T_right = 0.0f;  // T of element j+1 (same lane)
+    // the ray's total optical depth and cotangent row change only where a ray
+    // starts inside the lane: loaded once per ray, not per element
+    int cs = cur_[K - 1] < 0 ? 0 : cur_[K - 1];
+    double ptot = L.ptot[cs];
+    float4 g4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b4 = g4;
+    if (kMode == kBwd) {
+      g4 = *reinterpret_cast<const float4*>(&L.cot[cs][0]);
+      b4 = *reinterpret_cast<const float4*>(&L.cot[cs][4]);
+    }
 #pragma unroll
     for (int j = K - 1; j >= 0; --j) {
+      if (j < K - 1 && mk[j + 1] != 0) {  // element j belongs to an earlier ray
+        cs = cur_[j] < 0 ? 0 : cur_[j];
+        ptot = L.ptot[cs];
+        if (kMode == kBwd) {
+          g4 = *reinterpret_cast<const float4*>(&L.cot[cs][0]);
+          b4 = *reinterpret_cast<const float4*>(&L.cot[cs][4]);
+        }
+      }
       q += (double)tau[j];  // Q_j, inclusive
-      const int cs = cur_[j] < 0 ? 0 : cur_[j];
-      const double P = L.ptot[cs] - q;
+      const double P = ptot - q;
       const float T = exp_neg(P);
       // T_{j+1} is the next element's T unless j ends its lane or its ray
       const float Tn = (j == K - 1 || mk[j + 1] != 0) ? exp_neg(P + (double)tau[j]) : T_right;
@@ -95,12 +119,14 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
       const float w = T * one_minus_exp_neg(tau[j]);
       float v;
       if (kMode == kBwd) {
-        const float4 g4 = *reinterpret_cast<const float4*>(&L.cot[cs][0]);
-        const float4 b4 = *reinterpret_cast<const float4*>(&L.cot[cs][4]);
         // cot row: g0 g1 g2 h | q bg0 bg1 bg2
         v = g4.x * (c[j][0] - b4.y) + g4.y * (c[j][1] - b4.z) + g4.z * (c[j][2] - b4.w) + g4.w +
             b4.x * mid[j];
-        if (a.d_rgb && own[j]) {
+        if (staged) {
+          st[3 * j] = w * g4.x;
+          st[3 * j + 1] = w * g4.y;
+          st[3 * j + 2] = w * g4.z;
+        } else if (a.d_rgb && own[j]) {
           a.d_rgb[3 * (pos0 + j)] = w * g4.x;
           a.d_rgb[3 * (pos0 + j) + 1] = w * g4.y;
           a.d_rgb[3 * (pos0 + j) + 2] = w * g4.z;
@@ -112,6 +138,7 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
       tv[j] = own[j] ? Tn * v : 0.0f;
       if (mk[j] != 0) q = 0.0;
     }
+    if (staged) store_rgb_staged(a.d_rgb, p, stage);
     bool before_first = true;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -124,10 +151,12 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
   double Rs = seg_scan_rev(Bs, fl);
   if (fl == kWave) Rs += cS;
   double s = lane_next(Rs, cS);
+  // the difference T_{j+1} v_j - S_j in binary32: its rounding is relative to
+  // the larger term, which is within the adjoint's own conditioning scale
   float ds[K];
 #pragma unroll
   for (int j = K - 1; j >= 0; --j) {
-    ds[j] = (float)((double)delta[j] * ((double)tv[j] - s));
+    ds[j] = delta[j] * (tv[j] - (float)s);
     s += (double)u[j];
     if (mk[j] != 0) s = 0.0;
   }
@@ -139,7 +168,9 @@ __device__ void bwd_window(const Args& a, WaveLds& L, int64_t p, int64_t lim, in
 template <int kMode>
 __global__ __launch_bounds__(kBlock) void bwd_kernel(Args a) {
   __shared__ WaveLds lds[kWaves];
+  __shared__ float4 stage_mem[kWaves][StageSize<kMode>::value];
   WaveLds& L = lds[threadIdx.x / kWave];
+  float4* stage = stage_mem[threadIdx.x / kWave];
   const int ln = lane();
   const int64_t wave = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
   const int32_t r0 = (int32_t)(wave * kWave);
@@ -174,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(Args a) {
     const uint64_t cover = __ballot(R.active && R.st < p && p < R.en);
     const int seg_in = cover ? __builtin_ctzll(cover) : -1;
     write_marks(L, p, R.st, R.en, R.active);
-    bwd_window<kMode>(a, L, p, min(p + W, R.hi), seg_in, cQ, cS);
+    bwd_window<kMode>(a, L, stage, p, min(p + W, R.hi), seg_in, cQ, cS);
   }
 }
 

@@ -65,6 +65,14 @@ struct WaveLds {
   double ptot[kWave];
 };
 
+// Per-wave LDS staging of a window's [W][3] colour rows (colours on the way
+// in, colour gradients on the way out), so that HBM sees whole-row float4
+// accesses at consecutive lanes.  Only the modes that move colours have it.
+template <int kMode>
+struct StageSize {
+  static constexpr int value = (kMode == kFwd || kMode == kBwd) ? 3 * W / 4 : 1;
+};
+
 // mark value: 0 none, lane+1 = first sample of that lane's ray, -1 = sample
 // after the end of a ray (dead until the next head).
 __device__ __forceinline__ int decode_mark(int m) { return m > 0 ? m - 1 : -1; }
@@ -92,20 +100,7 @@ __device__ __forceinline__ void ray_row(const Args& a, int32_t r, int64_t& st, i
 // then the three row-end values are read into scalars and carried into the
 // later rows.  They must be called with all 64 lanes active.
 
-// Inclusive max over lanes <= this one.
-__device__ __forceinline__ int max_scan_incl(int v) {
-  const int ri = lane() & 15, row = lane() >> 4;
-  int t;
-  t = dpp<kRowShr1>(v, v); if (ri >= 1) v = max(v, t);
-  t = dpp<kRowShr2>(v, v); if (ri >= 2) v = max(v, t);
-  t = dpp<kRowShr4>(v, v); if (ri >= 4) v = max(v, t);
-  t = dpp<kRowShr8>(v, v); if (ri >= 8) v = max(v, t);
-  const int e0 = readlane(v, 15), e1 = readlane(v, 31), e2 = readlane(v, 47);
-  const int c1 = e0, c2 = max(c1, e1), c3 = max(c2, e2);
-  const int c = row == 1 ? c1 : row == 2 ? c2 : row == 3 ? c3 : v;
-  return max(v, c);
-}
-
+// Inclusive max over lanes <= this one: max_scan_incl (txs_common.h).
 // Inclusive min over lanes >= this one.
 __device__ __forceinline__ int min_scan_rev_incl(int v) {
   const int ri = lane() & 15, row = lane() >> 4;
@@ -179,6 +174,9 @@ __device__ __forceinline__ double readlane_d(double v, int l) { return readlane(
 // binary32 f, whose rounding (2^-24 absolute) is the only error besides the
 // exp2 itself, for any x.  Results below 2^-250 flush to zero.
 __device__ __forceinline__ float exp_neg(double x) {
+  // x < 16: rounding x and x log2(e) to binary32 costs < 2e-6 relative in the
+  // result, so the exponent is formed in binary32
+  if (x < 16.0) return __builtin_amdgcn_exp2f((float)x * -1.44269504f);
   const double y = -x * 1.4426950408889634;
   if (!(y > -250.0)) return 0.0f;
   const double n = floor(y);
@@ -187,7 +185,8 @@ __device__ __forceinline__ float exp_neg(double x) {
 
 // 1 - exp(-t) for t >= 0 without cancellation: for t < 1/4 the nested Taylor
 // form t (1 - t/2 (1 - t/3 (1 - ... (1 - t/7)))) (truncation < 1e-9
-// relative), otherwise 1 - exp(-t) with exp(-t) <= 0.78.
+// relative), otherwise 1 - exp(-t) with exp(-t) <= 0.78.  (Inputs are finite
+// and >= 0; an infinite t gives 1.)
 __device__ __forceinline__ float one_minus_exp_neg(float t) {
   if (t < 0.25f) {
     float r = 1.0f - t * (1.0f / 7.0f);
@@ -198,7 +197,8 @@ __device__ __forceinline__ float one_minus_exp_neg(float t) {
     r = 1.0f - t * 0.5f * r;
     return t * r;
   }
-  return 1.0f - exp_neg((double)t);
+  // exp(-t) <= 0.78 here: its binary32 error is < 6e-7 of 1 - exp(-t)
+  return 1.0f - __builtin_amdgcn_exp2f(t * -1.44269504f);
 }
 
 struct Acc5 {
@@ -259,6 +259,43 @@ __device__ __forceinline__ void load_rgb(const float* __restrict__ src, int64_t 
 }
 
 // Stores v[j] where own[j]; a full vector store when every element is owned.
+// The window's rgb rows [p, p+W) through LDS: lane l loads float4s l, l+64,
+// ... (consecutive lanes, consecutive 16 bytes), then reads back its own K
+// rows.  Caller guarantees p + W <= the array's row count.
+__device__ __forceinline__ void load_rgb_staged(const float* __restrict__ src, int64_t p,
+                                                float4* stage, float (&c)[K][3]) {
+  const int ln = lane();
+  const float4* s4 = reinterpret_cast<const float4*>(src + 3 * p);
+#pragma unroll
+  for (int q = 0; q < 3 * K / 4; ++q) stage[q * kWave + ln] = s4[q * kWave + ln];
+  wave_sync();
+  float f[3 * K];
+#pragma unroll
+  for (int q = 0; q < 3 * K / 4; ++q) {
+    const float4 x = stage[(3 * K / 4) * ln + q];
+    f[4 * q] = x.x;
+    f[4 * q + 1] = x.y;
+    f[4 * q + 2] = x.z;
+    f[4 * q + 3] = x.w;
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
+    for (int c3 = 0; c3 < 3; ++c3) c[j][c3] = f[3 * j + c3];
+  wave_sync();
+}
+
+// Writes the staged [W][3] rows to dst rows [p, p+W) as consecutive-lane float4s.
+__device__ __forceinline__ void store_rgb_staged(float* __restrict__ dst, int64_t p,
+                                                 const float4* stage) {
+  const int ln = lane();
+  wave_sync();
+  float4* d4 = reinterpret_cast<float4*>(dst + 3 * p);
+#pragma unroll
+  for (int q = 0; q < 3 * K / 4; ++q) d4[q * kWave + ln] = stage[q * kWave + ln];
+  wave_sync();
+}
+
 __device__ __forceinline__ void store_k(float* __restrict__ dst, int64_t pos0, const float (&v)[K],
                                         const bool (&own)[K]) {
   bool all = true;

@@ -8,7 +8,9 @@ namespace {
 template <int kMode>
 __global__ __launch_bounds__(kBlock) void fwd_kernel(Args a) {
   __shared__ WaveLds lds[kWaves];
+  __shared__ float4 stage_mem[kWaves][StageSize<kMode>::value];
   WaveLds& L = lds[threadIdx.x / kWave];
+  float4* stage = stage_mem[threadIdx.x / kWave];
   const int64_t wave = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
   const int32_t r0 = (int32_t)(wave * kWave);
   if (r0 >= a.n_rays) return;
@@ -21,7 +23,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(Args a) {
   FwdCarry carry{-1, 0.0, Acc5{0.f, 0.f, 0.f, 0.f, 0.f}, 0};
   for (int64_t p = R.lo & ~int64_t(3); p < R.hi; p += W) {
     write_marks(L, p, R.st, R.en, R.active);
-    carry = fwd_window<kMode>(a, L, r0, p, min(p + W, R.hi), carry);
+    carry = fwd_window<kMode>(a, L, stage, r0, p, min(p + W, R.hi), carry);
   }
 }
 

@@ -37,8 +37,8 @@ __device__ __forceinline__ void emit_ray(const Args& a, int32_t r, const Acc5& s
 // One window of the forward direction: samples [p, p+W) clipped to lim, the
 // window's marks already in LDS, cin the state entering the window.
 template <int kMode>
-__device__ FwdCarry fwd_window(const Args& a, WaveLds& L, int32_t r0, int64_t p, int64_t lim,
-                               const FwdCarry& cin) {
+__device__ FwdCarry fwd_window(const Args& a, WaveLds& L, float4* stage, int32_t r0, int64_t p,
+                               int64_t lim, const FwdCarry& cin) {
   const int ln = lane();
   const int64_t pos0 = p + (int64_t)K * ln;
   float t0v[K], t1v[K], sg[K];
@@ -80,7 +80,8 @@ __device__ FwdCarry fwd_window(const Args& a, WaveLds& L, int32_t r0, int64_t p,
   float c[K][3];
   if (kMode == kFwd) {
     if (a.rgb) {
-      load_rgb(a.rgb, pos0, lim, c);
+      if (p + W <= lim) load_rgb_staged(a.rgb, p, stage, c);  // wave-uniform
+      else load_rgb(a.rgb, pos0, lim, c);
     } else {  // colourless: weights, opacity and depth only
 #pragma unroll
       for (int j = 0; j < K; ++j) c[j][0] = c[j][1] = c[j][2] = 0.0f;
@@ -165,7 +166,7 @@ __device__ __forceinline__ void wave_optical_depth(const Args& a, WaveLds& L, in
   FwdCarry carry{-1, 0.0, Acc5{0.f, 0.f, 0.f, 0.f, 0.f}, 0};
   for (int64_t p = R.lo & ~int64_t(3); p < R.hi; p += W) {
     write_marks(L, p, R.st, R.en, R.active);
-    carry = fwd_window<kTotal>(a, L, r0, p, min(p + W, R.hi), carry);
+    carry = fwd_window<kTotal>(a, L, nullptr, r0, p, min(p + W, R.hi), carry);
   }
   wave_sync();
 }

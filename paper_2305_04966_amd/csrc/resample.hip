@@ -106,8 +106,34 @@ __global__ __launch_bounds__(256) void uniform_bins_kernel(txs_grid g, float nea
   out[i] = tn + (tf - tn) * ((float)k / (float)n_bins);
 }
 
+// t0[r*n + k] = e[r][k], t1[r*n + k] = e[r][k+1]: thread per output pair
+__global__ __launch_bounds__(256) void intervals_kernel(const float* __restrict__ edges,
+                                                        int64_t total, int32_t n,
+                                                        float* __restrict__ t0,
+                                                        float* __restrict__ t1) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t r = i / n;
+  const float* e = edges + i + r;  // row r starts at r*(n+1) = i - k + r
+  t0[i] = e[0];
+  t1[i] = e[1];
+}
+
 }  // namespace
 }  // namespace txs
+
+extern "C" txs_status txs_edges_to_intervals(const float* edges, int32_t n_rays, int32_t n,
+                                             float* t0, float* t1, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(n_rays >= 0 && n >= 1, "txs_edges_to_intervals: bad size");
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(edges && t0 && t1, "txs_edges_to_intervals: null array");
+  const int64_t total = (int64_t)n_rays * n;
+  hipLaunchKernelGGL(intervals_kernel, dim3(grid_1d(total, 256)), dim3(256), 0,
+                     as_stream(stream), edges, total, n, t0, t1);
+  return launch_status("txs_edges_to_intervals");
+}
 
 extern "C" txs_status txs_resample(int32_t n_rays, int32_t n_bins, const float* edges,
                                    const float* vals, int32_t mode, int32_t n_out,

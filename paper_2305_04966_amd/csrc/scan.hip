@@ -92,16 +92,24 @@ __global__ __launch_bounds__(kScanBlock) void write_packed(const int32_t* __rest
 // with all lanes (contiguous loads and stores).
 constexpr int kGatherWaves = 4;
 
+// The wave's 64 rays are copied as one walk over their output positions, 64
+// consecutive positions per chunk (one per lane) and kGatherUnroll chunks in
+// flight: stores are contiguous and coalesced, loads contiguous within a ray.
+// A lane finds the ray of its position from the ray starts that fall in the
+// chunk (marked in LDS, inclusive max scan over lanes) or, failing that, the
+// ray carried from the previous chunk.
+constexpr int kGatherUnroll = 4;
+
 __global__ __launch_bounds__(kWave* kGatherWaves) void gather_prefix_kernel(
     const int32_t* __restrict__ info_in, const int32_t* __restrict__ info_out, int32_t n_rays,
     int64_t n_in, const float* __restrict__ t0, const float* __restrict__ t1, int64_t capacity,
     float* __restrict__ t0o, float* __restrict__ t1o, int32_t* __restrict__ rido) {
-  const int ln = lane();
-  const int64_t r0 = ((int64_t)blockIdx.x * kGatherWaves + threadIdx.x / kWave) * kWave;
+  __shared__ int marks[kGatherWaves][kGatherUnroll][kWave];
+  const int ln = lane(), wv = threadIdx.x / kWave;
+  const int64_t r0 = ((int64_t)blockIdx.x * kGatherWaves + wv) * kWave;
   if (r0 >= n_rays) return;
   const int64_t r = r0 + ln;
-  int64_t si = 0, so = 0;
-  int32_t cnt = 0;
+  int32_t si = 0, so = 0, cnt = 0;
   if (r < n_rays) {
     const int2 a = reinterpret_cast<const int2*>(info_in)[r];
     const int2 b = reinterpret_cast<const int2*>(info_out)[r];
@@ -109,18 +117,54 @@ __global__ __launch_bounds__(kWave* kGatherWaves) void gather_prefix_kernel(
     so = b.x;
     cnt = min(b.y, a.y);
     // rows that would read or write out of range copy nothing
-    if (a.x < 0 || b.x < 0 || cnt < 0 || si + cnt > n_in || so + cnt > capacity) cnt = 0;
+    if (a.x < 0 || b.x < 0 || cnt < 0 || (int64_t)si + cnt > n_in ||
+        (int64_t)so + cnt > capacity)
+      cnt = 0;
   }
-  const int nr = (int)min<int64_t>(kWave, n_rays - r0);
-  for (int l = 0; l < nr; ++l) {
-    const int32_t c = __shfl(cnt, l, kWave);
-    if (c == 0) continue;
-    const int64_t a = __shfl((long long)si, l, kWave);
-    const int64_t o = __shfl((long long)so, l, kWave);
-    for (int32_t j = ln; j < c; j += kWave) {
-      t0o[o + j] = t0[a + j];
-      t1o[o + j] = t1[a + j];
-      if (rido) rido[o + j] = (int32_t)(r0 + l);
+  // output span of the wave's non-empty rows
+  const int64_t lo = wave_min(cnt > 0 ? (int64_t)so : INT64_MAX);
+  if (lo == INT64_MAX) return;
+  const int64_t hi = wave_max(cnt > 0 ? (int64_t)so + cnt : INT64_MIN);
+  int carry = -1;  // lane of the ray covering the position before the chunk
+  for (int64_t base = lo; base < hi; base += (int64_t)kWave * kGatherUnroll) {
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) marks[wv][u][ln] = -1;
+    wave_sync();
+    {
+      const int64_t d = (int64_t)so - base;
+      if (cnt > 0 && d >= 0 && d < (int64_t)kWave * kGatherUnroll)
+        marks[wv][d / kWave][d % kWave] = ln;
+    }
+    wave_sync();
+    int ray[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      int m = max_scan_incl(marks[wv][u][ln]);
+      if (m < 0) m = carry;
+      ray[u] = m;
+      carry = readlane(m, kWave - 1);
+    }
+    float v0[kGatherUnroll], v1[kGatherUnroll];
+    bool on[kGatherUnroll];
+    int64_t pos[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const int q = ray[u] < 0 ? 0 : ray[u];
+      const int32_t so_r = __shfl(so, q, kWave), si_r = __shfl(si, q, kWave),
+                    c_r = __shfl(cnt, q, kWave);
+      const int64_t p = base + (int64_t)kWave * u + ln;
+      pos[u] = p;
+      on[u] = ray[u] >= 0 && p < (int64_t)so_r + c_r;
+      const int64_t src = (int64_t)si_r + (p - so_r);
+      v0[u] = on[u] ? t0[src] : 0.0f;
+      v1[u] = on[u] ? t1[src] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      if (!on[u]) continue;
+      t0o[pos[u]] = v0[u];
+      t1o[pos[u]] = v1[u];
+      if (rido) rido[pos[u]] = (int32_t)(r0 + ray[u]);
     }
   }
 }

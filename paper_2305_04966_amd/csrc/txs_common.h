@@ -102,4 +102,19 @@ __device__ __forceinline__ double readlane(double v, int l) {
 // hardware already executes one wave's LDS operations in order.
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
+// Inclusive max over lanes <= this one: DPP row shifts inside each 16-lane row,
+// then the three row carries by readlane.
+__device__ __forceinline__ int max_scan_incl(int v) {
+  const int ri = lane() & 15, row = lane() >> 4;
+  int t;
+  t = dpp<kRowShr1>(v, v); if (ri >= 1) v = max(v, t);
+  t = dpp<kRowShr2>(v, v); if (ri >= 2) v = max(v, t);
+  t = dpp<kRowShr4>(v, v); if (ri >= 4) v = max(v, t);
+  t = dpp<kRowShr8>(v, v); if (ri >= 8) v = max(v, t);
+  const int e0 = readlane(v, 15), e1 = readlane(v, 31), e2 = readlane(v, 47);
+  const int c1 = e0, c2 = max(c1, e1), c3 = max(c2, e2);
+  const int c = row == 1 ? c1 : row == 2 ? c2 : row == 3 ? c3 : v;
+  return max(v, c);
+}
+
 }  // namespace txs

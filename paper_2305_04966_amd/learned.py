@@ -12,13 +12,13 @@ library:
     -> mlp_pack
 
 Targets come from the plain occupancy-grid renderer (march, filter, field,
-render with weights), computed by `grid_targets`.  Only argument plumbing
+render with weights), computed by `grid_render`.  Only argument plumbing
 lives here.
 """
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import Optional
 
 import torch
@@ -70,7 +70,6 @@ class ProposalEstimator:
     m: Optional[torch.Tensor] = None
     v: Optional[torch.Tensor] = None
     workspace: Optional[torch.Tensor] = None
-    _bins: dict = field(default_factory=dict)
 
     def __post_init__(self):
         self.spec = ops.MlpSpec(self.params, self.hidden, self.scale, self.contract).repack()
@@ -93,7 +92,7 @@ class ProposalEstimator:
     @staticmethod
     def dense_intervals(edges):
         """(t0, t1) [N*n_bins] of dense bins."""
-        return edges[:, :-1].contiguous().view(-1), edges[:, 1:].contiguous().view(-1)
+        return ops.edges_to_intervals(edges)
 
     def loss_and_grad(self, rays_o, rays_d, edges, target: GridRender, t0=None, t1=None):
         """Mean PDF-matching loss and its gradient w.r.t. the parameters."""
@@ -123,3 +122,19 @@ class ProposalEstimator:
         loss, grad = self.loss_and_grad(rays_o, rays_d, edges, target, t0, t1)
         self.apply(grad, lr)
         return loss
+
+
+def proposal_render(est: ProposalEstimator, rays_o, rays_d, edges, n_out, field_fn, keep=False):
+    """Render with the learned sampler: proposal density on `edges` -> inverse
+    CDF to n_out intervals -> field_fn(rays_o, rays_d, t0, t1, n_out) ->
+    (sigma, rgb) -> render forward.  Returns (rgb, opacity, depth), or with
+    keep=True (edges_out, t0, t1, sigma, rgb, optical_depth) for a backward."""
+    n = edges.shape[0]
+    e = est.sample(rays_o, rays_d, edges, n_out)
+    t0, t1 = ProposalEstimator.dense_intervals(e)
+    sig, rgb = field_fn(rays_o, rays_d, t0, t1, n_out)
+    out = ops.render_fwd(None, t0, t1, sig, rgb, n_rays=n, fixed_count=n_out,
+                         want_optical_depth=keep)
+    if keep:
+        return e, t0, t1, sig, rgb, out[4]
+    return out[0], out[1], out[2]

@@ -108,11 +108,13 @@ def mlp_case(txs, H, n_rays, n_bins, contract, seed):
 
 def assert_grad_close(got, ref, mag, name):
     # The two sides round the same operands to bf16 but sum in different orders
-    # (fp32 matrix cores vs binary64); a flipped bf16 rounding or ReLU mask moves
-    # one term by about one bf16 ulp.  Scale: the sum of |term| per parameter.
+    # (fp32 matrix cores vs binary64) and evaluate the features differently, so
+    # an operand's bf16 rounding can flip: that moves the operand by one bf16 ulp
+    # (at most 2^-8 of it), and a term whose two operands both flip by at most
+    # 2 x 2^-8 of the term.  Scale: the sum of |term| per parameter.
     err = np.abs(got.astype(np.float64) - ref) / (mag + 1e-30)
     q = np.quantile(err, 0.999)
-    assert q <= 2.0 ** -8, (name, q, err.max())
+    assert q <= 2.0 ** -7, (name, q, err.max())
     assert err.max() <= 2.0 ** -4, (name, int(err.argmax()), err.max())
     # global: against the magnitudes, not |grad| -- with random-sign upstream
     # gradients over N points the gradient itself is ~sqrt(N) times smaller
@@ -224,3 +226,12 @@ def test_adam_step(gpu_lib):
         rp, rm, rv = oracle.adam(rp, rm, rv, grad, lr=1e-2, step=step)
     np.testing.assert_allclose(host(P), rp, rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(host(M), rm, rtol=1e-5, atol=1e-7)
+
+
+def test_edges_to_intervals(gpu_lib):
+    g = scenes.rng(33)
+    for n_rays, n in ((1, 1), (37, 5), (1000, 192)):
+        e = np.sort(g.uniform(0, 10, (n_rays, n + 1)), 1).astype(np.float32)
+        t0, t1 = gpu_lib.edges_to_intervals(dev(e))
+        assert np.array_equal(host(t0), e[:, :-1].ravel())
+        assert np.array_equal(host(t1), e[:, 1:].ravel())

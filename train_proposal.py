@@ -4,18 +4,20 @@ The unbounded scene (64 blobs and a background shell, 4 nested 128^3 grids,
 8 cameras of 512x256 = 2^20 rays).  Steps:
 
 1. Judge and targets: the plain grid renderer (march, no-gradient filter at
-   T < 1e-4, field, render with weights) on every ray.  Its colours judge the
-   learned sampler; its weights are the PDF-matching targets.
+   T < 1e-4, field, render with weights).  Its colours judge the learned
+   sampler; its weights are the PDF-matching targets.
 2. Train the proposal network (hidden 128, contracted Fourier encoding) for
-   --steps Adam steps on all rays (full batch), lr cosine 1e-2 -> 1e-4, on
-   128 uniform bins per ray over the chord through the outermost grid cube.
+   `steps` Adam steps, full batch over the training rays (every
+   `train_stride`-th ray), lr cosine 1e-2 -> 1e-4, on 128 uniform bins per ray
+   over the chord through the outermost grid cube.
 3. Sweep the number of final samples drawn from the proposal by inverse CDF;
-   render the field on them; mean |rgb - judge| over all rays and channels,
-   for the trained and the untrained network.
+   render the field on them; mean |rgb - judge| over all evaluation rays and
+   channels, for the trained and the untrained network.
 4. Time both samplers end to end (fwd + bwd, field stand-in included on both
    sides) at the smallest sample count within the error bar.
 
-Prints one JSON line; --save writes the trained parameters (.npy).
+`python train_proposal.py` prints one JSON line; --save writes the trained
+parameters (.npy).
 """
 from __future__ import annotations
 
@@ -31,107 +33,108 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--hidden", type=int, default=128)
-    ap.add_argument("--bins", type=int, default=128)
-    ap.add_argument("--ray-stride", type=int, default=1, help="train/evaluate every k-th ray")
-    ap.add_argument("--sweep", default="32,48,64,96,128,192,256")
-    ap.add_argument("--err-bar", type=float, default=1e-3)
-    ap.add_argument("--lr0", type=float, default=1e-2)
-    ap.add_argument("--lr1", type=float, default=1e-4)
-    ap.add_argument("--log-every", type=int, default=50)
-    ap.add_argument("--time-reps", type=int, default=5)
-    ap.add_argument("--oracle-every", type=int, default=0,
-                    help="check the judge against the FP64 oracle on every k-th ray (0 = skip)")
-    ap.add_argument("--save", default="")
-    return ap.parse_args()
+def _timed(torch, fn, reps):
+    """Mean ms of fn over reps calls (HIP events on the current stream)."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
 
-def main():
-    args = parse()
+def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
+        sweep=(32, 48, 64, 96, 128, 192, 256), err_bar=1e-3, lr0=1e-2, lr1=1e-4,
+        log_every=50, time_reps=5, oracle_every=0, untrained=True, log=print):
     import torch
 
     import paper_2305_04966_amd as txs
     import scenes
-    from paper_2305_04966_amd.learned import ProposalEstimator, cosine_lr, grid_render
+    from paper_2305_04966_amd.learned import (ProposalEstimator, cosine_lr, grid_render,
+                                              proposal_render)
 
     txs.load()
     w = scenes.unbounded()
-    idx = np.arange(0, w.n_rays, args.ray_stride)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    o, d = dev(w.rays_o[idx]), dev(w.rays_d[idx])
-    N = len(idx)
     grid = txs.GridSpec(dev(w.bits.view(np.int32)), w.res, w.n_levels, (0.0, 0.0, 0.0),
                         w.half_extent0)
     fp = dev(w.fld.packed_params().astype(np.float32))
     nb = w.fld.n_blobs
-    rec = {"workload": f"unbounded: 64 blobs + shell, 4x128^3 cascade, {N} rays",
-           "hidden": args.hidden, "bins": args.bins, "steps": args.steps}
+    field = lambda o, d, t0, t1, n: txs.blob_field(fp, nb, o, d, t0, t1, fixed_count=n)
 
-    # 1. judge + targets
+    ev = np.arange(0, w.n_rays, ray_stride)
+    tr = np.arange(0, w.n_rays, train_stride)
+    o, d = dev(w.rays_o[ev]), dev(w.rays_d[ev])
+    ot, dt = dev(w.rays_o[tr]), dev(w.rays_d[tr])
+    N = len(ev)
+    rec = {"workload": f"unbounded: 64 blobs + shell, 4x128^3 cascade, 8 cameras; "
+                       f"{N} evaluation rays, {len(tr)} training rays",
+           "hidden": hidden, "bins": bins, "train_steps": steps, "err_bar": err_bar}
+
+    # 1. judge (evaluation rays) and targets (training rays)
     judge = grid_render(grid, o, d, fp, nb, dt0=w.dt0, t_min=w.t_min)
+    target = judge if train_stride == ray_stride else grid_render(grid, ot, dt, fp, nb,
+                                                                  dt0=w.dt0, t_min=w.t_min)
     torch.cuda.synchronize()
     rec["grid_samples"] = judge.samples.n_samples
-    print(f"[judge] {N} rays, {judge.samples.n_samples} grid samples", flush=True)
-    if args.oracle_every > 0:
+    log(f"[judge] {N} rays, {judge.samples.n_samples} grid samples")
+    if oracle_every > 0:
         import oracle
-        k = np.arange(0, N, args.oracle_every)
-        oo, od_ = w.rays_o[idx][k], w.rays_d[idx][k]
+        k = np.arange(0, N, oracle_every)
+        oo, od_ = w.rays_o[ev][k], w.rays_d[ev][k]
+        p = w.fld.packed_params()
         m = oracle.march(oo, od_, w.bits, w.res, n_levels=w.n_levels,
                          half_extent0=w.half_extent0, dt0=w.dt0)
-        s_ng, _ = oracle.field_at_samples(oo, od_, m["t0"], m["t1"], m["ray_id"],
-                                          w.fld.packed_params())
+        s_ng, _ = oracle.field_at_samples(oo, od_, m["t0"], m["t1"], m["ray_id"], p)
         kept, _ = oracle.transmittance_prefix(m["packed_info"], m["t0"], m["t1"],
                                               s_ng.astype(np.float32), w.t_min)
         info, t0o, t1o, rido = oracle.gather_prefix(m["packed_info"], kept, m["t0"], m["t1"],
                                                     m["ray_id"])
-        s, c = oracle.field_at_samples(oo, od_, t0o, t1o, rido, w.fld.packed_params())
+        s, c = oracle.field_at_samples(oo, od_, t0o, t1o, rido, p)
         ref = oracle.render_fwd(info, t0o, t1o, s.astype(np.float32), c.astype(np.float32))
         rec["judge_vs_oracle_max_abs"] = float(np.abs(judge.rgb.cpu().numpy()[k]
                                                       - ref["rgb"]).max())
 
     # 2. train
-    edges = txs.uniform_bins(grid, o, d, args.bins)
-    est = ProposalEstimator(dev(scenes.mlp_init(args.hidden)), args.hidden, scale=1.5,
-                            contract=True)
-    t0d, t1d = est.dense_intervals(edges)
+    edges = txs.uniform_bins(grid, o, d, bins)
+    edges_t = edges if train_stride == ray_stride else txs.uniform_bins(grid, ot, dt, bins)
+    est = ProposalEstimator(dev(scenes.mlp_init(hidden)), hidden, scale=1.5, contract=True)
 
-    def evaluate(n_out):
-        e = est.sample(o, d, edges, n_out)
-        a, b = est.dense_intervals(e)
-        sig, rgb = txs.blob_field(fp, nb, o, d, a, b, fixed_count=n_out)
-        out = txs.render_fwd(None, a, b, sig, rgb, n_rays=N, fixed_count=n_out)
-        return float((out[0] - judge.rgb).abs().mean())
+    def err(n_out):
+        rgb = proposal_render(est, o, d, edges, n_out, field)[0]
+        return float((rgb - judge.rgb).abs().mean())
 
-    sweep = [int(s) for s in args.sweep.split(",")]
-    rec["untrained_err"] = {n: evaluate(n) for n in sweep}
+    if untrained:
+        rec["untrained_err"] = {n: err(n) for n in sweep}
+    t0d, t1d = est.dense_intervals(edges_t)
     losses = []
     torch.cuda.synchronize()
     t_train = time.perf_counter()
-    for step in range(1, args.steps + 1):
-        loss = est.train_step(o, d, edges, judge, cosine_lr(step, args.steps, args.lr0, args.lr1),
+    for step in range(1, steps + 1):
+        loss = est.train_step(ot, dt, edges_t, target, cosine_lr(step, steps, lr0, lr1),
                               t0d, t1d)
-        if step == 1 or step % args.log_every == 0 or step == args.steps:
+        if step == 1 or step % log_every == 0 or step == steps:
             lm = float(loss.mean())
             losses.append((step, lm))
-            print(f"[train] step {step} loss {lm:.6g} {time.perf_counter() - t_train:.1f} s",
-                  flush=True)
+            log(f"[train] step {step} loss {lm:.6g} {time.perf_counter() - t_train:.1f} s")
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t_train
     rec["train_s"] = train_s
-    rec["ms_per_train_step"] = 1000.0 * train_s / max(args.steps, 1)
+    rec["ms_per_train_step"] = 1000.0 * train_s / max(steps, 1)
     rec["loss"] = losses
-    rec["trained_err"] = {n: evaluate(n) for n in sweep}
-    print(f"[eval] untrained {rec['untrained_err']} trained {rec['trained_err']}", flush=True)
-    ok = [n for n in sweep if rec["trained_err"][n] <= args.err_bar]
+    rec["trained_err"] = {n: err(n) for n in sweep}
+    log(f"[eval] trained {rec['trained_err']}")
+    ok = [n for n in sweep if rec["trained_err"][n] <= err_bar]
     n_star = min(ok) if ok else max(sweep)
     rec["n_final"] = n_star
     rec["within_err_bar"] = bool(ok)
 
     # 4. timing, fwd + bwd, field included on both sides
-    g_rgb = dev(w.grads[idx])
+    g_rgb = dev(w.grads[ev])
 
     def grid_step():
         p = txs.march(grid, o, d, dt0=w.dt0)
@@ -142,26 +145,42 @@ def main():
         txs.render_bwd(q.packed_info, q.t0, q.t1, sg, rgb, g_rgb, optical_depth=out[4])
 
     def learned_step():
-        e0 = txs.uniform_bins(grid, o, d, args.bins)
-        e = est.sample(o, d, e0, n_star)
-        a, b = est.dense_intervals(e)
-        sg, rgb = txs.blob_field(fp, nb, o, d, a, b, fixed_count=n_star)
-        out = txs.render_fwd(None, a, b, sg, rgb, n_rays=N, fixed_count=n_star,
-                             want_optical_depth=True)
+        e0 = txs.uniform_bins(grid, o, d, bins)
+        _, a, b, sg, rgb, od = proposal_render(est, o, d, e0, n_star, field, keep=True)
         txs.render_bwd(None, a, b, sg, rgb, g_rgb, n_rays=N, fixed_count=n_star,
-                       optical_depth=out[4])
+                       optical_depth=od)
 
     for name, fn in (("grid", grid_step), ("learned", learned_step)):
-        fn()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.time_reps):
-            fn()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / args.time_reps
-        rec[f"{name}_ms"] = 1000.0 * dt
-        rec[f"{name}_rays_per_s"] = N / dt
+        ms = _timed(torch, fn, time_reps)
+        rec[f"{name}_ms"] = ms
+        rec[f"{name}_rays_per_s"] = N / (ms * 1e-3)
     rec["learned_over_grid"] = rec["learned_rays_per_s"] / rec["grid_rays_per_s"]
+    return rec, est
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--hidden", type=int, default=128)
+    ap.add_argument("--bins", type=int, default=128)
+    ap.add_argument("--ray-stride", type=int, default=1, help="evaluate every k-th ray")
+    ap.add_argument("--train-stride", type=int, default=1, help="train on every k-th ray")
+    ap.add_argument("--sweep", default="32,48,64,96,128,192,256")
+    ap.add_argument("--err-bar", type=float, default=1e-3)
+    ap.add_argument("--lr0", type=float, default=1e-2)
+    ap.add_argument("--lr1", type=float, default=1e-4)
+    ap.add_argument("--log-every", type=int, default=50)
+    ap.add_argument("--time-reps", type=int, default=5)
+    ap.add_argument("--oracle-every", type=int, default=0,
+                    help="check the judge against the FP64 oracle on every k-th ray (0 = skip)")
+    ap.add_argument("--save", default="")
+    args = ap.parse_args()
+    rec, est = run(steps=args.steps, hidden=args.hidden, bins=args.bins,
+                   ray_stride=args.ray_stride, train_stride=args.train_stride,
+                   sweep=[int(s) for s in args.sweep.split(",")], err_bar=args.err_bar,
+                   lr0=args.lr0, lr1=args.lr1, log_every=args.log_every,
+                   time_reps=args.time_reps, oracle_every=args.oracle_every,
+                   log=lambda s: print(s, flush=True))
     if args.save:
         np.save(args.save, est.params.cpu().numpy())
     print(json.dumps(rec), flush=True)
