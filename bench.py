@@ -140,6 +140,19 @@ def gpu_bench(args, w):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    # live reference: a plain 1 GiB device copy (reads and writes 1 GiB)
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    stats["copy_GBps"] = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
     if args.copy_mib > 0:  # known-size copy: reads and writes copy_mib MiB once each
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -259,7 +272,8 @@ def main():
         "kernels_ms": {k: round(v[0], 4) for k, v in ker.items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom), "alg_bytes_per_launch": bytes_launch},
+                     "traffic": measured_traffic(dom), "alg_bytes_per_launch": bytes_launch,
+                     "device_copy_GBps": st["copy_GBps"]},
     }
     if args.learned_steps > 0:
         rec["learned_vs_grid"] = learned_vs_grid(args)

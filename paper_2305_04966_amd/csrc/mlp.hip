@@ -34,7 +34,7 @@ struct ParamOffsets {
 };
 
 // Packed operand tiles (bf16), each tile = 64 lanes x 8 values:
-//   A1[m][s]  layer 1 (W1), m < H/16, s < 2
+//   A1[m][s]  layer 1 (W1; b1 in the constant-1 slots), m < H/16, s < 2
 //   A2[m][s]  layer 2 (W2), s < H/32
 //   A2t[m][s] layer 2 transposed (W2^T, for the adjoint), s < H/32
 //   w3 (H values, unit order)
@@ -46,7 +46,8 @@ struct PackOffsets {
 };
 
 // Feature slot q (0..15) of lane group g: q < 12 -> sin/cos of octave q/2 of
-// axis g, q = 12 -> x_hat_g, otherwise unused.  Canonical feature index or -1.
+// axis g, q = 12 -> x_hat_g; slots 13..15 of group 0 hold the constant 1 that
+// carries the layer-1 bias, the rest are zero.  Canonical feature index or -1.
 __host__ __device__ inline int feature_of(int g, int q) {
   if (g > 2) return -1;
   if (q < 12) return 3 + 12 * g + q;
@@ -68,8 +69,17 @@ __global__ void pack_kernel(const float* __restrict__ p, int H, __bf16* __restri
   if (e < ko.A2) {  // A1[m][s][lane][i]
     const int64_t t = e / 512, r = e % 512;
     const int m = (int)(t / 2), s = (int)(t % 2), l = (int)(r / 8), i = (int)(r % 8);
-    const int f = feature_of(l / 16, 8 * s + i);
-    v = f >= 0 ? p[po.W1 + (int64_t)(16 * m + l % 16) * kNF + f] : 0.0f;
+    const int q = 8 * s + i, f = feature_of(l / 16, q);
+    const int row = 16 * m + l % 16;
+    if (f >= 0) {
+      v = p[po.W1 + (int64_t)row * kNF + f];
+    } else if (l / 16 == 0 && q >= 13) {
+      // b1 as three bf16 pieces (hi + mid + lo = b1 to binary32 precision),
+      // multiplied by the constant-1 feature slots 13..15 of lane group 0
+      const float b = p[po.b1 + row];
+      const float hi = (float)(__bf16)b, mid = (float)(__bf16)(b - hi);
+      v = q == 13 ? hi : q == 14 ? mid : (b - hi) - mid;
+    }
   } else if (e < ko.A2t) {  // A2[m][s][lane][i] = W2[out][in]
     const int64_t t = (e - ko.A2) / 512, r = (e - ko.A2) % 512;
     const int m = (int)(t / (H / 32)), s = (int)(t % (H / 32)), l = (int)(r / 8), i = (int)(r % 8);
@@ -93,6 +103,8 @@ struct FwdArgs {
   const float* ro;
   const float* rd;
   int32_t n_rays, n_bins;
+  FastDiv bins_div;   // division by n_bins
+  int32_t small;      // n_rays * n_bins < 2^32: point -> ray by FastDiv
   const float* edges;
   float* sigma;
 };
@@ -104,14 +116,24 @@ __device__ __forceinline__ bf16x8 pack8(const float (&v)[8]) {
   return r;
 }
 
+// softplus(z) = log(1 + e^z): e = 2^(z log2 e) by the hardware exp2; for
+// e < 1/16 the series e (1 - e/2 + e^2/3 - e^3/4 + e^4/5) (truncation < 2e-7
+// relative), else log2(1 + e) ln 2 (rounding of 1 + e costs < 1e-6 relative).
 __device__ __forceinline__ float softplus(float z) {
-  return z > 20.0f ? z : log1pf(expf(z));
+  if (z > 20.0f) return z;
+  const float e = __builtin_amdgcn_exp2f(z * 1.44269504f);
+  if (e < 0.0625f)
+    return e * (1.0f - e * (0.5f - e * (1.0f / 3.0f - e * (0.25f - e * 0.2f))));
+  return __builtin_amdgcn_logf(1.0f + e) * 0.693147181f;
 }
 
 // x_hat of a bin midpoint: x / scale, optionally contracted into the unit ball
 template <class Args>
 __device__ __forceinline__ void encode_point(const Args& a, int64_t p, float (&y)[3]) {
-  const int64_t r = p / a.n_bins, j = p - r * a.n_bins;
+  int64_t r;
+  if (a.small) r = a.bins_div.div((uint32_t)p);
+  else r = p / a.n_bins;
+  const int64_t j = p - r * a.n_bins;
   const float* e = a.edges + r * (a.n_bins + 1) + j;
   const float tm = 0.5f * (e[0] + e[1]);
 #pragma unroll
@@ -130,7 +152,8 @@ __device__ __forceinline__ void encode_point(const Args& a, int64_t p, float (&y
 // cos at x/2 + 1/4); each further octave by the double-angle identities
 // sin 2a = 2 sin a cos a, cos 2a = 1 - 2 sin^2 a (absolute error grows about
 // 2x per octave: ~1e-6 at octave 5, far below a bf16 step).
-__device__ __forceinline__ void features(float xa, bool in_range, bf16x8& b0, bf16x8& b1) {
+__device__ __forceinline__ void features(float xa, int g, bool in_range, bf16x8& b0,
+                                         bf16x8& b1) {
   float f[16];
   float sn = __builtin_amdgcn_sinf(0.5f * xa);
   float cs = __builtin_amdgcn_sinf(0.5f * xa + 0.25f);
@@ -146,7 +169,7 @@ __device__ __forceinline__ void features(float xa, bool in_range, bf16x8& b0, bf
     f[2 * k + 1] = cs;
   }
   f[12] = xa;
-  f[13] = f[14] = f[15] = 0.0f;
+  f[13] = f[14] = f[15] = g == 0 ? 1.0f : 0.0f;
   if (!in_range) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) f[q] = 0.0f;
@@ -210,7 +233,7 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
       float y[3] = {0.0f, 0.0f, 0.0f};
       if (valid[t]) encode_point(a, p, y);
       const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
-      features(xa, g < 3, B1[t][0], B1[t][1]);
+      features(xa, g, g < 3, B1[t][0], B1[t][1]);
     }
     // layer 1; B operand of layer 2's K-step s = fragments 2s and 2s+1
     bf16x8 B2[NT][KS];
@@ -221,11 +244,10 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
       for (int h = 0; h < 2; ++h) {
         const int m = 2 * s + h;
         const bf16x8 w0 = sA1[(m * 2 + 0) * 64 + ln], w1 = sA1[(m * 2 + 1) * 64 + ln];
-        const f32x4 bias = {sb1[16 * m + 4 * g], sb1[16 * m + 4 * g + 1], sb1[16 * m + 4 * g + 2],
-                            sb1[16 * m + 4 * g + 3]};
+        const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};  // b1 arrives through K
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, B1[t][0], bias, 0, 0, 0);
+          f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, B1[t][0], zero, 0, 0, 0);
           hh[t][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, B1[t][1], c, 0, 0, 0);
         }
       }
@@ -306,6 +328,8 @@ struct BwdArgs {
   const float* ro;
   const float* rd;
   int32_t n_rays, n_bins;
+  FastDiv bins_div;   // division by n_bins
+  int32_t small;      // n_rays * n_bins < 2^32: point -> ray by FastDiv
   const float* edges;
   const float* d_sigma;
   float* partial;  // [gridDim.x][param count]
@@ -374,7 +398,7 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
       float y[3] = {0.0f, 0.0f, 0.0f};
       if (valid) encode_point(a, p, y);
       const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
-      features(xa, g < 3 && valid, B1[0], B1[1]);
+      features(xa, g, g < 3 && valid, B1[0], B1[1]);
       if (g < 3) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) sG[(16 * g + q) * RS + pc] = B1[q / 8][q % 8];
@@ -387,9 +411,8 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int m = 2 * s + h;
-        const f32x4 bias = {sb1[16 * m + 4 * g], sb1[16 * m + 4 * g + 1], sb1[16 * m + 4 * g + 2],
-                            sb1[16 * m + 4 * g + 3]};
-        f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA1[(m * 2 + 0) * 64 + ln], B1[0], bias,
+        const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};  // b1 arrives through K
+        f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA1[(m * 2 + 0) * 64 + ln], B1[0], zero,
                                                            0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA1[(m * 2 + 1) * 64 + ln], B1[1], c, 0, 0, 0);
         hh[h] = c;
@@ -587,7 +610,8 @@ extern "C" txs_status txs_prop_mlp_fwd(const txs_mlp* mlp, const float* rays_o,
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && edges && sigma, "txs_prop_mlp_fwd: null array");
   FwdArgs a{static_cast<const __bf16*>(mlp->packed), mlp->params, 1.0f / mlp->scale,
-            mlp->contract, rays_o, rays_d, n_rays, n_bins, edges, sigma};
+            mlp->contract, rays_o, rays_d, n_rays, n_bins, FastDiv((uint32_t)n_bins),
+            (int64_t)n_rays * n_bins < ((int64_t)1 << 32), edges, sigma};
   const int64_t n_tiles = ((int64_t)n_rays * n_bins + 15) / 16;
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -635,8 +659,8 @@ extern "C" txs_status txs_prop_mlp_bwd(const txs_mlp* mlp, const float* rays_o,
                 "txs_prop_mlp_bwd: workspace of %zu bytes, need %zu", workspace_bytes,
                 txs_mlp_bwd_workspace_size(H));
     BwdArgs a{static_cast<const __bf16*>(mlp->packed), mlp->params, 1.0f / mlp->scale,
-              mlp->contract, rays_o, rays_d, n_rays, n_bins, edges, d_sigma,
-              static_cast<float*>(workspace)};
+              mlp->contract, rays_o, rays_d, n_rays, n_bins, FastDiv((uint32_t)n_bins),
+              n_points < ((int64_t)1 << 32), edges, d_sigma, static_cast<float*>(workspace)};
     if (H == 64)
       hipLaunchKernelGGL(mlp_bwd_kernel<64>, dim3(blocks), dim3(256), 0, as_stream(stream), a);
     else

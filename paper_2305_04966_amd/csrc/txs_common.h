@@ -98,6 +98,27 @@ __device__ __forceinline__ double readlane(double v, int l) {
                           __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
+// Unsigned 32-bit division by a divisor d >= 1 fixed at launch, by a
+// multiply-high and two shifts (Granlund and Montgomery 1994, Sec. 4): with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, t = mulhi(m, n),
+// n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0) for every n < 2^32.
+struct FastDiv {
+  uint32_t m = 1;
+  int s1 = 0, s2 = 0;
+  FastDiv() = default;
+  __host__ __device__ explicit FastDiv(uint32_t d) {
+    int l = 0;
+    while (l < 32 && ((uint64_t)1 << l) < d) ++l;
+    m = (uint32_t)(((((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d) + 1);
+    s1 = l < 1 ? l : 1;
+    s2 = l > 1 ? l - 1 : 0;
+  }
+  __host__ __device__ uint32_t div(uint32_t n) const {
+    const uint32_t t = (uint32_t)(((uint64_t)m * n) >> 32);
+    return (t + ((n - t) >> s1)) >> s2;
+  }
+};
+
 // Keeps the compiler from moving memory operations across this point; the
 // hardware already executes one wave's LDS operations in order.
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
