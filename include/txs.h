@@ -220,6 +220,16 @@ txs_status txs_resample(int32_t n_rays, int32_t n_bins, const float* edges, cons
                         void* stream);
 
 /*
+ * txs_resample with the n_out intervals between consecutive output edges
+ * written in the dense layout of the renderer and the field instead of the
+ * edges: out_t0[r*n_out + k] = edge k, out_t1[r*n_out + k] = edge k+1
+ * (float [n_rays*n_out] each).  Same arguments, rules and errors otherwise.
+ */
+txs_status txs_resample_intervals(int32_t n_rays, int32_t n_bins, const float* edges,
+                                  const float* vals, int32_t mode, int32_t n_out, const float* u,
+                                  float* out_t0, float* out_t1, void* stream);
+
+/*
  * Uniform estimator (Table 1, first row): n_bins+1 equally spaced edges per
  * ray over its chord through the outermost cube of `grid` (bits unused),
  *   e_k = t_near + (t_far - t_near) * (k / n_bins),   out: float [n_rays, n_bins+1].

@@ -52,6 +52,7 @@ SIGNATURES = {
     "txs_render_bwd": (I32, [P, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P, P]),
     "txs_weights_bwd": (I32, [P, I32, I32, I64, P, P, P, P, P, P, P]),
     "txs_resample": (I32, [I32, I32, P, P, I32, I32, P, P, P]),
+    "txs_resample_intervals": (I32, [I32, I32, P, P, I32, I32, P, P, P, P]),
     "txs_uniform_bins": (I32, [GP, F32, F32, P, P, I32, I32, P, P]),
     "txs_edges_to_intervals": (I32, [P, I32, I32, P, P, P]),
     "txs_blob_field": (I32, [P, I32, P, P, I32, P, P, P, I32, I64, P, P, P]),

@@ -285,6 +285,30 @@ __device__ __forceinline__ void load_rgb_staged(const float* __restrict__ src, i
   wave_sync();
 }
 
+// The second half of load_rgb_staged, for rows already loaded as
+// consecutive-lane float4s (rg[q] = float4 q*64 + lane of the window).
+__device__ __forceinline__ void unstage_rgb(const float4 (&rg)[3 * K / 4], float4* stage,
+                                            float (&c)[K][3]) {
+  const int ln = lane();
+#pragma unroll
+  for (int q = 0; q < 3 * K / 4; ++q) stage[q * kWave + ln] = rg[q];
+  wave_sync();
+  float f[3 * K];
+#pragma unroll
+  for (int q = 0; q < 3 * K / 4; ++q) {
+    const float4 x = stage[(3 * K / 4) * ln + q];
+    f[4 * q] = x.x;
+    f[4 * q + 1] = x.y;
+    f[4 * q + 2] = x.z;
+    f[4 * q + 3] = x.w;
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
+    for (int c3 = 0; c3 < 3; ++c3) c[j][c3] = f[3 * j + c3];
+  wave_sync();
+}
+
 // Writes the staged [W][3] rows to dst rows [p, p+W) as consecutive-lane float4s.
 __device__ __forceinline__ void store_rgb_staged(float* __restrict__ dst, int64_t p,
                                                  const float4* stage) {

@@ -15,10 +15,12 @@ constexpr int kRsWaves = 4;
 
 // One wave per ray: wave-wide scan of the bin masses into the CDF, kept in
 // LDS, then one binary search per output edge.
+// out != NULL: edges [n_rays, n_out+1]; otherwise the intervals between them,
+// t0o[r*n_out + k] = edge k and t1o[r*n_out + k] = edge k+1.
 __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(
     int32_t n_rays, int32_t n_bins, const float* __restrict__ edges,
     const float* __restrict__ vals, int32_t mode, int32_t n_out, const float* __restrict__ u,
-    float* __restrict__ out) {
+    float* __restrict__ out, float* __restrict__ t0o, float* __restrict__ t1o) {
   __shared__ float lds_F[kRsWaves][kMaxBins + 1];
   __shared__ float lds_e[kRsWaves][kMaxBins + 1];
   const int w = threadIdx.x / kWave, ln = lane();
@@ -73,7 +75,12 @@ __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(
       const float frac = (up - f0) / (f1 - f0);
       t = e[lo] + frac * (e[lo + 1] - e[lo]);
     }
-    out[r * (n_out + 1) + k] = t;
+    if (out) {
+      out[r * (n_out + 1) + k] = t;
+    } else {
+      if (k < n_out) t0o[r * n_out + k] = t;
+      if (k > 0) t1o[r * n_out + k - 1] = t;
+    }
   }
 }
 
@@ -150,8 +157,30 @@ extern "C" txs_status txs_resample(int32_t n_rays, int32_t n_bins, const float* 
   TXS_REQUIRE(edges && vals && out_edges, "txs_resample: null array");
   const int64_t blocks = ((int64_t)n_rays + kRsWaves - 1) / kRsWaves;
   hipLaunchKernelGGL(resample_kernel, dim3((unsigned)blocks), dim3(kWave * kRsWaves), 0,
-                     as_stream(stream), n_rays, n_bins, edges, vals, mode, n_out, u, out_edges);
+                     as_stream(stream), n_rays, n_bins, edges, vals, mode, n_out, u, out_edges,
+                     nullptr, nullptr);
   return launch_status("txs_resample");
+}
+
+extern "C" txs_status txs_resample_intervals(int32_t n_rays, int32_t n_bins, const float* edges,
+                                             const float* vals, int32_t mode, int32_t n_out,
+                                             const float* u, float* out_t0, float* out_t1,
+                                             void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(n_rays >= 0, "txs_resample_intervals: n_rays < 0");
+  TXS_REQUIRE(n_bins >= 1 && n_bins <= kMaxBins,
+              "txs_resample_intervals: n_bins must be in [1,%d]", kMaxBins);
+  TXS_REQUIRE(n_out >= 1, "txs_resample_intervals: n_out must be >= 1");
+  TXS_REQUIRE(mode == TXS_PDF_SIGMA || mode == TXS_PDF_WEIGHTS,
+              "txs_resample_intervals: bad mode %d", mode);
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(edges && vals && out_t0 && out_t1, "txs_resample_intervals: null array");
+  const int64_t blocks = ((int64_t)n_rays + kRsWaves - 1) / kRsWaves;
+  hipLaunchKernelGGL(resample_kernel, dim3((unsigned)blocks), dim3(kWave * kRsWaves), 0,
+                     as_stream(stream), n_rays, n_bins, edges, vals, mode, n_out, u, nullptr,
+                     out_t0, out_t1);
+  return launch_status("txs_resample_intervals");
 }
 
 extern "C" txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, float far_plane,

@@ -93,18 +93,19 @@ __global__ __launch_bounds__(kScanBlock) void write_packed(const int32_t* __rest
 constexpr int kGatherWaves = 4;
 
 // The wave's 64 rays are copied as one walk over their output positions, 64
-// consecutive positions per chunk (one per lane) and kGatherUnroll chunks in
-// flight: stores are contiguous and coalesced, loads contiguous within a ray.
-// A lane finds the ray of its position from the ray starts that fall in the
-// chunk (marked in LDS, inclusive max scan over lanes) or, failing that, the
-// ray carried from the previous chunk.
+// consecutive positions per chunk (one per lane), kGatherUnroll chunks per
+// step: stores are contiguous and coalesced, loads contiguous within a ray.
+// A chunk that lies inside the ray carried from the previous chunk (the
+// common case: rays are hundreds of samples long) takes a wave-uniform fast
+// path; otherwise each lane finds the ray of its position from the ray starts
+// that fall in the chunk (marked in LDS, inclusive max scan over lanes).
 constexpr int kGatherUnroll = 4;
 
 __global__ __launch_bounds__(kWave* kGatherWaves) void gather_prefix_kernel(
     const int32_t* __restrict__ info_in, const int32_t* __restrict__ info_out, int32_t n_rays,
     int64_t n_in, const float* __restrict__ t0, const float* __restrict__ t1, int64_t capacity,
     float* __restrict__ t0o, float* __restrict__ t1o, int32_t* __restrict__ rido) {
-  __shared__ int marks[kGatherWaves][kGatherUnroll][kWave];
+  __shared__ int marks[kGatherWaves][kWave];
   const int ln = lane(), wv = threadIdx.x / kWave;
   const int64_t r0 = ((int64_t)blockIdx.x * kGatherWaves + wv) * kWave;
   if (r0 >= n_rays) return;
@@ -125,47 +126,66 @@ __global__ __launch_bounds__(kWave* kGatherWaves) void gather_prefix_kernel(
   const int64_t lo = wave_min(cnt > 0 ? (int64_t)so : INT64_MAX);
   if (lo == INT64_MAX) return;
   const int64_t hi = wave_max(cnt > 0 ? (int64_t)so + cnt : INT64_MIN);
-  int carry = -1;  // lane of the ray covering the position before the chunk
-  for (int64_t base = lo; base < hi; base += (int64_t)kWave * kGatherUnroll) {
+  // ray carried into the next chunk (lane index, -1 none) and its row, uniform
+  int cur = -1;
+  int64_t c_so = 0, c_si = 0, c_end = 0;  // c_end = c_so + count
+  int64_t base = lo;
+  while (base < hi) {
+    if (cur >= 0 && c_end > base) {
+      // positions [base, end) all belong to the carried ray (wave-uniform
+      // branch): up to kGatherUnroll chunks with their loads in flight together
+      const int64_t end = min(min(c_end, hi), base + (int64_t)kWave * kGatherUnroll);
+      float v0[kGatherUnroll], v1[kGatherUnroll];
 #pragma unroll
-    for (int u = 0; u < kGatherUnroll; ++u) marks[wv][u][ln] = -1;
+      for (int u = 0; u < kGatherUnroll; ++u) {
+        const int64_t p = base + (int64_t)kWave * u + ln;
+        if (p < end) {
+          const int64_t src = c_si + (p - c_so);
+          v0[u] = t0[src];
+          v1[u] = t1[src];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGatherUnroll; ++u) {
+        const int64_t p = base + (int64_t)kWave * u + ln;
+        if (p < end) {
+          t0o[p] = v0[u];
+          t1o[p] = v1[u];
+          if (rido) rido[p] = (int32_t)(r0 + cur);
+        }
+      }
+      base = end;
+      continue;
+    }
+    // a chunk where rays start (or a gap): ray of each position by lane scan
+    const int64_t p = base + ln;
+    marks[wv][ln] = -1;
     wave_sync();
     {
       const int64_t d = (int64_t)so - base;
-      if (cnt > 0 && d >= 0 && d < (int64_t)kWave * kGatherUnroll)
-        marks[wv][d / kWave][d % kWave] = ln;
+      if (cnt > 0 && d >= 0 && d < kWave) marks[wv][d] = ln;
     }
     wave_sync();
-    int ray[kGatherUnroll];
-#pragma unroll
-    for (int u = 0; u < kGatherUnroll; ++u) {
-      int m = max_scan_incl(marks[wv][u][ln]);
-      if (m < 0) m = carry;
-      ray[u] = m;
-      carry = readlane(m, kWave - 1);
-    }
-    float v0[kGatherUnroll], v1[kGatherUnroll];
-    bool on[kGatherUnroll];
-    int64_t pos[kGatherUnroll];
-#pragma unroll
-    for (int u = 0; u < kGatherUnroll; ++u) {
-      const int q = ray[u] < 0 ? 0 : ray[u];
-      const int32_t so_r = __shfl(so, q, kWave), si_r = __shfl(si, q, kWave),
-                    c_r = __shfl(cnt, q, kWave);
-      const int64_t p = base + (int64_t)kWave * u + ln;
-      pos[u] = p;
-      on[u] = ray[u] >= 0 && p < (int64_t)so_r + c_r;
+    int m = max_scan_incl(marks[wv][ln]);
+    if (m < 0) m = cur;
+    const int q = m < 0 ? 0 : m;
+    const int32_t so_r = __shfl(so, q, kWave), si_r = __shfl(si, q, kWave),
+                  c_r = __shfl(cnt, q, kWave);
+    if (m >= 0 && p < (int64_t)so_r + c_r) {
       const int64_t src = (int64_t)si_r + (p - so_r);
-      v0[u] = on[u] ? t0[src] : 0.0f;
-      v1[u] = on[u] ? t1[src] : 0.0f;
+      t0o[p] = t0[src];
+      t1o[p] = t1[src];
+      if (rido) rido[p] = (int32_t)(r0 + m);
     }
-#pragma unroll
-    for (int u = 0; u < kGatherUnroll; ++u) {
-      if (!on[u]) continue;
-      t0o[pos[u]] = v0[u];
-      t1o[pos[u]] = v1[u];
-      if (rido) rido[pos[u]] = (int32_t)(r0 + ray[u]);
+    // carry the ray of the chunk's last position
+    cur = readlane(m, kWave - 1);
+    if (cur >= 0) {
+      c_so = readlane(so, cur);
+      c_si = readlane(si, cur);
+      c_end = c_so + readlane(cnt, cur);
     }
+    wave_sync();
+    base += kWave;
   }
 }
 

@@ -88,6 +88,11 @@ class ProposalEstimator:
         sig = self.density(rays_o, rays_d, edges)
         return ops.resample(edges, sig, n_out, mode=ops.TXS_PDF_SIGMA, u=u)
 
+    def sample_intervals(self, rays_o, rays_d, edges, n_out, u=None):
+        """The same intervals in the dense layout -> (t0, t1) [N*n_out]."""
+        sig = self.density(rays_o, rays_d, edges)
+        return ops.resample_intervals(edges, sig, n_out, mode=ops.TXS_PDF_SIGMA, u=u)
+
     # ------------------------------------------------------------ update
     @staticmethod
     def dense_intervals(edges):
@@ -123,18 +128,25 @@ class ProposalEstimator:
         self.apply(grad, lr)
         return loss
 
+    def update_every_n_steps(self, step, rays_o, rays_d, edges, target: GridRender, lr, n=1,
+                             t0=None, t1=None):
+        """The estimator update of Algorithm 1: a train step on every n-th
+        training step of the radiance field (returns its loss), else None."""
+        if step % n != 0:
+            return None
+        return self.train_step(rays_o, rays_d, edges, target, lr, t0, t1)
+
 
 def proposal_render(est: ProposalEstimator, rays_o, rays_d, edges, n_out, field_fn, keep=False):
     """Render with the learned sampler: proposal density on `edges` -> inverse
     CDF to n_out intervals -> field_fn(rays_o, rays_d, t0, t1, n_out) ->
     (sigma, rgb) -> render forward.  Returns (rgb, opacity, depth), or with
-    keep=True (edges_out, t0, t1, sigma, rgb, optical_depth) for a backward."""
+    keep=True (t0, t1, sigma, rgb, optical_depth) for a backward."""
     n = edges.shape[0]
-    e = est.sample(rays_o, rays_d, edges, n_out)
-    t0, t1 = ProposalEstimator.dense_intervals(e)
+    t0, t1 = est.sample_intervals(rays_o, rays_d, edges, n_out)
     sig, rgb = field_fn(rays_o, rays_d, t0, t1, n_out)
     out = ops.render_fwd(None, t0, t1, sig, rgb, n_rays=n, fixed_count=n_out,
                          want_optical_depth=keep)
     if keep:
-        return e, t0, t1, sig, rgb, out[4]
+        return t0, t1, sig, rgb, out[4]
     return out[0], out[1], out[2]

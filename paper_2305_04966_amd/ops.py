@@ -15,7 +15,7 @@ from ._lib import TXS_PDF_SIGMA, TXS_PDF_WEIGHTS, Grid, MarchParams, check, load
 
 __all__ = ["GridSpec", "march_count", "exclusive_scan", "march_fill", "transmittance_prefix",
            "gather_prefix", "render_fwd", "render_bwd", "weights_bwd", "resample",
-           "uniform_bins", "edges_to_intervals", "blob_field", "TXS_PDF_SIGMA", "TXS_PDF_WEIGHTS"]
+           "uniform_bins", "edges_to_intervals", "resample_intervals", "blob_field", "TXS_PDF_SIGMA", "TXS_PDF_WEIGHTS"]
 
 
 def _stream():
@@ -235,6 +235,20 @@ def resample(edges, vals, n_out, mode=TXS_PDF_SIGMA, u=None):
     check(load().txs_resample(n, nb1 - 1, _ptr(edges), _ptr(vals), mode, n_out, _ptr(u),
                               _ptr(out), _stream()), "txs_resample")
     return out
+
+
+def resample_intervals(edges, vals, n_out, mode=TXS_PDF_SIGMA, u=None):
+    """Inverse CDF straight to dense intervals -> (t0, t1) float32 [N*n_out]."""
+    n, nb1 = edges.shape
+    _need(edges, "edges", torch.float32, (n, nb1))
+    _need(vals, "vals", torch.float32, (n, nb1 - 1))
+    _opt(u, "u", torch.float32, (n, n_out + 1))
+    t0 = torch.empty(n * n_out, dtype=torch.float32, device=edges.device)
+    t1 = torch.empty_like(t0)
+    check(load().txs_resample_intervals(n, nb1 - 1, _ptr(edges), _ptr(vals), mode, n_out,
+                                        _ptr(u), _ptr(t0), _ptr(t1), _stream()),
+          "txs_resample_intervals")
+    return t0, t1
 
 
 def edges_to_intervals(edges):

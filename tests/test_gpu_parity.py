@@ -408,6 +408,11 @@ def test_resample(gpu_lib, mode, use_u):
     err = np.abs(out - ref)
     bad = (err > tol) & ~band[:, None]
     assert not bad.any(), (bad.sum(), np.argwhere(bad)[:5])
+    # the dense-interval form carries the same edges
+    t0, t1 = gpu_lib.resample_intervals(dev(edges), dev(vals), n_out, mode,
+                                        None if u is None else dev(u))
+    assert np.array_equal(host(t0).reshape(n, n_out), out[:, :-1])
+    assert np.array_equal(host(t1).reshape(n, n_out), out[:, 1:])
 
 
 def test_uniform_bins(gpu_lib, tiny):

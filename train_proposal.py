@@ -49,7 +49,7 @@ def _timed(torch, fn, reps):
 
 def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
         sweep=(32, 48, 64, 96, 128, 192, 256), err_bar=1e-3, lr0=1e-2, lr1=1e-4,
-        log_every=50, time_reps=5, oracle_every=0, untrained=True, log=print):
+        log_every=50, time_reps=5, untrained=True, log=print):
     import torch
 
     import paper_2305_04966_amd as txs
@@ -82,22 +82,6 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
     torch.cuda.synchronize()
     rec["grid_samples"] = judge.samples.n_samples
     log(f"[judge] {N} rays, {judge.samples.n_samples} grid samples")
-    if oracle_every > 0:
-        import oracle
-        k = np.arange(0, N, oracle_every)
-        oo, od_ = w.rays_o[ev][k], w.rays_d[ev][k]
-        p = w.fld.packed_params()
-        m = oracle.march(oo, od_, w.bits, w.res, n_levels=w.n_levels,
-                         half_extent0=w.half_extent0, dt0=w.dt0)
-        s_ng, _ = oracle.field_at_samples(oo, od_, m["t0"], m["t1"], m["ray_id"], p)
-        kept, _ = oracle.transmittance_prefix(m["packed_info"], m["t0"], m["t1"],
-                                              s_ng.astype(np.float32), w.t_min)
-        info, t0o, t1o, rido = oracle.gather_prefix(m["packed_info"], kept, m["t0"], m["t1"],
-                                                    m["ray_id"])
-        s, c = oracle.field_at_samples(oo, od_, t0o, t1o, rido, p)
-        ref = oracle.render_fwd(info, t0o, t1o, s.astype(np.float32), c.astype(np.float32))
-        rec["judge_vs_oracle_max_abs"] = float(np.abs(judge.rgb.cpu().numpy()[k]
-                                                      - ref["rgb"]).max())
 
     # 2. train
     edges = txs.uniform_bins(grid, o, d, bins)
@@ -146,7 +130,7 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
 
     def learned_step():
         e0 = txs.uniform_bins(grid, o, d, bins)
-        _, a, b, sg, rgb, od = proposal_render(est, o, d, e0, n_star, field, keep=True)
+        a, b, sg, rgb, od = proposal_render(est, o, d, e0, n_star, field, keep=True)
         txs.render_bwd(None, a, b, sg, rgb, g_rgb, n_rays=N, fixed_count=n_star,
                        optical_depth=od)
 
@@ -171,16 +155,13 @@ def main():
     ap.add_argument("--lr1", type=float, default=1e-4)
     ap.add_argument("--log-every", type=int, default=50)
     ap.add_argument("--time-reps", type=int, default=5)
-    ap.add_argument("--oracle-every", type=int, default=0,
-                    help="check the judge against the FP64 oracle on every k-th ray (0 = skip)")
     ap.add_argument("--save", default="")
     args = ap.parse_args()
     rec, est = run(steps=args.steps, hidden=args.hidden, bins=args.bins,
                    ray_stride=args.ray_stride, train_stride=args.train_stride,
                    sweep=[int(s) for s in args.sweep.split(",")], err_bar=args.err_bar,
                    lr0=args.lr0, lr1=args.lr1, log_every=args.log_every,
-                   time_reps=args.time_reps, oracle_every=args.oracle_every,
-                   log=lambda s: print(s, flush=True))
+                   time_reps=args.time_reps, log=lambda s: print(s, flush=True))
     if args.save:
         np.save(args.save, est.params.cpu().numpy())
     print(json.dumps(rec), flush=True)
