@@ -127,17 +127,36 @@ __device__ __forceinline__ float softplus(float z) {
   return __builtin_amdgcn_logf(1.0f + e) * 0.693147181f;
 }
 
-// x_hat of a bin midpoint: x / scale, optionally contracted into the unit ball
+// Raw inputs of one point (its bin's edges, its ray's origin and direction),
+// loaded apart from their use so that a kernel can fetch them a step ahead.
+struct PointIn {
+  float e0, e1, o[3], d[3];
+};
+
 template <class Args>
-__device__ __forceinline__ void encode_point(const Args& a, int64_t p, float (&y)[3]) {
+__device__ __forceinline__ PointIn load_point(const Args& a, int64_t p) {
   int64_t r;
   if (a.small) r = a.bins_div.div((uint32_t)p);
   else r = p / a.n_bins;
   const int64_t j = p - r * a.n_bins;
   const float* e = a.edges + r * (a.n_bins + 1) + j;
-  const float tm = 0.5f * (e[0] + e[1]);
+  PointIn in;
+  in.e0 = e[0];
+  in.e1 = e[1];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) y[c] = (a.ro[3 * r + c] + tm * a.rd[3 * r + c]) * a.inv_scale;
+  for (int c = 0; c < 3; ++c) {
+    in.o[c] = a.ro[3 * r + c];
+    in.d[c] = a.rd[3 * r + c];
+  }
+  return in;
+}
+
+// x_hat of a bin midpoint: x / scale, optionally contracted into the unit ball
+template <class Args>
+__device__ __forceinline__ void encode_loaded(const Args& a, const PointIn& in, float (&y)[3]) {
+  const float tm = 0.5f * (in.e0 + in.e1);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) y[c] = (in.o[c] + tm * in.d[c]) * a.inv_scale;
   if (a.contract) {
     const float n = sqrtf(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
     const float rn = 1.0f / n;
@@ -223,6 +242,13 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
   const int64_t n_tiles = (n_points + 15) / 16;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  // inputs of the current tile group, fetched one group ahead
+  PointIn in[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int64_t p = (wave * NT + t) * 16 + col;
+    if (p < n_points) in[t] = load_point(a, p);
+  }
   for (int64_t t0 = wave * NT; t0 < n_tiles; t0 += n_waves * NT) {
     bf16x8 B1[NT][2];
     bool valid[NT];
@@ -231,9 +257,14 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
       const int64_t p = (t0 + t) * 16 + col;
       valid[t] = p < n_points;
       float y[3] = {0.0f, 0.0f, 0.0f};
-      if (valid[t]) encode_point(a, p, y);
+      if (valid[t]) encode_loaded(a, in[t], y);
       const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
       features(xa, g, g < 3, B1[t][0], B1[t][1]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int64_t pn = (t0 + n_waves * NT + t) * 16 + col;
+      if (pn < n_points) in[t] = load_point(a, pn);
     }
     // layer 1; B operand of layer 2's K-step s = fragments 2s and 2s+1
     bf16x8 B2[NT][KS];
@@ -388,15 +419,25 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
     for (int i = 0; i < 4; ++i) acc3[m][i] = 0.0f;
   float acc_b3 = 0.0f;
 
+  const int pc = 16 * w + col;  // column of this lane's point in the staged rows
+  // inputs of the current batch, fetched one batch ahead (before phase B)
+  PointIn in{};
+  float dsig = 0.0f;
+  {
+    const int64_t p = (int64_t)blockIdx.x * kBwdBatch + pc;
+    if (p < n_points) {
+      in = load_point(a, p);
+      dsig = a.d_sigma[p];
+    }
+  }
   for (int64_t batch = blockIdx.x; batch < n_batches; batch += gridDim.x) {
     // ---------------- phase A: this wave's 16 points
-    const int pc = 16 * w + col;  // column of this lane's point in the staged rows
     const int64_t p = batch * kBwdBatch + pc;
     const bool valid = p < n_points;
     bf16x8 B1[2];
     {
       float y[3] = {0.0f, 0.0f, 0.0f};
-      if (valid) encode_point(a, p, y);
+      if (valid) encode_loaded(a, in, y);
       const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
       features(xa, g, g < 3 && valid, B1[0], B1[1]);
       if (g < 3) {
@@ -440,7 +481,7 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
     }
     z += __shfl_xor(z, 16, kWave);
     z += __shfl_xor(z, 32, kWave);
-    const float dz = valid ? a.d_sigma[p] / (1.0f + expf(-(z + b3))) : 0.0f;
+    const float dz = valid ? dsig / (1.0f + expf(-(z + b3))) : 0.0f;
     if (g == 0) acc_b3 += dz;
     bf16x8 D2B[KS];
 #pragma unroll
@@ -471,6 +512,13 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
       }
     }
     __syncthreads();
+    {
+      const int64_t pn = (batch + gridDim.x) * kBwdBatch + pc;
+      if (pn < n_points) {
+        in = load_point(a, pn);
+        dsig = a.d_sigma[pn];
+      }
+    }
     // ---------------- phase B: contract over the batch's 64 points
 #pragma unroll
     for (int ks = 0; ks < kBwdBatch / 32; ++ks) {

@@ -13,75 +13,78 @@ namespace {
 constexpr int kMaxBins = 1024;
 constexpr int kRsWaves = 4;
 
-// One wave per ray: wave-wide scan of the bin masses into the CDF, kept in
-// LDS, then one binary search per output edge.
+// Persistent waves, one ray at a time: edges to LDS, wave-wide scan of the
+// bin masses into the CDF (LDS), then one binary search per output edge.  LDS
+// per wave is 2 (n_bins + 1) floats (dynamic).
+//
 // out != NULL: edges [n_rays, n_out+1]; otherwise the intervals between them,
 // t0o[r*n_out + k] = edge k and t1o[r*n_out + k] = edge k+1.
 __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(
     int32_t n_rays, int32_t n_bins, const float* __restrict__ edges,
     const float* __restrict__ vals, int32_t mode, int32_t n_out, const float* __restrict__ u,
     float* __restrict__ out, float* __restrict__ t0o, float* __restrict__ t1o) {
-  __shared__ float lds_F[kRsWaves][kMaxBins + 1];
-  __shared__ float lds_e[kRsWaves][kMaxBins + 1];
+  extern __shared__ float lds_rs[];
   const int w = threadIdx.x / kWave, ln = lane();
-  const int64_t r = (int64_t)blockIdx.x * kRsWaves + w;
-  if (r >= n_rays) return;
-  float* F = lds_F[w];
-  float* e = lds_e[w];
-  const float* er = edges + r * (n_bins + 1);
-  const float* vr = vals + r * n_bins;
-  for (int i = ln; i <= n_bins; i += kWave) e[i] = er[i];
-  wave_sync();
-  // running sum over bins in chunks of 64
-  float carry = 0.0f;
-  if (ln == 0) F[0] = 0.0f;
-  for (int base = 0; base < n_bins; base += kWave) {
-    const int i = base + ln;
-    float m = 0.0f;
-    if (i < n_bins) m = (mode == TXS_PDF_SIGMA) ? vr[i] * (e[i + 1] - e[i]) : vr[i];
-    float incl = m;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const float t = shfl_up(incl, d);
-      if (ln >= d) incl += t;
-    }
-    incl += carry;
-    if (i < n_bins) F[i + 1] = (mode == TXS_PDF_SIGMA) ? -expm1f(-incl) : incl;
-    carry = readlane(incl, kWave - 1);
-  }
-  wave_sync();
-  float Fn = F[n_bins];
-  const bool uniform = !(Fn > 1e-12f);
-  if (uniform) {
-    for (int i = ln; i <= n_bins; i += kWave) F[i] = (float)i / (float)n_bins;
+  float* F = lds_rs + (size_t)w * 2 * (n_bins + 1);
+  float* e = F + (n_bins + 1);
+  const int64_t stride = (int64_t)gridDim.x * kRsWaves;
+  for (int64_t r = (int64_t)blockIdx.x * kRsWaves + w; r < n_rays; r += stride) {
+    const float* er = edges + r * (n_bins + 1);
+    const float* vr = vals + r * n_bins;
+    for (int i = ln; i <= n_bins; i += kWave) e[i] = er[i];
     wave_sync();
-    Fn = 1.0f;
+    // running sum over bins in chunks of 64
+    float carry = 0.0f;
+    if (ln == 0) F[0] = 0.0f;
+    for (int base = 0; base < n_bins; base += kWave) {
+      const int i = base + ln;
+      float m = 0.0f;
+      if (i < n_bins) m = (mode == TXS_PDF_SIGMA) ? vr[i] * (e[i + 1] - e[i]) : vr[i];
+      const float incl = add_scan_incl(m) + carry;
+      if (i < n_bins) F[i + 1] = (mode == TXS_PDF_SIGMA) ? -expm1f(-incl) : incl;
+      carry = readlane(incl, kWave - 1);
+    }
+    wave_sync();
+    float Fn = F[n_bins];
+    const bool uniform = !(Fn > 1e-12f);
+    if (uniform) {
+      for (int i = ln; i <= n_bins; i += kWave) F[i] = (float)i / (float)n_bins;
+      wave_sync();
+      Fn = 1.0f;
+    }
+    for (int k = ln; k <= n_out; k += kWave) {
+      const float uk = u ? u[r * (n_out + 1) + k] : (float)k / (float)n_out;
+      const float up = uk * Fn;
+      // largest i in [0, n_bins] with F[i] <= up (F[0] = 0 <= up)
+      int lo = 0, hi = n_bins;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (F[mid] <= up) lo = mid;
+        else hi = mid - 1;
+      }
+      float t;
+      if (lo >= n_bins) {
+        t = e[n_bins];
+      } else {
+        const float f0 = F[lo], f1 = F[lo + 1];
+        const float frac = (up - f0) / (f1 - f0);
+        t = e[lo] + frac * (e[lo + 1] - e[lo]);
+      }
+      if (out) {
+        out[r * (n_out + 1) + k] = t;
+      } else {
+        if (k < n_out) t0o[r * n_out + k] = t;
+        if (k > 0) t1o[r * n_out + k - 1] = t;
+      }
+    }
+    wave_sync();  // this ray's LDS reads are done before the next ray overwrites it
   }
-  for (int k = ln; k <= n_out; k += kWave) {
-    const float uk = u ? u[r * (n_out + 1) + k] : (float)k / (float)n_out;
-    const float up = uk * Fn;
-    // largest i in [0, n_bins] with F[i] <= up (F[0] = 0 <= up)
-    int lo = 0, hi = n_bins;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (F[mid] <= up) lo = mid;
-      else hi = mid - 1;
-    }
-    float t;
-    if (lo >= n_bins) {
-      t = e[n_bins];
-    } else {
-      const float f0 = F[lo], f1 = F[lo + 1];
-      const float frac = (up - f0) / (f1 - f0);
-      t = e[lo] + frac * (e[lo + 1] - e[lo]);
-    }
-    if (out) {
-      out[r * (n_out + 1) + k] = t;
-    } else {
-      if (k < n_out) t0o[r * n_out + k] = t;
-      if (k > 0) t1o[r * n_out + k - 1] = t;
-    }
-  }
+}
+
+// grid of persistent resample blocks
+inline unsigned resample_blocks(int32_t n_rays) {
+  const int64_t need = ((int64_t)n_rays + kRsWaves - 1) / kRsWaves;
+  return (unsigned)std::min<int64_t>(need, 256 * 16);
 }
 
 __global__ __launch_bounds__(256) void uniform_bins_kernel(txs_grid g, float near_plane,
@@ -155,10 +158,9 @@ extern "C" txs_status txs_resample(int32_t n_rays, int32_t n_bins, const float* 
               mode);
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(edges && vals && out_edges, "txs_resample: null array");
-  const int64_t blocks = ((int64_t)n_rays + kRsWaves - 1) / kRsWaves;
-  hipLaunchKernelGGL(resample_kernel, dim3((unsigned)blocks), dim3(kWave * kRsWaves), 0,
-                     as_stream(stream), n_rays, n_bins, edges, vals, mode, n_out, u, out_edges,
-                     nullptr, nullptr);
+  hipLaunchKernelGGL(resample_kernel, dim3(resample_blocks(n_rays)), dim3(kWave * kRsWaves),
+                     kRsWaves * 2 * (n_bins + 1) * sizeof(float), as_stream(stream), n_rays,
+                     n_bins, edges, vals, mode, n_out, u, out_edges, nullptr, nullptr);
   return launch_status("txs_resample");
 }
 
@@ -176,10 +178,9 @@ extern "C" txs_status txs_resample_intervals(int32_t n_rays, int32_t n_bins, con
               "txs_resample_intervals: bad mode %d", mode);
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(edges && vals && out_t0 && out_t1, "txs_resample_intervals: null array");
-  const int64_t blocks = ((int64_t)n_rays + kRsWaves - 1) / kRsWaves;
-  hipLaunchKernelGGL(resample_kernel, dim3((unsigned)blocks), dim3(kWave * kRsWaves), 0,
-                     as_stream(stream), n_rays, n_bins, edges, vals, mode, n_out, u, nullptr,
-                     out_t0, out_t1);
+  hipLaunchKernelGGL(resample_kernel, dim3(resample_blocks(n_rays)), dim3(kWave * kRsWaves),
+                     kRsWaves * 2 * (n_bins + 1) * sizeof(float), as_stream(stream), n_rays,
+                     n_bins, edges, vals, mode, n_out, u, nullptr, out_t0, out_t1);
   return launch_status("txs_resample_intervals");
 }
 

@@ -33,60 +33,96 @@ __device__ __forceinline__ void bin_range(const float* e, int nb, float a, float
   jhi = lo;
 }
 
-// gap = w - (proposal mass over the bins overlapping the target interval)
-__device__ __forceinline__ float target_gap(const float* e, const float* pw, int nb, float a,
-                                            float b, float w) {
-  int jlo, jhi;
-  bin_range(e, nb, a, b, jlo, jhi);
-  float bound = 0.0f;
-  for (int j = jlo; j <= jhi; ++j) bound += pw[j];
-  return w - bound;
+constexpr int kChunk = 512;  // targets staged per pass
+
+// LDS of one wave: edges [nb+1], proposal weights [nb], and for a chunk of
+// targets their gradient coefficient and overlapping bin range.
+__host__ __device__ inline size_t loss_lds_bytes(int nb) {
+  return ((size_t)(2 * nb + 1) * 4 + 15) / 16 * 16 + (size_t)kChunk * (4 + 2 + 2);
 }
 
-// One wave per ray: the ray's proposal edges and weights in LDS; the loss
-// sums over the ray's target intervals; the gradient of each bin sums, in
-// target order, over the contiguous run of targets that overlap it.
+// One wave per ray.  Each target's bin range (two binary searches over the
+// edges in LDS), gap w - bound and loss term are computed once, by the lane
+// that owns the target; its gradient coefficient c_i = -2 gap/(w + eps)/n (0
+// when gap <= 0) and bin range go to LDS in target order.  Targets are sorted
+// and disjoint, so bin ranges are non-decreasing in the target index and the
+// targets overlapping a bin form a contiguous run: the lane of bin j finds its
+// run by a binary search over the staged ranges and sums it in target order.
+// Rays with more than kChunk targets are staged in chunks, each bin carrying
+// its partial sum across them (same order).
 __global__ __launch_bounds__(kWave* kLossWaves) void hist_loss_kernel(
     const int32_t* __restrict__ info, const float* __restrict__ t0, const float* __restrict__ t1,
     const float* __restrict__ w, int32_t n_rays, int64_t n_targets, int32_t nb,
     const float* __restrict__ edges, const float* __restrict__ prop, float eps, float inv_n,
     float* __restrict__ loss, float* __restrict__ d_prop) {
-  __shared__ float sE[kLossWaves][kMaxBins + 1];
-  __shared__ float sP[kLossWaves][kMaxBins];
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   const int wv = threadIdx.x / kWave, ln = lane();
   const int64_t r = (int64_t)blockIdx.x * kLossWaves + wv;
   if (r >= n_rays) return;
-  float* e = sE[wv];
-  float* pw = sP[wv];
+  unsigned char* base = lds_raw + (size_t)wv * loss_lds_bytes(nb);
+  float* e = reinterpret_cast<float*>(base);
+  float* pw = e + nb + 1;
+  float* cc = reinterpret_cast<float*>(base + ((size_t)(2 * nb + 1) * 4 + 15) / 16 * 16);
+  int16_t* jl = reinterpret_cast<int16_t*>(cc + kChunk);
+  int16_t* jh = jl + kChunk;
   for (int j = ln; j <= nb; j += kWave) e[j] = edges[r * (nb + 1) + j];
   for (int j = ln; j < nb; j += kWave) pw[j] = prop[r * nb + j];
   wave_sync();
   int64_t st = info[2 * r], ct = info[2 * r + 1];
   if (st < 0 || ct < 0 || st + ct > n_targets) ct = 0;  // malformed row: no targets
+  constexpr int kBinsPerLane = kMaxBins / kWave;
+  float gacc[kBinsPerLane];
+#pragma unroll
+  for (int q = 0; q < kBinsPerLane; ++q) gacc[q] = 0.0f;
   float acc = 0.0f;
-  for (int64_t i = st + ln; i < st + ct; i += kWave) {
-    const float g = target_gap(e, pw, nb, t0[i], t1[i], w[i]);
-    if (g > 0.0f) acc += g * g / (w[i] + eps);
+  for (int64_t c0 = 0; c0 < ct || c0 == 0; c0 += kChunk) {
+    const int n = (int)min<int64_t>(kChunk, ct - c0);
+    for (int k = ln; k < n; k += kWave) {
+      const int64_t i = st + c0 + k;
+      const float a = t0[i], b = t1[i], wi = w[i];
+      int jlo, jhi;
+      bin_range(e, nb, a, b, jlo, jhi);
+      float bound = 0.0f;
+      for (int j = jlo; j <= jhi; ++j) bound += pw[j];
+      const float gap = wi - bound;
+      float c = 0.0f;
+      if (gap > 0.0f) {
+        acc += gap * gap / (wi + eps);
+        c = -2.0f * gap / (wi + eps) * inv_n;
+      }
+      cc[k] = c;
+      jl[k] = (int16_t)jlo;
+      jh[k] = (int16_t)jhi;
+    }
+    wave_sync();
+    if (d_prop) {
+#pragma unroll
+      for (int q = 0; q < kBinsPerLane; ++q) {
+        const int j = ln + q * kWave;
+        if (j >= nb) break;
+        int lo = 0, hi = n;  // first staged target with jhi >= j
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (jh[mid] >= j) hi = mid;
+          else lo = mid + 1;
+        }
+        float g = gacc[q];
+        for (int k = lo; k < n && jl[k] <= j; ++k) g += cc[k];
+        gacc[q] = g;
+      }
+    }
+    wave_sync();
+    if (ct == 0) break;
   }
 #pragma unroll
   for (int s = kWave / 2; s >= 1; s >>= 1) acc += __shfl_xor(acc, s, kWave);
   if (ln == 0) loss[r] = acc;
-  if (!d_prop) return;
-  for (int j = ln; j < nb; j += kWave) {
-    const float lo = e[j], hi = e[j + 1];
-    // targets overlapping (lo, hi): t1_i > lo and t0_i < hi (sorted, disjoint)
-    int64_t a = st, b = st + ct;
-    while (a < b) {
-      const int64_t mid = (a + b) >> 1;
-      if (t1[mid] > lo) b = mid;
-      else a = mid + 1;
+  if (d_prop) {
+#pragma unroll
+    for (int q = 0; q < kBinsPerLane; ++q) {
+      const int j = ln + q * kWave;
+      if (j < nb) d_prop[r * nb + j] = gacc[q];
     }
-    float g = 0.0f;
-    for (int64_t i = a; i < st + ct && t0[i] < hi; ++i) {
-      const float gap = target_gap(e, pw, nb, t0[i], t1[i], w[i]);
-      if (gap > 0.0f) g += -2.0f * gap / (w[i] + eps) * inv_n;
-    }
-    d_prop[r * nb + j] = g;
   }
 }
 
@@ -122,7 +158,8 @@ extern "C" txs_status txs_hist_loss(const int32_t* packed_info, int32_t n_rays, 
   TXS_REQUIRE(packed_info && edges && prop_w && loss, "txs_hist_loss: null array");
   TXS_REQUIRE(n_targets == 0 || (t0 && t1 && w), "txs_hist_loss: null target array");
   const int64_t blocks = ((int64_t)n_rays + kLossWaves - 1) / kLossWaves;
-  hipLaunchKernelGGL(hist_loss_kernel, dim3((unsigned)blocks), dim3(kWave * kLossWaves), 0,
+  const size_t lds = kLossWaves * loss_lds_bytes(n_bins);
+  hipLaunchKernelGGL(hist_loss_kernel, dim3((unsigned)blocks), dim3(kWave * kLossWaves), lds,
                      as_stream(stream), packed_info, t0, t1, w, n_rays, n_targets, n_bins, edges,
                      prop_w, eps, 1.0f / (float)n_rays, loss, d_prop);
   return launch_status("txs_hist_loss");

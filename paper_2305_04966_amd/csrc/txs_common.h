@@ -123,6 +123,19 @@ struct FastDiv {
 // hardware already executes one wave's LDS operations in order.
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
+// Inclusive sum over lanes <= this one (same scheme as max_scan_incl).
+__device__ __forceinline__ float add_scan_incl(float v) {
+  const int ri = lane() & 15, row = lane() >> 4;
+  float t;
+  t = dpp<kRowShr1>(v, v); if (ri >= 1) v += t;
+  t = dpp<kRowShr2>(v, v); if (ri >= 2) v += t;
+  t = dpp<kRowShr4>(v, v); if (ri >= 4) v += t;
+  t = dpp<kRowShr8>(v, v); if (ri >= 8) v += t;
+  const float e0 = readlane(v, 15), e1 = readlane(v, 31), e2 = readlane(v, 47);
+  const float c1 = e0, c2 = c1 + e1, c3 = c2 + e2;
+  return row == 1 ? v + c1 : row == 2 ? v + c2 : row == 3 ? v + c3 : v;
+}
+
 // Inclusive max over lanes <= this one: DPP row shifts inside each 16-lane row,
 // then the three row carries by readlane.
 __device__ __forceinline__ int max_scan_incl(int v) {
