@@ -119,6 +119,23 @@ __device__ __forceinline__ bf16x8 pack8(const float (&v)[8]) {
 // softplus(z) = log(1 + e^z): e = 2^(z log2 e) by the hardware exp2; for
 // e < 1/16 the series e (1 - e/2 + e^2/3 - e^3/4 + e^4/5) (truncation < 2e-7
 // relative), else log2(1 + e) ln 2 (rounding of 1 + e costs < 1e-6 relative).
+// bf16 of relu(v), eight at a time.  Round-to-nearest-even keeps the sign, so
+// relu after rounding equals rounding after relu; on the packed halves it is
+// one arithmetic shift (sign -> all-ones mask) and one masked clear per pair,
+// where fmaxf costs a NaN-quieting max plus the max per value.
+__device__ __forceinline__ bf16x8 pack8_relu(const float (&v)[8]) {
+  typedef unsigned uint4v __attribute__((ext_vector_type(4)));
+  uint4v w = __builtin_bit_cast(uint4v, pack8(v));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    // as signed 16-bit integers, bf16 values with the sign bit set are negative
+    unsigned r;
+    asm("v_pk_max_i16 %0, %1, 0" : "=v"(r) : "v"(w[q]));
+    w[q] = r;
+  }
+  return __builtin_bit_cast(bf16x8, w);
+}
+
 __device__ __forceinline__ float softplus(float z) {
   if (z > 20.0f) return z;
   const float e = __builtin_amdgcn_exp2f(z * 1.44269504f);
@@ -171,8 +188,7 @@ __device__ __forceinline__ void encode_loaded(const Args& a, const PointIn& in, 
 // cos at x/2 + 1/4); each further octave by the double-angle identities
 // sin 2a = 2 sin a cos a, cos 2a = 1 - 2 sin^2 a (absolute error grows about
 // 2x per octave: ~1e-6 at octave 5, far below a bf16 step).
-__device__ __forceinline__ void features(float xa, int g, bool in_range, bf16x8& b0,
-                                         bf16x8& b1) {
+__device__ __forceinline__ void features(float xa, int g, bf16x8& b0, bf16x8& b1) {
   float f[16];
   float sn = __builtin_amdgcn_sinf(0.5f * xa);
   float cs = __builtin_amdgcn_sinf(0.5f * xa + 0.25f);
@@ -189,10 +205,6 @@ __device__ __forceinline__ void features(float xa, int g, bool in_range, bf16x8&
   }
   f[12] = xa;
   f[13] = f[14] = f[15] = g == 0 ? 1.0f : 0.0f;
-  if (!in_range) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) f[q] = 0.0f;
-  }
   float lo[8], hi[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -259,7 +271,7 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
       float y[3] = {0.0f, 0.0f, 0.0f};
       if (valid[t]) encode_loaded(a, in[t], y);
       const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
-      features(xa, g, g < 3, B1[t][0], B1[t][1]);
+      features(xa, g, B1[t][0], B1[t][1]);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -284,11 +296,9 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
       }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const float v[8] = {fmaxf(hh[t][0][0], 0.0f), fmaxf(hh[t][0][1], 0.0f),
-                            fmaxf(hh[t][0][2], 0.0f), fmaxf(hh[t][0][3], 0.0f),
-                            fmaxf(hh[t][1][0], 0.0f), fmaxf(hh[t][1][1], 0.0f),
-                            fmaxf(hh[t][1][2], 0.0f), fmaxf(hh[t][1][3], 0.0f)};
-        B2[t][s] = pack8(v);
+        const float v[8] = {hh[t][0][0], hh[t][0][1], hh[t][0][2], hh[t][0][3],
+                            hh[t][1][0], hh[t][1][1], hh[t][1][2], hh[t][1][3]};
+        B2[t][s] = pack8_relu(v);
       }
     }
     // layers 2 and 3: two row tiles of h2 at a time make one K-step of layer 3
@@ -316,11 +326,9 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
       const bf16x8 w3 = sA3[s3 * 64 + ln];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const float v[8] = {fmaxf(c[t][0][0], 0.0f), fmaxf(c[t][0][1], 0.0f),
-                            fmaxf(c[t][0][2], 0.0f), fmaxf(c[t][0][3], 0.0f),
-                            fmaxf(c[t][1][0], 0.0f), fmaxf(c[t][1][1], 0.0f),
-                            fmaxf(c[t][1][2], 0.0f), fmaxf(c[t][1][3], 0.0f)};
-        zt[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, pack8(v), zt[t], 0, 0, 0);
+        const float v[8] = {c[t][0][0], c[t][0][1], c[t][0][2], c[t][0][3],
+                            c[t][1][0], c[t][1][1], c[t][1][2], c[t][1][3]};
+        zt[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, pack8_relu(v), zt[t], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -439,7 +447,7 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
       float y[3] = {0.0f, 0.0f, 0.0f};
       if (valid) encode_loaded(a, in, y);
       const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
-      features(xa, g, g < 3 && valid, B1[0], B1[1]);
+      features(xa, g, B1[0], B1[1]);
       if (g < 3) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) sG[(16 * g + q) * RS + pc] = B1[q / 8][q % 8];
@@ -458,10 +466,9 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA1[(m * 2 + 1) * 64 + ln], B1[1], c, 0, 0, 0);
         hh[h] = c;
       }
-      const float v[8] = {fmaxf(hh[0][0], 0.0f), fmaxf(hh[0][1], 0.0f), fmaxf(hh[0][2], 0.0f),
-                          fmaxf(hh[0][3], 0.0f), fmaxf(hh[1][0], 0.0f), fmaxf(hh[1][1], 0.0f),
-                          fmaxf(hh[1][2], 0.0f), fmaxf(hh[1][3], 0.0f)};
-      B2[s] = pack8(v);
+      const float v[8] = {hh[0][0], hh[0][1], hh[0][2], hh[0][3],
+                          hh[1][0], hh[1][1], hh[1][2], hh[1][3]};
+      B2[s] = pack8_relu(v);
 #pragma unroll
       for (int j = 0; j < 8; ++j) sH1[(16 * (2 * s + j / 4) + 4 * g + j % 4) * RS + pc] = B2[s][j];
     }
