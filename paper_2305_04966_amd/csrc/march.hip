@@ -74,50 +74,68 @@ struct Emit {
   int32_t ray;
 };
 
-// One segment [a, b) on level l, 64 lattice points per step.  n: samples so
-// far (wave-uniform); returns the new count.
+// One segment [a, b) on level l.  Each step tests kGroups groups of 64
+// consecutive lattice points (one per lane), with all their grid-word loads in
+// flight together, then emits the groups in k order.  n: samples so far
+// (wave-uniform); returns the new count.
+constexpr int kGroups = 2;
+
 template <bool kFill>
 __device__ __forceinline__ int32_t march_segment(const MarchArgs& g, const float o[3],
-                                                 const float d[3], float a,
-                                 float b, int l, int32_t n, int32_t cap, const Emit& em) {
+                                                 const float d[3], float a, float b, int l,
+                                                 int32_t n, int32_t cap, const Emit& em) {
   const float dt = g.dt0 * (float)(1 << l);
   const LevelBox box = level_box(g, l);
   const int res = g.res;
   const float resf = (float)res;
   const uint32_t* bits = g.bits + (int64_t)l * g.level_words;
   const int ln = lane();
-  for (int32_t k0 = 0; k0 < kLatticeLimit; k0 += kWave) {
-    const int32_t k = k0 + ln;
-    const float m = a + ((float)k + 0.5f) * dt;
-    const bool valid = (k < kLatticeLimit) && (m < b);
-    bool occ = false;
-    if (valid) {
-      int cell[3];
+  for (int32_t k0 = 0; k0 < kLatticeLimit; k0 += kWave * kGroups) {
+    bool valid[kGroups], occ[kGroups];
+    uint32_t word[kGroups];
+    int32_t sh[kGroups];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float x = o[c] + m * d[c];
-        const float u = (x - box.bmin[c]) * box.scale[c];
-        float f = floorf(u);
-        f = fminf(fmaxf(f, 0.0f), resf - 1.0f);
-        cell[c] = (int)f;
+    for (int q = 0; q < kGroups; ++q) {
+      const int32_t k = k0 + kWave * q + ln;
+      const float m = a + ((float)k + 0.5f) * dt;
+      valid[q] = (k < kLatticeLimit) && (m < b);
+      word[q] = 0u;
+      sh[q] = 0;
+      if (valid[q]) {
+        int cell[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float x = o[c] + m * d[c];
+          const float u = (x - box.bmin[c]) * box.scale[c];
+          float f = floorf(u);
+          f = fminf(fmaxf(f, 0.0f), resf - 1.0f);
+          cell[c] = (int)f;
+        }
+        const int32_t idx = cell[0] + res * (cell[1] + res * cell[2]);
+        word[q] = bits[idx >> 5];
+        sh[q] = idx & 31;
       }
-      const int32_t idx = cell[0] + res * (cell[1] + res * cell[2]);
-      occ = (bits[idx >> 5] >> (idx & 31)) & 1u;
     }
-    const uint64_t mask = __ballot(occ);
-    if (kFill && occ) {
-      const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
-          (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-      const int64_t pos = em.base + n + rank;
-      if ((cap == 0 || n + rank < cap) && pos < em.capacity) {
-        em.t0[pos] = a + (float)k * dt;
-        em.t1[pos] = fminf(a + (float)(k + 1) * dt, b);
-        if (em.ray_id) em.ray_id[pos] = em.ray;
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) occ[q] = valid[q] && ((word[q] >> sh[q]) & 1u);
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) {
+      const int32_t k = k0 + kWave * q + ln;
+      const uint64_t mask = __ballot(occ[q]);
+      if (kFill && occ[q]) {
+        const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        const int64_t pos = em.base + n + rank;
+        if ((cap == 0 || n + rank < cap) && pos < em.capacity) {
+          em.t0[pos] = a + (float)k * dt;
+          em.t1[pos] = fminf(a + (float)(k + 1) * dt, b);
+          if (em.ray_id) em.ray_id[pos] = em.ray;
+        }
       }
+      n += __popcll(mask);
+      if (cap > 0 && n >= cap) return cap;
     }
-    n += __popcll(mask);
-    if (cap > 0 && n >= cap) return cap;
-    if (__ballot(valid) != ~0ull) break;  // the segment ended inside this step
+    if (__ballot(valid[kGroups - 1]) != ~0ull) break;  // the segment ended in this step
   }
   return n;
 }
