@@ -129,17 +129,34 @@ def gpu_bench(args, w):
         grads = tl.run("render_bwd", txs.render_bwd, info2, q0, q1, sig, rgb, g_rgb,
                        optical_depth=out[4])
         stats["Sm"], stats["S"] = sm, s
+        stats["_probe"] = (q0, q1, sig, rgb)
         return out, grads
 
+    last = None
     for _ in range(args.warmup):
-        step()
+        last = step()
     torch.cuda.synchronize()
     tl.on = True
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        last = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    # live reference: the render adjoint's traffic (same arrays, same layout,
+    # trivial arithmetic) -- the ceiling of that pattern on this device
+    sp = stats.pop("_probe", None)
+    if sp is not None and last is not None:
+        q0, q1, sig, rgb = sp
+        ds_out, dr_out = last[1]
+        txs.stream_probe(q0, q1, sig, rgb, ds_out, dr_out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            txs.stream_probe(q0, q1, sig, rgb, ds_out, dr_out)
+        e1.record()
+        torch.cuda.synchronize()
+        stats["pattern_ms"] = e0.elapsed_time(e1) / 5
     # live reference: a plain 1 GiB device copy (reads and writes 1 GiB)
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -273,7 +290,11 @@ def main():
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom), "alg_bytes_per_launch": bytes_launch,
-                     "device_copy_GBps": st["copy_GBps"]},
+                     "device_copy_GBps": st["copy_GBps"],
+                     # the probe moves 40 B per kept sample (the adjoint's per-sample bytes)
+                     "pattern_ceiling_GBps": (40.0 * st["S"] / (st["pattern_ms"] * 1e-3) / 1e9
+                                              if dom == "render_bwd" and "pattern_ms" in st
+                                              else None)},
     }
     if args.learned_steps > 0:
         rec["learned_vs_grid"] = learned_vs_grid(args)

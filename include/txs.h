@@ -348,6 +348,17 @@ txs_status txs_blob_field(const float* params, int32_t n_blobs, const float* ray
                           const int32_t* ray_id, int32_t fixed_count, int64_t n, float* sigma,
                           float* rgb, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Measurement support (not part of the method).  Moves the HBM traffic of
+ * txs_render_bwd in its layout -- reads t0, t1, sigma (float [n]) and rgb
+ * (float [n,3]); writes out_a (float [n]) and out_b (float [n,3]) -- with
+ * trivial arithmetic (out_a = t0 + t1 + sigma, out_b = 2 rgb), so that its
+ * time is the ceiling of that traffic pattern on the device.  Arrays 16-byte
+ * aligned.                                                                  */
+txs_status txs_stream_probe(int64_t n_samples, const float* t0, const float* t1,
+                            const float* sigma, const float* rgb, float* out_a, float* out_b,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,7 @@ from .ops import (GridSpec, MlpSpec, adam_step, blob_field, edges_to_intervals,
                   exclusive_scan, gather_prefix,
                   hist_loss, march_count, march_fill, mlp_param_count, prop_mlp_bwd,
                   prop_mlp_fwd, render_bwd,
-                  render_fwd, resample, resample_intervals, transmittance_prefix, uniform_bins, weights_bwd)
+                  render_fwd, resample, resample_intervals, stream_probe, transmittance_prefix, uniform_bins, weights_bwd)
 from .pipeline import (Packed, RenderFn, filter_transmittance, march, rendering,
                        rendering_dense, sampling)
 

@@ -64,6 +64,7 @@ SIGNATURES = {
     "txs_prop_mlp_bwd": (I32, [MLP, P, P, I32, I32, P, P, P, P, SZ, P]),
     "txs_hist_loss": (I32, [P, I32, I64, P, P, P, I32, P, P, F32, P, P, P]),
     "txs_adam_step": (I32, [P, P, P, P, I64, F32, F32, F32, F32, I32, P]),
+    "txs_stream_probe": (I32, [I64, P, P, P, P, P, P, P]),
 }
 
 _lock = threading.Lock()

@@ -387,3 +387,15 @@ def prop_mlp_fwd(mlp: MlpSpec, rays_o, rays_d, edges):
     check(load().txs_prop_mlp_fwd(C.byref(m), _ptr(rays_o), _ptr(rays_d), n, nb1 - 1,
                                   _ptr(edges), _ptr(out), _stream()), "txs_prop_mlp_fwd")
     return out
+
+
+def stream_probe(t0, t1, sigma, rgb, out_a, out_b):
+    """Measurement support: the render adjoint's traffic with trivial arithmetic."""
+    n = t0.shape[0]
+    for name, t in (("t0", t0), ("t1", t1), ("sigma", sigma), ("out_a", out_a)):
+        _need(t, name, torch.float32, (n,))
+    _need(rgb, "rgb", torch.float32, (n, 3))
+    _need(out_b, "out_b", torch.float32, (n, 3))
+    check(load().txs_stream_probe(n, _ptr(t0), _ptr(t1), _ptr(sigma), _ptr(rgb), _ptr(out_a),
+                                  _ptr(out_b), _stream()), "txs_stream_probe")
+

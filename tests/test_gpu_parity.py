@@ -439,3 +439,17 @@ def test_blob_field(gpu_lib):
     s = host(s)
     assert np.all(np.abs(s - rs) <= 2e-4 * rs + 1e-6 * w.fld.peak)
     assert np.all(np.abs(host(c) - rc) <= 1e-4)
+
+
+@pytest.mark.parametrize("n", [1, 511, 512 * 16384 + 777])
+def test_stream_probe_outputs(gpu_lib, n):
+    # measurement support: its outputs are exact sums, so its reads and writes
+    # cover every sample once (full windows and the tail of each range)
+    g = scenes.rng(50)
+    t0, t1, s = (g.random(n, dtype=np.float32) for _ in range(3))
+    rgb = g.random((n, 3), dtype=np.float32)
+    oa = torch.empty(n, dtype=torch.float32, device="cuda")
+    ob = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    gpu_lib.stream_probe(dev(t0), dev(t1), dev(s), dev(rgb), oa, ob)
+    assert np.array_equal(host(oa), (t0 + t1) + s)
+    assert np.array_equal(host(ob), rgb + rgb)
