@@ -349,6 +349,29 @@ txs_status txs_blob_field(const float* params, int32_t n_blobs, const float* ray
                           float* rgb, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Update of the occupancy-grid estimator (Section 3.1 "Spatial Skipping";
+ * Table 1, occupancy-grid row, EMA update): the density cached per cell is
+ * blended with the radiance field's density at one point of the cell,
+ *   D_c <- gamma D_c + (1 - gamma) sigma_c,
+ * and the grid bit of the cell is set iff D_c > tau.  Cells are ordered as
+ * the grid's bits (level-major, i = x + res (y + res z)); n_cells =
+ * n_levels res^3.  The caller evaluates its field at the points of
+ * txs_grid_points and passes the densities to txs_grid_ema.
+ *
+ * txs_grid_points: points float [n_cells, 3], the point of cell (x, y, z) on
+ * level l being bmin_l + (index + u) (2 half_extent0 2^l / res) per axis, in
+ * binary32; u float [n_cells, 3] in [0, 1) (per-cell jitter) or NULL for the
+ * cell centres (u = 1/2).  grid->bits is not read.
+ *
+ * txs_grid_ema: density float [n_cells] (in/out, the cache), sigma float
+ * [n_cells], 0 <= gamma <= 1; writes the n_cells / 32 grid words of bits.
+ * n_cells must be a multiple of 32 (res >= 4).  Binary32 arithmetic.
+ */
+txs_status txs_grid_points(const txs_grid* grid, const float* u, float* points, void* stream);
+txs_status txs_grid_ema(int64_t n_cells, float* density, const float* sigma, float gamma,
+                        float tau, uint32_t* bits, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Measurement support (not part of the method).  Moves the HBM traffic of
  * txs_render_bwd in its layout -- reads t0, t1, sigma (float [n]) and rgb
  * (float [n,3]); writes out_a (float [n]) and out_b (float [n,3]) -- with

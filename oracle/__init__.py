@@ -297,3 +297,22 @@ def adam(p, m, v, g, lr, b1=0.9, b2=0.99, eps=1e-15, step=1):
     lib().oracle_adam(C.c_int64(p.size), _p(p), _p(m), _p(v), _p(_f64(g)), C.c_double(lr),
                       C.c_double(b1), C.c_double(b2), C.c_double(eps), C.c_int32(step))
     return p, m, v
+
+
+def grid_points(res, n_levels=1, center=(0.0, 0.0, 0.0), half_extent0=1.5, u=None):
+    """One point per cell, level-major, cell index x + res (y + res z) -> [L res^3, 3]."""
+    n = n_levels * res ** 3
+    out = np.zeros((n, 3), np.float64)
+    lib().oracle_grid_points(C.c_int32(res), C.c_int32(n_levels), _p(_f32(center)),
+                             C.c_double(half_extent0), _p(None if u is None else _f32(u)),
+                             _p(out))
+    return out
+
+
+def grid_ema(density, sigma, gamma, tau):
+    """D <- gamma D + (1 - gamma) sigma; occupied = D > tau -> (D, occupied bool)."""
+    d = _f64(density).copy()
+    occ = np.zeros(d.shape[0], np.uint8)
+    lib().oracle_grid_ema(C.c_int64(d.shape[0]), _p(d), _p(_f64(sigma)), C.c_double(gamma),
+                          C.c_double(tau), _p(occ))
+    return d, occ.astype(bool)

@@ -448,3 +448,41 @@ EXPORT int32_t oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/*
+ * Update of the occupancy-grid estimator (Section 3.1 "Spatial Skipping";
+ * the update column of Table 1's occupancy-grid row): the density cached per
+ * cell is blended with the radiance field's density at a point of the cell by
+ * an exponential moving average over updates,
+ *   D_c <- gamma D_c + (1 - gamma) sigma_c,
+ * and the cell is occupied iff D_c > tau (the binarisation of the estimator).
+ *
+ * Cells are indexed as the grid's bits: level-major, i = x + res (y + res z).
+ * The point of cell (x, y, z) on level l is
+ *   bmin_l + (index + u) * (2 h0 2^l / res),   u in [0, 1)^3,
+ * with u = (1/2, 1/2, 1/2) (the cell centre) when no jitter is given.
+ */
+EXPORT void oracle_grid_points(int32_t res, int32_t n_levels, const float* center, double h0,
+                               const float* u, double* out) {
+  const int64_t n_cell = (int64_t)res * res * res;
+  for (int l = 0; l < n_levels; ++l) {
+    const double h = h0 * (double)(1 << l);
+    const double cs = 2.0 * h / res;
+    for (int64_t i = 0; i < n_cell; ++i) {
+      const int64_t c = (int64_t)l * n_cell + i;
+      const int64_t idx[3] = {i % res, (i / res) % res, i / ((int64_t)res * res)};
+      for (int a = 0; a < 3; ++a) {
+        const double ua = u ? (double)u[3 * c + a] : 0.5;
+        out[3 * c + a] = ((double)center[a] - h) + ((double)idx[a] + ua) * cs;
+      }
+    }
+  }
+}
+
+EXPORT void oracle_grid_ema(int64_t n, double* density, const double* sigma, double gamma,
+                            double tau, uint8_t* occupied) {
+  for (int64_t c = 0; c < n; ++c) {
+    density[c] = gamma * density[c] + (1.0 - gamma) * sigma[c];
+    occupied[c] = density[c] > tau;
+  }
+}

@@ -65,6 +65,8 @@ SIGNATURES = {
     "txs_hist_loss": (I32, [P, I32, I64, P, P, P, I32, P, P, F32, P, P, P]),
     "txs_adam_step": (I32, [P, P, P, P, I64, F32, F32, F32, F32, I32, P]),
     "txs_stream_probe": (I32, [I64, P, P, P, P, P, P, P]),
+    "txs_grid_points": (I32, [GP, P, P, P]),
+    "txs_grid_ema": (I32, [I64, P, P, F32, F32, P, P]),
 }
 
 _lock = threading.Lock()

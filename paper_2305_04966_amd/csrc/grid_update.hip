@@ -1,0 +1,82 @@
+// Update of the occupancy-grid estimator (Section 3.1 "Spatial Skipping";
+// Table 1, occupancy-grid row, update column): an exponential moving average
+// of the radiance field's density at one point per cell, binarised at a
+// threshold into the grid the marcher reads.
+#include "txs_common.h"
+
+namespace txs {
+namespace {
+
+// point of every cell: bmin_l + (index + u) * cell size, u = 1/2 without jitter
+__global__ __launch_bounds__(256) void grid_points_kernel(int32_t res, int32_t n_levels,
+                                                          float cx, float cy, float cz, float h0,
+                                                          const float* __restrict__ u,
+                                                          float* __restrict__ out) {
+  const int64_t n_cell = (int64_t)res * res * res;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cell * n_levels) return;
+  const int l = (int)(c / n_cell);
+  const int64_t i = c - (int64_t)l * n_cell;
+  const float h = h0 * (float)(1 << l);
+  const float cs = 2.0f * h / (float)res;
+  const int64_t idx[3] = {i % res, (i / res) % res, i / ((int64_t)res * res)};
+  const float ctr[3] = {cx, cy, cz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float ua = u ? u[3 * c + a] : 0.5f;
+    out[3 * c + a] = (ctr[a] - h) + ((float)idx[a] + ua) * cs;
+  }
+}
+
+// D <- gamma D + (1 - gamma) sigma; bit c of the grid = D_c > tau.  One lane
+// per cell; a wave's 64 decisions become two grid words by ballot.
+__global__ __launch_bounds__(256) void grid_ema_kernel(int64_t n, float* __restrict__ density,
+                                                       const float* __restrict__ sigma,
+                                                       float gamma, float tau,
+                                                       uint32_t* __restrict__ bits) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool occ = false;
+  if (c < n) {
+    const float d = gamma * density[c] + (1.0f - gamma) * sigma[c];
+    density[c] = d;
+    occ = d > tau;
+  }
+  const uint64_t m = __ballot(occ);
+  const int64_t c0 = c - lane();  // first cell of this wave (multiple of 64)
+  if (lane() == 0 && c0 < n) bits[c0 >> 5] = (uint32_t)m;
+  if (lane() == 32 && c < n) bits[c0 >> 5 | 1] = (uint32_t)(m >> 32);
+}
+
+}  // namespace
+}  // namespace txs
+
+extern "C" txs_status txs_grid_points(const txs_grid* grid, const float* u, float* points,
+                                      void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(grid, "txs_grid_points: null grid");
+  const int res = grid->res;
+  TXS_REQUIRE(res >= 2 && res <= 1024 && (res & (res - 1)) == 0,
+              "txs_grid_points: res must be a power of two in [2,1024], got %d", res);
+  TXS_REQUIRE(grid->n_levels >= 1 && grid->n_levels <= 8, "txs_grid_points: bad n_levels");
+  TXS_REQUIRE(grid->half_extent0 > 0.0f, "txs_grid_points: bad half_extent0");
+  TXS_REQUIRE(points, "txs_grid_points: null points");
+  const int64_t n = (int64_t)res * res * res * grid->n_levels;
+  hipLaunchKernelGGL(grid_points_kernel, dim3(grid_1d(n, 256)), dim3(256), 0, as_stream(stream),
+                     res, grid->n_levels, grid->center[0], grid->center[1], grid->center[2],
+                     grid->half_extent0, u, points);
+  return launch_status("txs_grid_points");
+}
+
+extern "C" txs_status txs_grid_ema(int64_t n_cells, float* density, const float* sigma,
+                                   float gamma, float tau, uint32_t* bits, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(n_cells >= 0 && n_cells % 32 == 0, "txs_grid_ema: n_cells must be a multiple of 32");
+  TXS_REQUIRE(gamma >= 0.0f && gamma <= 1.0f, "txs_grid_ema: gamma must be in [0,1]");
+  if (n_cells == 0) return TXS_OK;
+  TXS_REQUIRE(density && sigma && bits, "txs_grid_ema: null array");
+  hipLaunchKernelGGL(grid_ema_kernel, dim3(grid_1d(n_cells, 256)), dim3(256), 0,
+                     as_stream(stream), n_cells, density, sigma, gamma, tau, bits);
+  return launch_status("txs_grid_ema");
+}

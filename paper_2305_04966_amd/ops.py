@@ -389,6 +389,26 @@ def prop_mlp_fwd(mlp: MlpSpec, rays_o, rays_d, edges):
     return out
 
 
+def grid_points(grid: GridSpec, u=None):
+    """One point per grid cell (centres, or jittered by u [n_cells, 3]) -> [n_cells, 3]."""
+    n = grid.n_levels * grid.res ** 3
+    g = grid.struct()
+    _opt(u, "u", torch.float32, (n, 3))
+    out = torch.empty((n, 3), dtype=torch.float32, device=grid.bits.device)
+    check(load().txs_grid_points(C.byref(g), _ptr(u), _ptr(out), _stream()), "txs_grid_points")
+    return out
+
+
+def grid_ema(density, sigma, gamma, tau, bits):
+    """In place: density <- gamma density + (1 - gamma) sigma; bits <- density > tau."""
+    n = density.shape[0]
+    _need(density, "density", torch.float32, (n,))
+    _need(sigma, "sigma", torch.float32, (n,))
+    _need(bits, "bits", torch.int32, (n // 32,))
+    check(load().txs_grid_ema(n, _ptr(density), _ptr(sigma), float(gamma), float(tau),
+                              _ptr(bits), _stream()), "txs_grid_ema")
+
+
 def stream_probe(t0, t1, sigma, rgb, out_a, out_b):
     """Measurement support: the render adjoint's traffic with trivial arithmetic."""
     n = t0.shape[0]

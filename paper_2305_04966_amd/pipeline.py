@@ -107,3 +107,31 @@ def rendering(p: Packed, sigma, rgb, bg=None):
 
 def rendering_dense(t0, t1, sigma, rgb, n_rays, fixed_count, bg=None):
     return RenderFn.apply(sigma, rgb, None, t0, t1, bg, n_rays, fixed_count)
+
+
+class OccupancyGrid:
+    """The occupancy-grid transmittance estimator with its EMA update.
+
+    density: float32 [n_levels res^3] cached density; grid: the GridSpec whose
+    bits the marcher reads (updated in place).  update() evaluates
+    density_fn(points [n, 3]) -> sigma [n] at one point per cell and blends
+    it in (Section 3.1, Spatial Skipping; Table 1, occupancy-grid row).
+    """
+
+    def __init__(self, grid: ops.GridSpec, density: Optional[torch.Tensor] = None):
+        n = grid.n_levels * grid.res ** 3
+        self.grid = grid
+        self.density = (density if density is not None else
+                        torch.zeros(n, dtype=torch.float32, device=grid.bits.device))
+
+    def update(self, density_fn: Callable, gamma=0.95, tau=0.01, u=None):
+        pts = ops.grid_points(self.grid, u)
+        sigma = density_fn(pts)
+        ops.grid_ema(self.density, sigma, gamma, tau, self.grid.bits)
+
+    def update_every_n_steps(self, step, density_fn: Callable, n=16, gamma=0.95, tau=0.01,
+                             u=None):
+        """Algorithm 1's estimator update for the grid: every n-th training step."""
+        if step % n == 0:
+            self.update(density_fn, gamma, tau, u)
+

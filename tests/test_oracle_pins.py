@@ -596,3 +596,43 @@ def test_field_shell_is_opaque_and_grid_is_conservative():
     cell = np.clip(np.floor((x + 1.5) / 3.0 * res).astype(int), 0, res - 1)
     idx = cell[:, 0] + res * (cell[:, 1] + res * cell[:, 2])
     assert np.all(occ[idx[s > 0.01]])
+
+
+# ----------------------------------------------------------------------------
+# occupancy-grid EMA update (Section 3.1, Spatial Skipping)
+# ----------------------------------------------------------------------------
+def test_grid_points_closed_form_and_inside_cells():
+    pts = oracle.grid_points(4, n_levels=2, half_extent0=1.5)
+    # level 0 cell (0,0,0): centre -1.5 + 0.5 * 0.75
+    np.testing.assert_allclose(pts[0], [-1.125] * 3, rtol=0, atol=1e-15)
+    # level 1 cell (3,2,1): h = 3, cell 1.5 -> (-3 + 3.5*1.5, -3 + 2.5*1.5, -3 + 1.5*1.5)
+    i = 64 + 3 + 4 * (2 + 4 * 1)
+    np.testing.assert_allclose(pts[i], [2.25, 0.75, -0.75], rtol=0, atol=1e-15)
+    # jittered points stay in their own cells
+    res, L = 8, 3
+    u = scenes.rng(60).random((L * res ** 3, 3)).astype(np.float32) * np.float32(0.999)
+    p = oracle.grid_points(res, n_levels=L, half_extent0=1.5, u=u)
+    for l in range(L):
+        h = 1.5 * 2 ** l
+        q = p[l * res ** 3:(l + 1) * res ** 3]
+        cell = np.floor((q + h) / (2 * h / res)).astype(int)
+        i = np.arange(res ** 3)
+        assert np.array_equal(cell[:, 0], i % res)
+        assert np.array_equal(cell[:, 1], (i // res) % res)
+        assert np.array_equal(cell[:, 2], i // res ** 2)
+
+
+def test_grid_ema_closed_forms():
+    g = scenes.rng(61)
+    d0 = g.exponential(1.0, 256)
+    s = g.exponential(1.0, 256)
+    # gamma = 0: the cache becomes the new density; gamma = 1: unchanged
+    d, occ = oracle.grid_ema(d0, s, 0.0, 0.5)
+    assert np.array_equal(d, s) and np.array_equal(occ, s > 0.5)
+    d, occ = oracle.grid_ema(d0, s, 1.0, 0.5)
+    assert np.array_equal(d, d0)
+    # k updates with a constant density: D_k = s + gamma^k (D_0 - s)
+    gamma, d = 0.9, d0.copy()
+    for _ in range(25):
+        d, _ = oracle.grid_ema(d, s, gamma, 0.5)
+    np.testing.assert_allclose(d, s + gamma ** 25 * (d0 - s), rtol=1e-13)
