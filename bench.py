@@ -51,6 +51,11 @@ def parse():
                          "report learned vs grid sampling (0 = skip)")
     ap.add_argument("--learned-train-stride", type=int, default=4)
     ap.add_argument("--learned-sweep", default="128,160,192,224,256")
+    ap.add_argument("--combined-steps", type=int, default=300,
+                    help="train the proposal network alone and inside the grid's occupied "
+                         "spans this many steps each on the image scene and report both "
+                         "(0 = skip)")
+    ap.add_argument("--combined-sweep", default="32,48,64,96,128,192,256")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run a plain device copy of this many MiB (counter "
                          "calibration for profiler byte counts)")
@@ -218,6 +223,20 @@ def learned_vs_grid(args):
     return out
 
 
+def combined_vs_proposal(args):
+    """The combined estimator (grid first, proposal network inside each ray's
+    occupied span) against the proposal network alone on the image scene:
+    both trained alike (untimed), then timed end to end (fwd + bwd, field
+    stand-in included) on all 2^20 rays at their fewest final samples within
+    1e-3 mean rgb error of the grid renderer."""
+    from train_proposal import run_combined
+    rec = run_combined(steps=args.combined_steps, train_stride=args.learned_train_stride,
+                       sweep=[int(s) for s in args.combined_sweep.split(",")],
+                       log_every=max(args.combined_steps, 1), time_reps=3,
+                       log=lambda s: print(s, file=sys.stderr, flush=True))
+    return rec
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed profiler record
     (FETCH_SIZE and WRITE_SIZE, calibrated by a device copy of known size), or
@@ -323,6 +342,8 @@ def main():
     }
     if args.learned_steps > 0:
         rec["learned_vs_grid"] = learned_vs_grid(args)
+    if args.combined_steps > 0:
+        rec["combined_vs_proposal"] = combined_vs_proposal(args)
     if rank == 0 and args.cpu_sample > 0:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     if rank == 0:

@@ -234,6 +234,7 @@ txs_status txs_resample_intervals(int32_t n_rays, int32_t n_bins, const float* e
  * ray over its chord through the outermost cube of `grid` (bits unused),
  *   e_k = t_near + (t_far - t_near) * (k / n_bins),   out: float [n_rays, n_bins+1].
  * A ray that misses gets all edges equal to max(near_plane, 0) and t_far = t_near.
+ * 1 <= n_bins <= 2^24.
  */
 txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, float far_plane,
                             const float* rays_o, const float* rays_d, int32_t n_rays,
@@ -370,6 +371,43 @@ txs_status txs_blob_field(const float* params, int32_t n_blobs, const float* ray
 txs_status txs_grid_points(const txs_grid* grid, const float* u, float* points, void* stream);
 txs_status txs_grid_ema(int64_t n_cells, float* density, const float* sigma, float gamma,
                         float tau, uint32_t* bits, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Combined estimator (Section 3.1 "Insights from Unified Formulation";
+ * Section 5 "Combined Sampling"): the occupancy grid's transmittance comes
+ * first -- rays that cross no occupied cell are dropped and every other ray is
+ * narrowed to its occupied span -- and the proposal network refines inside
+ * that span (uniform bins -> proposal density -> inverse CDF).
+ *
+ * txs_march_span: the march of txs_march_count / txs_march_fill (same grid,
+ * params, recipe and errors; params->max_per_ray must be 0) without its
+ * samples: span float [n_rays, 2] = (t0 of the ray's first sample, t1 of its
+ * last), bit-identical to those samples' t0 and t1; hit int32 [n_rays] = 1 if
+ * the ray has a sample, else 0 (and span = (0, 0)).
+ *
+ * Compaction table: table int32 [n_rays, 2] = txs_exclusive_scan of hit, i.e.
+ * (slot_r, hit_r); the rays that hit own rows 0 .. total-1 of the compacted
+ * set in ray order.
+ * txs_compact_rows: dst row slot_r = src row r for every ray with hit_r = 1;
+ *   rows of `width` 32-bit words (any type; 1 <= width <= 64), src
+ *   [n_rays, width], dst [total, width].  Other memory is not written.
+ * txs_expand_rows: dst row r = src row slot_r if hit_r, else `fill` in every
+ *   word; src float [total, width] (may be NULL when total = 0), dst float
+ *   [n_rays, width].
+ * txs_span_bins: n_bins+1 equally spaced edges over each span,
+ *   e_k = lo + (hi - lo) * (k / n_bins) in binary32 (the recipe of
+ *   txs_uniform_bins), span float [n_rays, 2], out float [n_rays, n_bins+1],
+ *   1 <= n_bins <= 2^24.
+ */
+txs_status txs_march_span(const txs_grid* grid, const txs_march_params* params,
+                          const float* rays_o, const float* rays_d, int32_t n_rays, float* span,
+                          int32_t* hit, void* stream);
+txs_status txs_compact_rows(int32_t n_rays, const int32_t* table, int32_t width, const void* src,
+                            void* dst, void* stream);
+txs_status txs_expand_rows(int32_t n_rays, const int32_t* table, int32_t width, const float* src,
+                           float fill, float* dst, void* stream);
+txs_status txs_span_bins(int32_t n_rays, const float* span, int32_t n_bins, float* out_edges,
+                         void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Measurement support (not part of the method).  Moves the HBM traffic of

@@ -316,3 +316,24 @@ def grid_ema(density, sigma, gamma, tau):
     lib().oracle_grid_ema(C.c_int64(d.shape[0]), _p(d), _p(_f64(sigma)), C.c_double(gamma),
                           C.c_double(tau), _p(occ))
     return d, occ.astype(bool)
+
+
+def march_span(o, d, bits, res, **march_kw):
+    """Occupied span of every ray (Section 5, "Combined Sampling": the grid
+    shrinks each ray's near-far interval to where it found occupied space):
+    (t0 of the first sample, t1 of the last) of the dense march, (0, 0) for a
+    ray with none -> (span float32 [N, 2], hit int32 [N])."""
+    m = march(o, d, bits, res, **march_kw)
+    start, cnt = m["packed_info"][:, 0].astype(np.int64), m["counts"].astype(np.int64)
+    hit = cnt > 0
+    span = np.zeros((cnt.shape[0], 2), np.float32)
+    span[hit, 0] = m["t0"][start[hit]]
+    span[hit, 1] = m["t1"][start[hit] + cnt[hit] - 1]
+    return span, hit.astype(np.int32)
+
+
+def span_bins(span, n_bins):
+    """n_bins+1 equally spaced edges over each span, in binary64 -> [N, n_bins+1]."""
+    s = _f64(span)
+    k = np.arange(n_bins + 1, dtype=np.float64) / n_bins
+    return s[:, :1] + (s[:, 1:2] - s[:, :1]) * k

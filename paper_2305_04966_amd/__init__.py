@@ -6,12 +6,11 @@ Importing it does not touch the GPU; `load()` raises if the library is absent.
 """
 from ._lib import (TXS_EHIP, TXS_EINVAL, TXS_ECAPACITY, TXS_EOVERFLOW, TXS_OK,
                    TXS_PDF_SIGMA, TXS_PDF_WEIGHTS, LIB_PATH, TxsError, exported_symbols, load)
-from .ops import (GridSpec, MlpSpec, adam_step, blob_field, edges_to_intervals, grid_ema,
-                  grid_points,
-                  exclusive_scan, gather_prefix,
-                  hist_loss, march_count, march_fill, mlp_param_count, prop_mlp_bwd,
-                  prop_mlp_fwd, render_bwd,
-                  render_fwd, resample, resample_intervals, stream_probe, transmittance_prefix, uniform_bins, weights_bwd)
+from .ops import (GridSpec, MlpSpec, adam_step, blob_field, compact_rows, edges_to_intervals,
+                  exclusive_scan, expand_rows, gather_prefix, grid_ema, grid_points, hist_loss,
+                  march_count, march_fill, march_span, mlp_param_count, prop_mlp_bwd,
+                  prop_mlp_fwd, render_bwd, render_fwd, resample, resample_intervals,
+                  span_bins, stream_probe, transmittance_prefix, uniform_bins, weights_bwd)
 from .pipeline import (OccupancyGrid, Packed, RenderFn, filter_transmittance, march, rendering,
                        rendering_dense, sampling)
 

@@ -67,6 +67,10 @@ SIGNATURES = {
     "txs_stream_probe": (I32, [I64, P, P, P, P, P, P, P]),
     "txs_grid_points": (I32, [GP, P, P, P]),
     "txs_grid_ema": (I32, [I64, P, P, F32, F32, P, P]),
+    "txs_march_span": (I32, [GP, MP, P, P, I32, P, P, P]),
+    "txs_compact_rows": (I32, [I32, P, I32, P, P, P]),
+    "txs_expand_rows": (I32, [I32, P, I32, P, F32, P, P]),
+    "txs_span_bins": (I32, [I32, P, I32, P, P]),
 }
 
 _lock = threading.Lock()

@@ -65,6 +65,10 @@ __device__ __forceinline__ void clip_box(const float o[3], const float inv[3], c
   tf = t_far;
 }
 
+// What a march pass produces: per-ray sample counts, the samples themselves,
+// or the span [t0 of the first sample, t1 of the last] without the samples.
+enum MarchMode : int { kCount = 0, kFill = 1, kSpan = 2 };
+
 struct Emit {
   float* t0;
   float* t1;
@@ -72,63 +76,91 @@ struct Emit {
   int64_t base;
   int64_t capacity;
   int32_t ray;
+  float lo, hi;  // kSpan: the span so far (wave-uniform)
 };
+
+// Lattice point k of segment [a, b) on level l: its midpoint a + (k + 1/2) dt
+// must lie before b; valid points issue the load of their cell's grid word.
+struct Lattice {
+  LevelBox box;
+  const uint32_t* bits;
+  float a, b, dt, resf;
+  int res;
+};
+
+__device__ __forceinline__ Lattice lattice(const MarchArgs& g, float a, float b, int l) {
+  Lattice p;
+  p.box = level_box(g, l);
+  p.bits = g.bits + (int64_t)l * g.level_words;
+  p.a = a;
+  p.b = b;
+  p.dt = g.dt0 * (float)(1 << l);
+  p.res = g.res;
+  p.resf = (float)g.res;
+  return p;
+}
+
+__device__ __forceinline__ bool probe(const Lattice& p, const float o[3], const float d[3],
+                                      int32_t k, uint32_t& word, int32_t& sh) {
+  const float m = p.a + ((float)k + 0.5f) * p.dt;
+  const bool valid = (k >= 0) && (k < kLatticeLimit) && (m < p.b);
+  word = 0u;
+  sh = 0;
+  if (valid) {
+    int cell[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float x = o[c] + m * d[c];
+      const float u = (x - p.box.bmin[c]) * p.box.scale[c];
+      float f = floorf(u);
+      f = fminf(fmaxf(f, 0.0f), p.resf - 1.0f);
+      cell[c] = (int)f;
+    }
+    const int32_t idx = cell[0] + p.res * (cell[1] + p.res * cell[2]);
+    word = p.bits[idx >> 5];
+    sh = idx & 31;
+  }
+  return valid;
+}
 
 // One segment [a, b) on level l.  Each step tests kGroups groups of 64
 // consecutive lattice points (one per lane), with all their grid-word loads in
 // flight together, then emits the groups in k order.  n: samples so far
-// (wave-uniform); returns the new count.
+// (wave-uniform); returns the new count.  kSpan stops at the first occupied
+// point, records its t0 in em.lo and returns a non-zero count.
 constexpr int kGroups = 2;
 
-template <bool kFill>
+template <int kMode>
 __device__ __forceinline__ int32_t march_segment(const MarchArgs& g, const float o[3],
                                                  const float d[3], float a, float b, int l,
-                                                 int32_t n, int32_t cap, const Emit& em) {
-  const float dt = g.dt0 * (float)(1 << l);
-  const LevelBox box = level_box(g, l);
-  const int res = g.res;
-  const float resf = (float)res;
-  const uint32_t* bits = g.bits + (int64_t)l * g.level_words;
+                                                 int32_t n, int32_t cap, Emit& em) {
+  const Lattice p = lattice(g, a, b, l);
   const int ln = lane();
   for (int32_t k0 = 0; k0 < kLatticeLimit; k0 += kWave * kGroups) {
     bool valid[kGroups], occ[kGroups];
     uint32_t word[kGroups];
     int32_t sh[kGroups];
 #pragma unroll
-    for (int q = 0; q < kGroups; ++q) {
-      const int32_t k = k0 + kWave * q + ln;
-      const float m = a + ((float)k + 0.5f) * dt;
-      valid[q] = (k < kLatticeLimit) && (m < b);
-      word[q] = 0u;
-      sh[q] = 0;
-      if (valid[q]) {
-        int cell[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float x = o[c] + m * d[c];
-          const float u = (x - box.bmin[c]) * box.scale[c];
-          float f = floorf(u);
-          f = fminf(fmaxf(f, 0.0f), resf - 1.0f);
-          cell[c] = (int)f;
-        }
-        const int32_t idx = cell[0] + res * (cell[1] + res * cell[2]);
-        word[q] = bits[idx >> 5];
-        sh[q] = idx & 31;
-      }
-    }
+    for (int q = 0; q < kGroups; ++q) valid[q] = probe(p, o, d, k0 + kWave * q + ln, word[q], sh[q]);
 #pragma unroll
     for (int q = 0; q < kGroups; ++q) occ[q] = valid[q] && ((word[q] >> sh[q]) & 1u);
 #pragma unroll
     for (int q = 0; q < kGroups; ++q) {
       const int32_t k = k0 + kWave * q + ln;
       const uint64_t mask = __ballot(occ[q]);
-      if (kFill && occ[q]) {
+      if (kMode == kSpan && mask != 0) {
+        // the fill pass's binary32 t0 at the lowest occupied k
+        const int32_t kf = k0 + kWave * q + (int32_t)__builtin_ctzll(mask);
+        em.lo = a + (float)kf * p.dt;
+        return n + __popcll(mask);
+      }
+      if (kMode == kFill && occ[q]) {
         const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
             (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
         const int64_t pos = em.base + n + rank;
         if ((cap == 0 || n + rank < cap) && pos < em.capacity) {
-          em.t0[pos] = a + (float)k * dt;
-          em.t1[pos] = fminf(a + (float)(k + 1) * dt, b);
+          em.t0[pos] = a + (float)k * p.dt;
+          em.t1[pos] = fminf(a + (float)(k + 1) * p.dt, b);
           if (em.ray_id) em.ray_id[pos] = em.ray;
         }
       }
@@ -140,9 +172,52 @@ __device__ __forceinline__ int32_t march_segment(const MarchArgs& g, const float
   return n;
 }
 
-template <bool kFill>
+// Last lattice point of segment [a, b): the largest k < kLatticeLimit with
+// a + (k + 1/2) dt < b in binary32, or -1.  That midpoint is non-decreasing in
+// k, so the segment's points are exactly k = 0 .. kmax (the forward pass
+// visits the same set); the quotient estimate is off by a few units at most.
+__device__ __forceinline__ int32_t last_lattice_point(float a, float b, float dt) {
+  auto inside = [&](int32_t k) { return a + ((float)k + 0.5f) * dt < b; };
+  const float e = floorf((b - a) / dt - 0.5f);
+  int32_t k = !(e >= 0.0f) ? -1 : (e >= (float)(kLatticeLimit - 1) ? kLatticeLimit - 1 : (int32_t)e);
+  while (k + 1 < kLatticeLimit && inside(k + 1)) ++k;
+  while (k >= 0 && !inside(k)) --k;
+  return k;
+}
+
+// Highest occupied lattice point of segment [a, b) on level l, scanning k
+// downwards from the last point kGroups groups of 64 at a time; on success
+// em.hi = the fill pass's binary32 t1 of that sample.
+__device__ __forceinline__ bool span_back(const MarchArgs& g, const float o[3], const float d[3],
+                                          float a, float b, int l, Emit& em) {
+  const Lattice p = lattice(g, a, b, l);
+  const int32_t kmax = last_lattice_point(a, b, p.dt);
+  const int ln = lane();
+  for (int32_t k0 = 0; k0 <= kmax; k0 += kWave * kGroups) {
+    bool occ[kGroups];
+    uint32_t word[kGroups];
+    int32_t sh[kGroups];
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q)
+      occ[q] = probe(p, o, d, kmax - (k0 + kWave * q + ln), word[q], sh[q]);
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) occ[q] = occ[q] && ((word[q] >> sh[q]) & 1u);
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) {
+      const uint64_t mask = __ballot(occ[q]);
+      if (mask != 0) {
+        const int32_t kl = kmax - (k0 + kWave * q + (int32_t)__builtin_ctzll(mask));
+        em.hi = fminf(a + (float)(kl + 1) * p.dt, b);
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
+template <int kMode>
 __device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const float o[3], const float d[3],
-                             const Emit& em) {
+                                             Emit& em) {
   float inv[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) inv[c] = 1.0f / d[c];
@@ -164,36 +239,53 @@ __device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const float o[3
   auto tn = [&](int l) { return readlane(tn_l, l); };
   auto tf = [&](int l) { return readlane(tf_l, l); };
 
-  const int32_t cap = g.max_per_ray;
-  int32_t n = 0;
-  // segments in increasing t: descend from the outermost level, then ascend
-  for (int s = 0; s < 2 * L - 1; ++s) {
-    int l;
-    float a, b;
+  // segment s in increasing t: descend from the outermost level, then ascend;
+  // false if the ray does not cross it
+  auto segment = [&](int s, int& l, float& a, float& b) {
     if (s < L) {
       l = L - 1 - s;
-      if (!((hit >> l) & 1u)) continue;
+      if (!((hit >> l) & 1u)) return false;
       a = tn(l);
       b = (l > 0 && ((hit >> (l - 1)) & 1u)) ? tn(l - 1) : tf(l);
     } else {
       l = s - L + 1;
-      if (!((hit >> l) & 1u) || !((hit >> (l - 1)) & 1u)) continue;
+      if (!((hit >> l) & 1u) || !((hit >> (l - 1)) & 1u)) return false;
       a = tf(l - 1);
       b = tf(l);
     }
-    n = march_segment<kFill>(g, o, d, a, b, l, n, cap, em);
+    return true;
+  };
+
+  const int32_t cap = g.max_per_ray;
+  int32_t n = 0;
+  int l;
+  float a, b;
+  if (kMode == kSpan) {
+    // the first occupied point going forward, then the last one going back
+    int s_first = -1;
+    for (int s = 0; s < 2 * L - 1 && s_first < 0; ++s)
+      if (segment(s, l, a, b) && march_segment<kSpan>(g, o, d, a, b, l, 0, 0, em) > 0)
+        s_first = s;
+    if (s_first < 0) return 0;
+    for (int s = 2 * L - 2; s >= s_first; --s)
+      if (segment(s, l, a, b) && span_back(g, o, d, a, b, l, em)) break;
+    return 1;
+  }
+  for (int s = 0; s < 2 * L - 1; ++s) {
+    if (!segment(s, l, a, b)) continue;
+    n = march_segment<kMode>(g, o, d, a, b, l, n, cap, em);
     if (cap > 0 && n >= cap) break;
   }
   return n;
 }
 
-template <bool kFill>
+template <int kMode>
 __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float* __restrict__ ro,
                                                        const float* __restrict__ rd,
                                                        int32_t n_rays, int32_t* counts,
                                                        const int32_t* __restrict__ info,
                                                        int64_t capacity, float* t0, float* t1,
-                                                       int32_t* ray_id) {
+                                                       int32_t* ray_id, float* span) {
   // one ray per wave; the ray index is wave-uniform
   const int32_t r = __builtin_amdgcn_readfirstlane(
       (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
@@ -204,9 +296,15 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float*
     o[c] = ro[3 * (int64_t)r + c];
     d[c] = rd[3 * (int64_t)r + c];
   }
-  Emit em{t0, t1, ray_id, kFill ? (int64_t)info[2 * (int64_t)r] : 0, capacity, r};
-  const int32_t n = march_ray<kFill>(g, o, d, em);
-  if (!kFill && lane() == 0) counts[r] = n;
+  Emit em{t0, t1, ray_id, kMode == kFill ? (int64_t)info[2 * (int64_t)r] : 0, capacity, r,
+          0.0f, 0.0f};
+  const int32_t n = march_ray<kMode>(g, o, d, em);
+  if (kMode == kCount && lane() == 0) counts[r] = n;
+  if (kMode == kSpan && lane() == 0) {
+    span[2 * (int64_t)r] = em.lo;
+    span[2 * (int64_t)r + 1] = em.hi;
+    counts[r] = n > 0 ? 1 : 0;
+  }
 }
 
 txs_status make_args(const txs_grid* grid, const txs_march_params* p, MarchArgs& g) {
@@ -257,9 +355,9 @@ extern "C" txs_status txs_march_count(const txs_grid* grid, const txs_march_para
   TXS_REQUIRE(n_rays >= 0, "txs_march_count: n_rays < 0");
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && counts, "txs_march_count: null array");
-  hipLaunchKernelGGL(march_kernel<false>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
+  hipLaunchKernelGGL(march_kernel<kCount>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
                      as_stream(stream), g, rays_o, rays_d, n_rays, counts, nullptr, 0, nullptr,
-                     nullptr, nullptr);
+                     nullptr, nullptr, nullptr);
   return launch_status("txs_march_count");
 }
 
@@ -275,8 +373,25 @@ extern "C" txs_status txs_march_fill(const txs_grid* grid, const txs_march_param
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && packed_info, "txs_march_fill: null array");
   TXS_REQUIRE(capacity == 0 || (t0 && t1), "txs_march_fill: null output");
-  hipLaunchKernelGGL(march_kernel<true>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
+  hipLaunchKernelGGL(march_kernel<kFill>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
                      as_stream(stream), g, rays_o, rays_d, n_rays, nullptr, packed_info, capacity,
-                     t0, t1, ray_id);
+                     t0, t1, ray_id, nullptr);
   return launch_status("txs_march_fill");
+}
+
+extern "C" txs_status txs_march_span(const txs_grid* grid, const txs_march_params* params,
+                                     const float* rays_o, const float* rays_d, int32_t n_rays,
+                                     float* span, int32_t* hit, void* stream) {
+  using namespace txs;
+  clear_error();
+  MarchArgs g;
+  if (txs_status s = make_args(grid, params, g)) return s;
+  TXS_REQUIRE(g.max_per_ray == 0, "txs_march_span: max_per_ray must be 0");
+  TXS_REQUIRE(n_rays >= 0, "txs_march_span: n_rays < 0");
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(rays_o && rays_d && span && hit, "txs_march_span: null array");
+  hipLaunchKernelGGL(march_kernel<kSpan>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
+                     as_stream(stream), g, rays_o, rays_d, n_rays, hit, nullptr, 0, nullptr,
+                     nullptr, nullptr, span);
+  return launch_status("txs_march_span");
 }

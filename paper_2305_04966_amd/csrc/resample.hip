@@ -87,33 +87,79 @@ inline unsigned resample_blocks(int32_t n_rays) {
   return (unsigned)std::min<int64_t>(need, 256 * 16);
 }
 
-__global__ __launch_bounds__(256) void uniform_bins_kernel(txs_grid g, float near_plane,
-                                                           float far_plane,
-                                                           const float* __restrict__ ro,
-                                                           const float* __restrict__ rd,
-                                                           int32_t n_rays, int32_t n_bins,
-                                                           float* __restrict__ out) {
-  const int64_t total = (int64_t)n_rays * (n_bins + 1);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int64_t r = i / (n_bins + 1);
-  const int k = (int)(i - r * (n_bins + 1));
-  const float h = g.half_extent0 * (float)(1 << (g.n_levels - 1));
-  float tn = near_plane, tf = far_plane;
+// Equally spaced edges e_k = lo + (hi - lo) * (k / n_bins) over per-ray
+// intervals.  A block writes whole rows: the endpoints of its rays go to LDS
+// first (thread per ray), then its threads store the block's contiguous run
+// of edges (a fixed divisor maps a position in the run to its row).
+constexpr int kEdgeBlock = 256;
+constexpr int kEdgeWords = 4096;  // edges per block, at least one row
+
+inline int32_t edge_rows(int32_t n_bins) { return std::max(1, kEdgeWords / (n_bins + 1)); }
+
+// chord of the ray through the outermost cube, clipped to [near, far]
+struct ChordEnds {
+  txs_grid g;
+  float near_plane, far_plane;
+  const float* ro;
+  const float* rd;
+  __device__ void operator()(int64_t r, float& lo, float& hi) const {
+    const float h = g.half_extent0 * (float)(1 << (g.n_levels - 1));
+    float tn = near_plane, tf = far_plane;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float inv = 1.0f / rd[3 * r + a];
-    const float o = ro[3 * r + a];
-    const float tlo = ((g.center[a] - h) - o) * inv;
-    const float thi = ((g.center[a] + h) - o) * inv;
-    tn = fmaxf(tn, fminf(tlo, thi));
-    tf = fminf(tf, fmaxf(tlo, thi));
+    for (int a = 0; a < 3; ++a) {
+      const float inv = 1.0f / rd[3 * r + a];
+      const float o = ro[3 * r + a];
+      const float tlo = ((g.center[a] - h) - o) * inv;
+      const float thi = ((g.center[a] + h) - o) * inv;
+      tn = fmaxf(tn, fminf(tlo, thi));
+      tf = fminf(tf, fmaxf(tlo, thi));
+    }
+    if (!(tn < tf)) {
+      tn = near_plane;
+      tf = near_plane;
+    }
+    lo = tn;
+    hi = tf;
   }
-  if (!(tn < tf)) {
-    tn = near_plane;
-    tf = near_plane;
+};
+
+// a given span per ray
+struct SpanEnds {
+  const float* span;
+  __device__ void operator()(int64_t r, float& lo, float& hi) const {
+    lo = span[2 * r];
+    hi = span[2 * r + 1];
   }
-  out[i] = tn + (tf - tn) * ((float)k / (float)n_bins);
+};
+
+template <class Ends>
+__global__ __launch_bounds__(kEdgeBlock) void edges_kernel(Ends ends, int32_t n_rays,
+                                                          int32_t n_bins, int32_t rows,
+                                                          FastDiv per_row,
+                                                          float* __restrict__ out) {
+  __shared__ float s_lo[kEdgeWords / 2], s_hi[kEdgeWords / 2];  // rows <= 2048 (n_bins >= 1)
+  const int64_t r0 = (int64_t)blockIdx.x * rows;
+  const int nr = (int)std::min<int64_t>(rows, (int64_t)n_rays - r0);
+  for (int j = threadIdx.x; j < nr; j += kEdgeBlock) ends(r0 + j, s_lo[j], s_hi[j]);
+  __syncthreads();
+  const int E = n_bins + 1;
+  const int cnt = nr * E;
+  float* o = out + r0 * E;
+  for (int j = threadIdx.x; j < cnt; j += kEdgeBlock) {
+    const int rr = (int)per_row.div((uint32_t)j);
+    const int k = j - rr * E;
+    const float lo = s_lo[rr], hi = s_hi[rr];
+    o[j] = lo + (hi - lo) * ((float)k / (float)n_bins);
+  }
+}
+
+template <class Ends>
+void launch_edges(const Ends& ends, int32_t n_rays, int32_t n_bins, float* out,
+                  hipStream_t stream) {
+  const int32_t rows = edge_rows(n_bins);
+  const int64_t blocks = ((int64_t)n_rays + rows - 1) / rows;
+  hipLaunchKernelGGL(edges_kernel<Ends>, dim3((unsigned)blocks), dim3(kEdgeBlock), 0, stream,
+                     ends, n_rays, n_bins, rows, FastDiv((uint32_t)(n_bins + 1)), out);
 }
 
 // t0[r*n + k] = e[r][k], t1[r*n + k] = e[r][k+1]: thread per output pair
@@ -193,13 +239,22 @@ extern "C" txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, f
   TXS_REQUIRE(grid->n_levels >= 1 && grid->n_levels <= 8, "txs_uniform_bins: bad n_levels");
   TXS_REQUIRE(std::isfinite(grid->half_extent0) && grid->half_extent0 > 0,
               "txs_uniform_bins: bad half_extent0");
-  TXS_REQUIRE(n_rays >= 0 && n_bins >= 1, "txs_uniform_bins: bad size");
+  TXS_REQUIRE(n_rays >= 0 && n_bins >= 1 && n_bins <= (1 << 24), "txs_uniform_bins: bad size");
   TXS_REQUIRE(near_plane >= 0.0f && far_plane > near_plane, "txs_uniform_bins: bad planes");
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && out_edges, "txs_uniform_bins: null array");
-  const int64_t total = (int64_t)n_rays * (n_bins + 1);
-  hipLaunchKernelGGL(uniform_bins_kernel, dim3(grid_1d(total, 256)), dim3(256), 0,
-                     as_stream(stream), *grid, near_plane, far_plane, rays_o, rays_d, n_rays,
-                     n_bins, out_edges);
+  launch_edges(ChordEnds{*grid, near_plane, far_plane, rays_o, rays_d}, n_rays, n_bins,
+               out_edges, as_stream(stream));
   return launch_status("txs_uniform_bins");
+}
+
+extern "C" txs_status txs_span_bins(int32_t n_rays, const float* span, int32_t n_bins,
+                                    float* out_edges, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(n_rays >= 0 && n_bins >= 1 && n_bins <= (1 << 24), "txs_span_bins: bad size");
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(span && out_edges, "txs_span_bins: null array");
+  launch_edges(SpanEnds{span}, n_rays, n_bins, out_edges, as_stream(stream));
+  return launch_status("txs_span_bins");
 }

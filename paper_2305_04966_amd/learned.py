@@ -12,8 +12,13 @@ library:
     -> mlp_pack
 
 Targets come from the plain occupancy-grid renderer (march, filter, field,
-render with weights), computed by `grid_render`.  Only argument plumbing
-lives here.
+render with weights), computed by `grid_render`.
+
+The combined estimator (Section 3.1, "Insights from Unified Formulation";
+Section 5, "Combined Sampling") stacks the occupancy grid on the proposal
+network: `occupied_span` marches the grid for each ray's occupied span and
+compacts the rays that have one, and `combined_render` bins only that span
+for the proposal network.  Only argument plumbing lives here.
 """
 from __future__ import annotations
 
@@ -150,3 +155,64 @@ def proposal_render(est: ProposalEstimator, rays_o, rays_d, edges, n_out, field_
     if keep:
         return t0, t1, sig, rgb, out[4]
     return out[0], out[1], out[2]
+
+
+# ---------------------------------------------------------------- combined
+@dataclass
+class OccupiedSpan:
+    """The occupancy grid's part of the combined estimator: the rays that
+    cross occupied space, compacted in ray order, with their occupied spans."""
+    table: torch.Tensor     # int32 [N, 2]: (slot, hit) per ray
+    n_alive: int
+    rays_o: torch.Tensor    # float32 [M, 3]
+    rays_d: torch.Tensor    # float32 [M, 3]
+    span: torch.Tensor      # float32 [M, 2]
+
+    def bins(self, n_bins):
+        """Uniform proposal bins over every occupied span -> edges [M, n_bins+1]."""
+        return ops.span_bins(self.span, n_bins)
+
+    def compact(self, rows):
+        """Rows of every ray -> rows of the rays that hit."""
+        return ops.compact_rows(self.table, self.n_alive, rows)
+
+    def expand(self, rows, fill=0.0):
+        """Rows of the rays that hit -> rows of every ray (`fill` elsewhere)."""
+        return ops.expand_rows(self.table, rows, fill)
+
+    def target(self, judge: GridRender) -> GridRender:
+        """A grid renderer's output restricted to the rays that hit (its packed
+        rows re-indexed; the samples themselves are shared)."""
+        q = judge.samples
+        info = self.compact(q.packed_info)
+        return GridRender(Packed(info, q.t0, q.t1, None), judge.weights,
+                          self.compact(judge.rgb), self.compact(judge.opacity))
+
+
+def occupied_span(grid: ops.GridSpec, rays_o, rays_d, *, dt0, near=0.0,
+                  far=float("inf")) -> OccupiedSpan:
+    """March the grid for every ray's occupied span, drop the rays without
+    one and compact the rest (one device -> host read: their number)."""
+    span, hit = ops.march_span(grid, rays_o, rays_d, dt0=dt0, near=near, far=far)
+    table, total = ops.exclusive_scan(hit)
+    m = int(total.item())
+    return OccupiedSpan(table, m, ops.compact_rows(table, m, rays_o),
+                        ops.compact_rows(table, m, rays_d), ops.compact_rows(table, m, span))
+
+
+def combined_render(est: ProposalEstimator, sp: OccupiedSpan, n_bins, n_out, field_fn,
+                    keep=False):
+    """Render with the combined estimator: uniform bins over each occupied span
+    -> proposal density -> inverse CDF to n_out intervals -> field -> render.
+    Returns (rgb, opacity, depth) of every ray (zero where a ray found no
+    occupied cell); with keep=True also the compacted (t0, t1, sigma, rgb,
+    optical_depth) for a backward over the rays that hit."""
+    edges = sp.bins(n_bins)
+    t0, t1 = est.sample_intervals(sp.rays_o, sp.rays_d, edges, n_out)
+    sig, rgb = field_fn(sp.rays_o, sp.rays_d, t0, t1, n_out)
+    out = ops.render_fwd(None, t0, t1, sig, rgb, n_rays=sp.n_alive, fixed_count=n_out,
+                         want_optical_depth=keep)
+    full = (sp.expand(out[0]), sp.expand(out[1]), sp.expand(out[2]))
+    if keep:
+        return full, (t0, t1, sig, rgb, out[4])
+    return full

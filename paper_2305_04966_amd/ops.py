@@ -15,7 +15,9 @@ from ._lib import TXS_PDF_SIGMA, TXS_PDF_WEIGHTS, Grid, MarchParams, check, load
 
 __all__ = ["GridSpec", "march_count", "exclusive_scan", "march_fill", "transmittance_prefix",
            "gather_prefix", "render_fwd", "render_bwd", "weights_bwd", "resample",
-           "uniform_bins", "edges_to_intervals", "resample_intervals", "blob_field", "TXS_PDF_SIGMA", "TXS_PDF_WEIGHTS"]
+           "uniform_bins", "edges_to_intervals", "resample_intervals", "blob_field",
+           "march_span", "compact_rows", "expand_rows", "span_bins", "TXS_PDF_SIGMA",
+           "TXS_PDF_WEIGHTS"]
 
 
 def _stream():
@@ -419,3 +421,53 @@ def stream_probe(t0, t1, sigma, rgb, out_a, out_b):
     check(load().txs_stream_probe(n, _ptr(t0), _ptr(t1), _ptr(sigma), _ptr(rgb), _ptr(out_a),
                                   _ptr(out_b), _stream()), "txs_stream_probe")
 
+
+
+def march_span(grid: GridSpec, rays_o, rays_d, *, near=0.0, far=float("inf"), dt0):
+    """Occupied span of every ray -> (span float32 [N, 2], hit int32 [N])."""
+    n = _rays(rays_o, rays_d)
+    dev = rays_o.device
+    span = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    hit = torch.empty(n, dtype=torch.int32, device=dev)
+    g, p = grid.struct(), _params(near, far, dt0, 0)
+    check(load().txs_march_span(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d), n,
+                                _ptr(span), _ptr(hit), _stream()), "txs_march_span")
+    return span, hit
+
+
+def compact_rows(table, n_alive, src):
+    """Rows of src [N, ...] of the rays whose table flag is 1 -> [n_alive, ...]."""
+    n = table.shape[0]
+    _need(table, "table", torch.int32, (n, 2))
+    if src.shape[0] != n or src.element_size() != 4:
+        raise ValueError("compact_rows: src must be [n_rays, ...] of 32-bit words")
+    if not src.is_cuda or not src.is_contiguous():
+        raise ValueError("compact_rows: src must be a contiguous GPU tensor")
+    width = max(1, src[0].numel()) if n else 1
+    dst = torch.empty((n_alive,) + tuple(src.shape[1:]), dtype=src.dtype, device=src.device)
+    check(load().txs_compact_rows(n, _ptr(table), width, _ptr(src), _ptr(dst), _stream()),
+          "txs_compact_rows")
+    return dst
+
+
+def expand_rows(table, src, fill=0.0):
+    """Compacted rows src [n_alive, ...] back to every ray, `fill` where a ray missed."""
+    n = table.shape[0]
+    _need(table, "table", torch.int32, (n, 2))
+    _need(src, "src", torch.float32)
+    width = 1
+    for s in src.shape[1:]:
+        width *= s
+    dst = torch.empty((n,) + tuple(src.shape[1:]), dtype=torch.float32, device=table.device)
+    check(load().txs_expand_rows(n, _ptr(table), width, _ptr(src) if src.numel() else None,
+                                 float(fill), _ptr(dst), _stream()), "txs_expand_rows")
+    return dst
+
+
+def span_bins(span, n_bins):
+    """n_bins+1 equally spaced edges over each span [N, 2] -> [N, n_bins+1]."""
+    n = span.shape[0]
+    _need(span, "span", torch.float32, (n, 2))
+    out = torch.empty((n, n_bins + 1), dtype=torch.float32, device=span.device)
+    check(load().txs_span_bins(n, _ptr(span), n_bins, _ptr(out), _stream()), "txs_span_bins")
+    return out

@@ -636,3 +636,56 @@ def test_grid_ema_closed_forms():
     for _ in range(25):
         d, _ = oracle.grid_ema(d, s, gamma, 0.5)
     np.testing.assert_allclose(d, s + gamma ** 25 * (d0 - s), rtol=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# combined estimator: the grid's occupied span (Section 5, "Combined Sampling")
+# ----------------------------------------------------------------------------
+def test_span_of_one_occupied_cell_is_its_chord_on_the_lattice():
+    # an 8^3 grid with cells (3, 4, 4) and (5, 4, 4) occupied; rays along +x
+    # through row (y, z) = (4, 4) enter cell 3 at x = -0.375 and leave cell 5 at
+    # x = 0.75.  t = x + 3, lattice a = 1.5, dt = 0.011 (no midpoint on a cell
+    # face): the span's ends lie within half a step of the faces.
+    res, dt = 8, 0.011
+    occ = np.zeros(res ** 3, bool)
+    for x in (3, 5):
+        occ[x + res * (4 + res * 4)] = True
+    yz = -1.5 + 0.375 * np.array([4.3, 4.6])
+    o = np.array([[-3.0, yz[0], yz[1]], [-3.0, yz[1], yz[0]], [-3.0, 1.0, 1.0]], np.float32)
+    d = np.tile(np.float32([[1, 0, 0]]), (3, 1))
+    span, hit = oracle.march_span(o, d, scenes.pack_bits(occ), res, dt0=dt)
+    assert hit.tolist() == [1, 1, 0]
+    assert span[2].tolist() == [0.0, 0.0]
+    for r in range(2):
+        assert abs(span[r, 0] - (3.0 - 0.375)) <= 0.5 * dt + 1e-6
+        assert abs(span[r, 1] - (3.0 + 0.75)) <= 0.5 * dt + 1e-6
+        # both ends sit on the lattice a + k dt (the march's own interval ends)
+        k = (span[r, 0] - 1.5) / dt
+        assert abs(k - round(k)) < 1e-3
+
+
+def test_span_of_full_and_empty_grids():
+    res = 8
+    o, d = scenes.sphere_rays(300, radius=20.0, target_half=2.0, seed=43)
+    full = scenes.pack_bits(np.ones(res ** 3, bool))
+    span, hit = oracle.march_span(o, d, full, res, dt0=0.02)
+    tn, tf = oracle.clip(o, d, BMIN, BMAX)
+    inside = tn < tf
+    # only rays through the cube hit; every chord longer than a step holds a midpoint
+    h = hit.astype(bool)
+    assert np.all(h <= inside)
+    assert np.all(h[inside & (tf - tn > 0.02 + 1e-5)])
+    assert h.sum() > 100
+    # full grid: the span starts exactly at the entry, ends within half a step of the exit
+    assert np.array_equal(span[h, 0], tn[h])
+    assert np.all(span[h, 1] <= tf[h]) and np.all(span[h, 1] > tf[h] - 0.01 - 1e-5)
+    span0, hit0 = oracle.march_span(o, d, np.zeros_like(full), res, dt0=0.02)
+    assert not hit0.any() and not span0.any()
+
+
+def test_span_bins_closed_form():
+    span = np.array([[1.0, 3.0], [0.5, 0.5], [2.0, 2.75]], np.float32)
+    e = oracle.span_bins(span, 4)
+    assert e[0].tolist() == [1.0, 1.5, 2.0, 2.5, 3.0]
+    assert e[1].tolist() == [0.5] * 5
+    assert np.allclose(np.diff(e[2]), 0.1875, rtol=0, atol=1e-15)

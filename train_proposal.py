@@ -16,8 +16,14 @@ The unbounded scene (64 blobs and a background shell, 4 nested 128^3 grids,
 4. Time both samplers end to end (fwd + bwd, field stand-in included on both
    sides) at the smallest sample count within the error bar.
 
-`python train_proposal.py` prints one JSON line; --save writes the trained
-parameters (.npy).
+`run_combined` repeats steps 1-4 on the bounded image scene (32 blobs, one
+128^3 grid, 1024x1024 pinhole camera) for the proposal network alone and for
+the combined estimator (Section 5, "Combined Sampling"): the grid first drops
+the rays that cross no occupied cell and narrows every other ray to its
+occupied span, and the proposal network bins only that span.
+
+`python train_proposal.py` prints one JSON line (`--combined` for the second
+experiment); --save writes the trained parameters (.npy).
 """
 from __future__ import annotations
 
@@ -45,6 +51,39 @@ def _timed(torch, fn, reps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+class _Scene:
+    """A workload's rays, grid and field stand-in on the device."""
+
+    def __init__(self, torch, txs, w):
+        import numpy as np_
+        self.w = w
+        self.dev = lambda a: torch.from_numpy(np_.ascontiguousarray(a)).cuda()
+        self.grid = txs.GridSpec(self.dev(w.bits.view(np_.int32)), w.res, w.n_levels,
+                                 (0.0, 0.0, 0.0), w.half_extent0)
+        self.fp = self.dev(w.fld.packed_params().astype(np_.float32))
+        nb = w.fld.n_blobs
+        fp = self.fp
+        self.field = lambda o, d, t0, t1, n: txs.blob_field(fp, nb, o, d, t0, t1,
+                                                             fixed_count=n)
+
+
+def _train(est, steps, lr0, lr1, log_every, log, step_fn):
+    """Cosine-decayed Adam steps; -> (seconds, [(step, mean loss)])."""
+    import torch
+    from paper_2305_04966_amd.learned import cosine_lr
+    losses = []
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for step in range(1, steps + 1):
+        loss = step_fn(cosine_lr(step, steps, lr0, lr1))
+        if step == 1 or step % log_every == 0 or step == steps:
+            lm = float(loss.mean())
+            losses.append((step, lm))
+            log(f"[train] step {step} loss {lm:.6g} {time.perf_counter() - t:.1f} s")
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, losses
 
 
 def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
@@ -142,6 +181,115 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
     return rec, est
 
 
+def run_combined(*, steps=300, hidden=128, bins=128, eval_bins=(64, 128), ray_stride=1,
+                 train_stride=4, sweep=(32, 48, 64, 96, 128, 192, 256), err_bar=1e-3, lr0=1e-2,
+                 lr1=1e-4, log_every=50, time_reps=5, log=print):
+    """Proposal network alone versus the combined estimator on the image scene.
+
+    Both train the same network from the same initialisation with the same
+    recipe on `bins` bins per ray; the proposal alone bins each ray's chord
+    through the grid cube, the combined estimator bins the occupied span of
+    the rays the grid keeps.  Each is then evaluated with every proposal bin
+    count in `eval_bins` and final sample count in `sweep`; for each bin count
+    the fewest final samples within `err_bar` of the grid renderer's colours
+    is timed end to end (fwd + bwd, field stand-in included), and the fastest
+    such configuration is each estimator's result."""
+    import torch
+
+    import paper_2305_04966_amd as txs
+    import scenes
+    from paper_2305_04966_amd.learned import (ProposalEstimator, combined_render, grid_render,
+                                              occupied_span, proposal_render)
+
+    txs.load()
+    sc = _Scene(torch, txs, scenes.image())
+    w, dev, grid = sc.w, sc.dev, sc.grid
+    ev = np.arange(0, w.n_rays, ray_stride)
+    tr = np.arange(0, w.n_rays, train_stride)
+    o, d = dev(w.rays_o[ev]), dev(w.rays_d[ev])
+    ot, dt = dev(w.rays_o[tr]), dev(w.rays_d[tr])
+    N = len(ev)
+    rec = {"workload": f"image: 32 blobs, 128^3 grid over [-1.5,1.5]^3, 1024x1024 pinhole; "
+                       f"{N} evaluation rays, {len(tr)} training rays",
+           "hidden": hidden, "train_bins": bins, "train_steps": steps, "err_bar": err_bar}
+
+    judge = grid_render(grid, o, d, sc.fp, w.fld.n_blobs, dt0=w.dt0, t_min=w.t_min)
+    target = judge if train_stride == ray_stride else grid_render(
+        grid, ot, dt, sc.fp, w.fld.n_blobs, dt0=w.dt0, t_min=w.t_min)
+    g_rgb = dev(w.grads[ev])
+    sp = occupied_span(grid, o, d, dt0=w.dt0)
+    chord = txs.uniform_bins(grid, o, d, bins)
+    chord_len = (chord[:, -1] - chord[:, 0]).double().sum()
+    span_len = (sp.span[:, 1] - sp.span[:, 0]).double().sum()
+    rec["rays_hit"] = sp.n_alive
+    rec["span_over_chord"] = float(span_len / chord_len)
+
+    # training: the proposal alone on chord bins, the combined estimator on span bins
+    chord_t = chord if train_stride == ray_stride else txs.uniform_bins(grid, ot, dt, bins)
+    est_p = ProposalEstimator(dev(scenes.mlp_init(hidden)), hidden, scale=1.5)
+    a_t, b_t = est_p.dense_intervals(chord_t)
+    secs_p, loss_p = _train(est_p, steps, lr0, lr1, log_every, log,
+                            lambda lr: est_p.train_step(ot, dt, chord_t, target, lr, a_t, b_t))
+    sp_t = sp if train_stride == ray_stride else occupied_span(grid, ot, dt, dt0=w.dt0)
+    span_t = sp_t.bins(bins)
+    tgt_c = sp_t.target(target)
+    est_c = ProposalEstimator(dev(scenes.mlp_init(hidden)), hidden, scale=1.5)
+    c_t0, c_t1 = est_c.dense_intervals(span_t)
+    secs_c, loss_c = _train(est_c, steps, lr0, lr1, log_every, log,
+                            lambda lr: est_c.train_step(sp_t.rays_o, sp_t.rays_d, span_t, tgt_c,
+                                                        lr, c_t0, c_t1))
+
+    def render_p(nb, n):
+        return proposal_render(est_p, o, d, txs.uniform_bins(grid, o, d, nb), n, sc.field)[0]
+
+    def render_c(nb, n):
+        return combined_render(est_c, sp, nb, n, sc.field)[0]
+
+    def step_p(nb, n):
+        e0 = txs.uniform_bins(grid, o, d, nb)
+        a, b, sg, rgb, od = proposal_render(est_p, o, d, e0, n, sc.field, keep=True)
+        txs.render_bwd(None, a, b, sg, rgb, g_rgb, n_rays=N, fixed_count=n, optical_depth=od)
+
+    def step_c(nb, n):
+        s = occupied_span(grid, o, d, dt0=w.dt0)
+        _, (a, b, sg, rgb, od) = combined_render(est_c, s, nb, n, sc.field, keep=True)
+        txs.render_bwd(None, a, b, sg, rgb, s.compact(g_rgb), n_rays=s.n_alive, fixed_count=n,
+                       optical_depth=od)
+
+    for name, render, step, secs, losses in (("proposal", render_p, step_p, secs_p, loss_p),
+                                             ("combined", render_c, step_c, secs_c, loss_c)):
+        err = {nb: {n: float((render(nb, n) - judge.rgb).abs().mean()) for n in sweep}
+               for nb in eval_bins}
+        log(f"[eval] {name} {err}")
+        timed = {}
+        for nb in eval_bins:
+            ok = [n for n in sweep if err[nb][n] <= err_bar]
+            if ok:
+                timed[(nb, min(ok))] = _timed(torch, lambda: step(nb, min(ok)), time_reps)
+        best = min(timed, key=timed.get) if timed else None
+        rec[name] = {"err": {str(nb): {str(n): e for n, e in err[nb].items()} for nb in err},
+                     "timed_ms": {f"{nb}x{n}": ms for (nb, n), ms in timed.items()},
+                     "bins": best[0] if best else None, "n_final": best[1] if best else None,
+                     "ms": timed[best] if best else None,
+                     "rays_per_s": N / (timed[best] * 1e-3) if best else None,
+                     "final_loss": losses[-1][1] if losses else None,
+                     "ms_per_train_step": 1000.0 * secs / max(steps, 1)}
+
+    def grid_step():
+        p = txs.march(grid, o, d, dt0=w.dt0)
+        sg, _ = txs.blob_field(sc.fp, w.fld.n_blobs, o, d, p.t0, p.t1, p.ray_id, want_rgb=False)
+        q = txs.filter_transmittance(p, sg, w.t_min)
+        sg, rgb = txs.blob_field(sc.fp, w.fld.n_blobs, o, d, q.t0, q.t1, q.ray_id)
+        out = txs.render_fwd(q.packed_info, q.t0, q.t1, sg, rgb, want_optical_depth=True)
+        txs.render_bwd(q.packed_info, q.t0, q.t1, sg, rgb, g_rgb, optical_depth=out[4])
+
+    rec["grid_ms"] = _timed(torch, grid_step, time_reps)
+    rec["grid_rays_per_s"] = N / (rec["grid_ms"] * 1e-3)
+    if rec["proposal"]["ms"] and rec["combined"]["ms"]:
+        rec["combined_over_proposal"] = rec["proposal"]["ms"] / rec["combined"]["ms"]
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=1000)
@@ -156,7 +304,17 @@ def main():
     ap.add_argument("--log-every", type=int, default=50)
     ap.add_argument("--time-reps", type=int, default=5)
     ap.add_argument("--save", default="")
+    ap.add_argument("--combined", action="store_true",
+                    help="proposal alone vs combined grid + proposal on the image scene")
     args = ap.parse_args()
+    if args.combined:
+        rec = run_combined(steps=args.steps, hidden=args.hidden, bins=args.bins,
+                           ray_stride=args.ray_stride, train_stride=args.train_stride,
+                           sweep=[int(s) for s in args.sweep.split(",")], err_bar=args.err_bar,
+                           lr0=args.lr0, lr1=args.lr1, log_every=args.log_every,
+                           time_reps=args.time_reps, log=lambda s: print(s, flush=True))
+        print(json.dumps(rec), flush=True)
+        return
     rec, est = run(steps=args.steps, hidden=args.hidden, bins=args.bins,
                    ray_stride=args.ray_stride, train_stride=args.train_stride,
                    sweep=[int(s) for s in args.sweep.split(",")], err_bar=args.err_bar,
