@@ -50,12 +50,18 @@ def parse():
                     help="train the proposal network this many steps on the unbounded scene and "
                          "report learned vs grid sampling (0 = skip)")
     ap.add_argument("--learned-train-stride", type=int, default=4)
-    ap.add_argument("--learned-sweep", default="128,160,192,224,256")
+    ap.add_argument("--learned-sweep", default="32,40,48,64,96,128")
+    ap.add_argument("--learned-spacing", default="disparity", choices=["linear", "disparity"],
+                    help="proposal bins equal in t, or equal in 1/t from --learned-near")
+    ap.add_argument("--learned-near", type=float, default=0.5)
     ap.add_argument("--combined-steps", type=int, default=300,
                     help="train the proposal network alone and inside the grid's occupied "
                          "spans this many steps each on the image scene and report both "
                          "(0 = skip)")
     ap.add_argument("--combined-sweep", default="32,48,64,96,128,192,256")
+    ap.add_argument("--pdf", type=int, default=1,
+                    help="run the coarse-to-fine PDF estimator on the image scene and report "
+                         "it (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run a plain device copy of this many MiB (counter "
                          "calibration for profiler byte counts)")
@@ -207,15 +213,18 @@ def gpu_bench(args, w):
 
 def learned_vs_grid(args):
     """The learned estimator against the occupancy grid on the unbounded scene:
-    train the proposal network (untimed), then time both samplers end to end
-    (fwd + bwd, the field stand-in on both sides) on all 2^20 rays, the learned
-    one at the fewest final samples within 1e-3 mean rgb error of the grid."""
+    train the proposal network (untimed) on bins spaced equally in disparity
+    from t = 0.5 (below the closest content, ~1 from every camera), then time
+    both samplers end to end (fwd + bwd, the field stand-in on both sides) on
+    all 2^20 rays, the learned one at the fewest final samples within 1e-3
+    mean rgb error of the grid."""
     from train_proposal import run
     rec, _ = run(steps=args.learned_steps, train_stride=args.learned_train_stride,
                  sweep=[int(s) for s in args.learned_sweep.split(",")], untrained=False,
+                 spacing=args.learned_spacing, near=args.learned_near,
                  log_every=max(args.learned_steps, 1), time_reps=3,
                  log=lambda s: print(s, file=sys.stderr, flush=True))
-    keep = ("workload", "hidden", "bins", "train_steps", "ms_per_train_step", "err_bar",
+    keep = ("workload", "hidden", "bins", "spacing", "train_steps", "ms_per_train_step", "err_bar",
             "n_final", "within_err_bar", "trained_err", "grid_samples", "grid_ms",
             "learned_ms", "grid_rays_per_s", "learned_rays_per_s", "learned_over_grid")
     out = {k: rec[k] for k in keep}
@@ -235,6 +244,15 @@ def combined_vs_proposal(args):
                        log_every=max(args.combined_steps, 1), time_reps=3,
                        log=lambda s: print(s, file=sys.stderr, flush=True))
     return rec
+
+
+def pdf_estimator(args):
+    """The coarse-to-fine PDF estimator (the field's density on coarse uniform
+    bins, inverse CDF, the field on coarse and fine edges together) on the
+    image scene, timed end to end on all 2^20 rays at its fastest
+    configuration within 1e-3 mean rgb error of the grid renderer."""
+    from train_proposal import run_pdf
+    return run_pdf(time_reps=3, log=lambda s: print(s, file=sys.stderr, flush=True))
 
 
 def measured_traffic(kernel):
@@ -344,6 +362,8 @@ def main():
         rec["learned_vs_grid"] = learned_vs_grid(args)
     if args.combined_steps > 0:
         rec["combined_vs_proposal"] = combined_vs_proposal(args)
+    if args.pdf:
+        rec["pdf_estimator"] = pdf_estimator(args)
     if rank == 0 and args.cpu_sample > 0:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     if rank == 0:

@@ -206,8 +206,14 @@ txs_status txs_weights_bwd(const int32_t* packed_info, int32_t fixed_count, int3
  *   mode TXS_PDF_WEIGHTS: F_{i+1} = sum_{j<=i} vals_j
  * Per ray: u' = u * F_n, i = the largest i in [0, n_bins] with F_i <= u',
  * t = e_i + (u' - F_i) / (F_{i+1} - F_i) * (e_{i+1} - e_i)  (t = e_n if
- * i = n_bins).  A ray whose F_n <= 1e-12 uses the uniform estimator
- * (F_i = i/n_bins, Table 1, first row).  u is float [n_rays, n_out+1] with
+ * i = n_bins): the transmittance is taken linear inside a bin (Table 1).
+ *   mode TXS_PDF_SIGMA_EXP: the CDF of TXS_PDF_SIGMA inverted exactly for a
+ *   density constant inside each bin (T exponential there): with
+ *   x = (u' - F_i) / (F_{i+1} - F_i) * (1 - exp(-tau_i)), tau_i = vals_i
+ *   (e_{i+1} - e_i), t = min(e_i + (e_{i+1} - e_i) * (-log(1 - x) / tau_i),
+ *   e_{i+1}).
+ * A ray whose F_n <= 1e-12 uses the uniform estimator (F_i = i/n_bins,
+ * Table 1, first row; linear in every mode).  u is float [n_rays, n_out+1] with
  * values in [0,1], non-decreasing per ray, or NULL for u_k = k/n_out.
  * edges float [n_rays, n_bins+1] (non-decreasing), vals float
  * [n_rays, n_bins] (>= 0); out_edges float [n_rays, n_out+1] are the
@@ -215,6 +221,7 @@ txs_status txs_weights_bwd(const int32_t* packed_info, int32_t fixed_count, int3
  */
 #define TXS_PDF_SIGMA 0
 #define TXS_PDF_WEIGHTS 1
+#define TXS_PDF_SIGMA_EXP 2
 txs_status txs_resample(int32_t n_rays, int32_t n_bins, const float* edges, const float* vals,
                         int32_t mode, int32_t n_out, const float* u, float* out_edges,
                         void* stream);
@@ -241,6 +248,19 @@ txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, float far_pl
                             int32_t n_bins, float* out_edges, void* stream);
 
 /*
+ * Uniform estimator in disparity: the chord of txs_uniform_bins (same clip,
+ * same handling of rays that miss) split into n_bins bins of equal width in
+ * 1/t, e_k = 1 / (1/t_near + (1/t_far - 1/t_near) * (k / n_bins)) in
+ * binary32, with e_0 = t_near and e_n = t_far exactly: finer near the ray's
+ * origin, coarser far away (the spacing Mip-NeRF 360 gives the proposal
+ * network's first samples on unbounded scenes, Section 3.2 of the paper
+ * cites it).  near_plane must be > 0 (1/t stays finite).
+ */
+txs_status txs_disparity_bins(const txs_grid* grid, float near_plane, float far_plane,
+                              const float* rays_o, const float* rays_d, int32_t n_rays,
+                              int32_t n_bins, float* out_edges, void* stream);
+
+/*
  * Dense interval layout of per-ray edges (the input layout of the renderer
  * and the field for a fixed number of samples per ray): for edges float
  * [n_rays, n+1], writes t0[r*n + k] = e_k and t1[r*n + k] = e_{k+1}
@@ -248,6 +268,18 @@ txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, float far_pl
  */
 txs_status txs_edges_to_intervals(const float* edges, int32_t n_rays, int32_t n, float* t0,
                                   float* t1, void* stream);
+
+/*
+ * Sorted union of two ascending edge rows per ray (the coarse-to-fine PDF
+ * estimator of Table 1's third row, as vanilla NeRF runs it, renders its fine
+ * pass on the coarse edges and the inverse-CDF edges together):
+ * a float [n_rays, na], b float [n_rays, nb], out float [n_rays, na+nb], the
+ * values of both rows in ascending order (stable: a before equal b).  Rows
+ * must be ascending (not checked; an unsorted row leaves unspecified values in
+ * its own output row and writes nothing outside it).  1 <= na, nb <= 4096.
+ */
+txs_status txs_merge_edges(int32_t n_rays, int32_t na, const float* a, int32_t nb, const float* b,
+                           float* out, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Learned transmittance estimator: the proposal network (Section 3.1 "PDF

@@ -195,7 +195,7 @@ def exclusive_scan(counts):
     return info, int(counts.sum())
 
 
-MODE_SIGMA, MODE_WEIGHTS = 0, 1
+MODE_SIGMA, MODE_WEIGHTS, MODE_SIGMA_EXP = 0, 1, 2
 
 
 def resample(edges, vals, n_out, mode=MODE_SIGMA, u=None):
@@ -337,3 +337,20 @@ def span_bins(span, n_bins):
     s = _f64(span)
     k = np.arange(n_bins + 1, dtype=np.float64) / n_bins
     return s[:, :1] + (s[:, 1:2] - s[:, :1]) * k
+
+
+def merge_edges(a, b):
+    """Sorted union of two edge rows per ray (the fine pass of the coarse-to-fine
+    PDF estimator renders coarse and fine edges together) -> [N, na+nb]."""
+    return np.sort(np.concatenate([_f32(a), _f32(b)], axis=1), axis=1, kind="stable")
+
+
+def disparity_bins(o, d, bmin, bmax, n_bins, near, far=float("inf")):
+    """Chord bins of equal width in 1/t (binary64 from the binary32 clip);
+    a ray that misses gets all edges at `near` -> [N, n_bins+1]."""
+    tn, tf = clip(o, d, bmin, bmax, near, far)
+    hit = tn < tf
+    lo = np.where(hit, tn, near).astype(np.float64)
+    hi = np.where(hit, tf, near).astype(np.float64)
+    k = np.arange(n_bins + 1, dtype=np.float64) / n_bins
+    return 1.0 / (1.0 / lo[:, None] + (1.0 / hi[:, None] - 1.0 / lo[:, None]) * k)

@@ -337,10 +337,15 @@ EXPORT void oracle_transmittance_prefix(int32_t n_rays, const int32_t* packed_in
  * Within a bin the estimator's T is linear (Table 1), so the inverse is linear:
  *   u' = u F_n;  i = largest i in [0, n] with F_i <= u'
  *   t  = e_i + (u' - F_i)/(F_{i+1} - F_i) (e_{i+1} - e_i)   if i < n, else t = e_n
+ * mode 2 (density, exponential in the bin): the CDF of mode 0, inverted
+ * exactly for a density that is constant inside each bin (T decays
+ * exponentially there): with P_i = sum_{j<i} sigma_j (e_{j+1}-e_j),
+ *   t = e_i + (-log(1 - u') - P_i) / sigma_i, kept inside [e_i, e_{i+1}].
  * When F_n <= 1e-12 the uniform estimator (Table 1, first row) is used
- * instead (F_i = i/n).  u defaults to k/n_out, k = 0..n_out, giving n_out+1
- * edges, i.e. n_out contiguous intervals.  out_bin records the chosen bin;
- * band flags an edge whose u' lies within relative 1e-5 of a CDF knot.     */
+ * instead (F_i = i/n, linear in every mode).  u defaults to k/n_out,
+ * k = 0..n_out, giving n_out+1 edges, i.e. n_out contiguous intervals.
+ * out_bin records the chosen bin; band flags an edge whose u' lies within
+ * relative 1e-5 of a CDF knot.                                              */
 EXPORT void oracle_resample(int32_t n_rays, int32_t n_bins, const float* edges, const float* vals,
                             int32_t mode, int32_t n_out, const float* u_in, double* out_edges,
                             int32_t* out_bin, int32_t* band) {
@@ -348,19 +353,23 @@ EXPORT void oracle_resample(int32_t n_rays, int32_t n_bins, const float* edges, 
   for (int32_t r = 0; r < n_rays; ++r) {
     const float* e = edges + (int64_t)r * (n_bins + 1);
     const float* v = vals + (int64_t)r * n_bins;
-    double* F = (double*)malloc((size_t)(n_bins + 1) * sizeof(double));
+    double* F = (double*)malloc((size_t)(2 * (n_bins + 1)) * sizeof(double));
+    double* P = F + n_bins + 1; /* optical depth before each edge (modes 0 and 2) */
     F[0] = 0.0;
+    P[0] = 0.0;
     double acc = 0.0;
     for (int i = 0; i < n_bins; ++i) {
-      if (mode == 0) {
+      if (mode == 0 || mode == 2) {
         acc += (double)v[i] * ((double)e[i + 1] - (double)e[i]);
         F[i + 1] = -expm1(-acc);
+        P[i + 1] = acc;
       } else {
         acc += (double)v[i];
         F[i + 1] = acc;
       }
     }
-    if (!(F[n_bins] > 1e-12))
+    const int uniform = !(F[n_bins] > 1e-12);
+    if (uniform)
       for (int i = 0; i <= n_bins; ++i) F[i] = (double)i / n_bins;
     const double Fn = F[n_bins];
     int b = 0;
@@ -373,10 +382,17 @@ EXPORT void oracle_resample(int32_t n_rays, int32_t n_bins, const float* edges, 
       for (int j = 1; j < n_bins; ++j)
         if (fabs(up - F[j]) <= 1e-5 * Fn) b = 1;
       double t;
-      if (i == n_bins)
+      if (i == n_bins) {
         t = (double)e[n_bins];
-      else /* F_i <= u' < F_{i+1} */
+      } else if (mode == 2 && !uniform) {
+        /* density constant in the bin: T(t) = exp(-P_i - sigma_i (t - e_i));
+           solve 1 - T(t) = u' exactly, kept inside the bin against rounding */
+        t = (double)e[i] + (-log1p(-up) - P[i]) / (double)v[i];
+        if (t < (double)e[i]) t = (double)e[i];
+        if (t > (double)e[i + 1]) t = (double)e[i + 1];
+      } else { /* F_i <= u' < F_{i+1}: linear in the bin */
         t = (double)e[i] + (up - F[i]) / (F[i + 1] - F[i]) * ((double)e[i + 1] - (double)e[i]);
+      }
       out_edges[(int64_t)r * (n_out + 1) + k] = t;
       if (out_bin) out_bin[(int64_t)r * (n_out + 1) + k] = i;
     }

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtxs.so")
 
 TXS_OK, TXS_EINVAL, TXS_ECAPACITY, TXS_EHIP, TXS_EOVERFLOW = 0, -1, -2, -3, -4
-TXS_PDF_SIGMA, TXS_PDF_WEIGHTS = 0, 1
+TXS_PDF_SIGMA, TXS_PDF_WEIGHTS, TXS_PDF_SIGMA_EXP = 0, 1, 2
 
 _STATUS = {TXS_EINVAL: "EINVAL", TXS_ECAPACITY: "ECAPACITY", TXS_EHIP: "EHIP",
            TXS_EOVERFLOW: "EOVERFLOW"}
@@ -71,6 +71,8 @@ SIGNATURES = {
     "txs_compact_rows": (I32, [I32, P, I32, P, P, P]),
     "txs_expand_rows": (I32, [I32, P, I32, P, F32, P, P]),
     "txs_span_bins": (I32, [I32, P, I32, P, P]),
+    "txs_merge_edges": (I32, [I32, I32, P, I32, P, P, P]),
+    "txs_disparity_bins": (I32, [GP, F32, F32, P, P, I32, I32, P, P]),
 }
 
 _lock = threading.Lock()

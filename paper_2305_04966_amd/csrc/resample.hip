@@ -39,9 +39,9 @@ __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(
     for (int base = 0; base < n_bins; base += kWave) {
       const int i = base + ln;
       float m = 0.0f;
-      if (i < n_bins) m = (mode == TXS_PDF_SIGMA) ? vr[i] * (e[i + 1] - e[i]) : vr[i];
+      if (i < n_bins) m = (mode != TXS_PDF_WEIGHTS) ? vr[i] * (e[i + 1] - e[i]) : vr[i];
       const float incl = add_scan_incl(m) + carry;
-      if (i < n_bins) F[i + 1] = (mode == TXS_PDF_SIGMA) ? -expm1f(-incl) : incl;
+      if (i < n_bins) F[i + 1] = (mode != TXS_PDF_WEIGHTS) ? -expm1f(-incl) : incl;
       carry = readlane(incl, kWave - 1);
     }
     wave_sync();
@@ -68,7 +68,17 @@ __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(
       } else {
         const float f0 = F[lo], f1 = F[lo + 1];
         const float frac = (up - f0) / (f1 - f0);
-        t = e[lo] + frac * (e[lo + 1] - e[lo]);
+        const float width = e[lo + 1] - e[lo];
+        if (mode == TXS_PDF_SIGMA_EXP && !uniform) {
+          // constant density in the bin: the share x of the transmittance at
+          // the bin's start used up by u' is frac (1 - exp(-tau)); then
+          // t - e = -log(1 - x) / sigma, and t stays inside the bin
+          const float tau = vr[lo] * width;
+          const float x = frac * -expm1f(-tau);
+          t = fminf(e[lo] + width * (-log1pf(-x) / tau), e[lo + 1]);
+        } else {
+          t = e[lo] + frac * width;
+        }
       }
       if (out) {
         out[r * (n_out + 1) + k] = t;
@@ -132,7 +142,12 @@ struct SpanEnds {
   }
 };
 
-template <class Ends>
+// Spacing of the edges between a ray's endpoints: equal steps in t, or equal
+// steps in disparity 1/t (e_k = 1 / (1/lo + (1/hi - 1/lo) k/n), lo > 0; the
+// end edges are lo and hi themselves).
+enum Spacing : int { kLinearT = 0, kDisparity = 1 };
+
+template <int kSpacing, class Ends>
 __global__ __launch_bounds__(kEdgeBlock) void edges_kernel(Ends ends, int32_t n_rays,
                                                           int32_t n_bins, int32_t rows,
                                                           FastDiv per_row,
@@ -149,17 +164,22 @@ __global__ __launch_bounds__(kEdgeBlock) void edges_kernel(Ends ends, int32_t n_
     const int rr = (int)per_row.div((uint32_t)j);
     const int k = j - rr * E;
     const float lo = s_lo[rr], hi = s_hi[rr];
-    o[j] = lo + (hi - lo) * ((float)k / (float)n_bins);
+    if (kSpacing == kLinearT) {
+      o[j] = lo + (hi - lo) * ((float)k / (float)n_bins);
+    } else {
+      const float a = 1.0f / lo, b = 1.0f / hi;
+      o[j] = k == 0 ? lo : (k == n_bins ? hi : 1.0f / (a + (b - a) * ((float)k / (float)n_bins)));
+    }
   }
 }
 
-template <class Ends>
+template <int kSpacing = kLinearT, class Ends>
 void launch_edges(const Ends& ends, int32_t n_rays, int32_t n_bins, float* out,
                   hipStream_t stream) {
   const int32_t rows = edge_rows(n_bins);
   const int64_t blocks = ((int64_t)n_rays + rows - 1) / rows;
-  hipLaunchKernelGGL(edges_kernel<Ends>, dim3((unsigned)blocks), dim3(kEdgeBlock), 0, stream,
-                     ends, n_rays, n_bins, rows, FastDiv((uint32_t)(n_bins + 1)), out);
+  hipLaunchKernelGGL((edges_kernel<kSpacing, Ends>), dim3((unsigned)blocks), dim3(kEdgeBlock), 0,
+                     stream, ends, n_rays, n_bins, rows, FastDiv((uint32_t)(n_bins + 1)), out);
 }
 
 // t0[r*n + k] = e[r][k], t1[r*n + k] = e[r][k+1]: thread per output pair
@@ -173,6 +193,58 @@ __global__ __launch_bounds__(256) void intervals_kernel(const float* __restrict_
   const float* e = edges + i + r;  // row r starts at r*(n+1) = i - k + r
   t0[i] = e[0];
   t1[i] = e[1];
+}
+
+// Sorted union of two sorted edge rows per ray, a [na] and b [nb] ->
+// out [na+nb] (the fine pass of the coarse-to-fine PDF estimator renders the
+// coarse and the fine edges together).  Output rank of a_i = i + #{b < a_i},
+// of b_j = j + #{a <= b_j}: a stable merge, a first among equal values.  A
+// block stages whole rows of a and b in LDS; each thread places elements by
+// a binary search in the other row.
+constexpr int kMergeWords = 4096;  // LDS words per block, at least one row
+constexpr int kMaxMergeRow = 4096;
+
+inline int32_t merge_rows(int32_t na, int32_t nb) {
+  return std::max(1, kMergeWords / (na + nb));
+}
+
+__device__ __forceinline__ int count_below(const float* row, int n, float v, bool or_equal) {
+  int lo = 0, hi = n;  // first index whose value is >= v (> v with or_equal)
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const bool before = or_equal ? (row[mid] <= v) : (row[mid] < v);
+    if (before) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void merge_kernel(int32_t n_rays, int32_t na, int32_t nb,
+                                                    int32_t rows, FastDiv div_a, FastDiv div_b,
+                                                    const float* __restrict__ a,
+                                                    const float* __restrict__ b,
+                                                    float* __restrict__ out) {
+  extern __shared__ float s_rows[];
+  const int64_t r0 = (int64_t)blockIdx.x * rows;
+  const int nr = (int)std::min<int64_t>(rows, (int64_t)n_rays - r0);
+  float* sa = s_rows;
+  float* sb = s_rows + (size_t)rows * na;
+  for (int j = threadIdx.x; j < nr * na; j += blockDim.x) sa[j] = a[r0 * na + j];
+  for (int j = threadIdx.x; j < nr * nb; j += blockDim.x) sb[j] = b[r0 * nb + j];
+  __syncthreads();
+  const int W = na + nb;
+  float* o = out + r0 * W;
+  for (int j = threadIdx.x; j < nr * na; j += blockDim.x) {
+    const int rr = (int)div_a.div((uint32_t)j);
+    const int i = j - rr * na;
+    const float v = sa[j];
+    o[rr * W + i + count_below(sb + rr * nb, nb, v, false)] = v;
+  }
+  for (int j = threadIdx.x; j < nr * nb; j += blockDim.x) {
+    const int rr = (int)div_b.div((uint32_t)j);
+    const int i = j - rr * nb;
+    const float v = sb[j];
+    o[rr * W + i + count_below(sa + rr * na, na, v, true)] = v;
+  }
 }
 
 }  // namespace
@@ -200,7 +272,8 @@ extern "C" txs_status txs_resample(int32_t n_rays, int32_t n_bins, const float* 
   TXS_REQUIRE(n_bins >= 1 && n_bins <= kMaxBins, "txs_resample: n_bins must be in [1,%d]",
               kMaxBins);
   TXS_REQUIRE(n_out >= 1, "txs_resample: n_out must be >= 1");
-  TXS_REQUIRE(mode == TXS_PDF_SIGMA || mode == TXS_PDF_WEIGHTS, "txs_resample: bad mode %d",
+  TXS_REQUIRE(mode == TXS_PDF_SIGMA || mode == TXS_PDF_WEIGHTS || mode == TXS_PDF_SIGMA_EXP,
+              "txs_resample: bad mode %d",
               mode);
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(edges && vals && out_edges, "txs_resample: null array");
@@ -220,7 +293,7 @@ extern "C" txs_status txs_resample_intervals(int32_t n_rays, int32_t n_bins, con
   TXS_REQUIRE(n_bins >= 1 && n_bins <= kMaxBins,
               "txs_resample_intervals: n_bins must be in [1,%d]", kMaxBins);
   TXS_REQUIRE(n_out >= 1, "txs_resample_intervals: n_out must be >= 1");
-  TXS_REQUIRE(mode == TXS_PDF_SIGMA || mode == TXS_PDF_WEIGHTS,
+  TXS_REQUIRE(mode == TXS_PDF_SIGMA || mode == TXS_PDF_WEIGHTS || mode == TXS_PDF_SIGMA_EXP,
               "txs_resample_intervals: bad mode %d", mode);
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(edges && vals && out_t0 && out_t1, "txs_resample_intervals: null array");
@@ -248,6 +321,26 @@ extern "C" txs_status txs_uniform_bins(const txs_grid* grid, float near_plane, f
   return launch_status("txs_uniform_bins");
 }
 
+extern "C" txs_status txs_disparity_bins(const txs_grid* grid, float near_plane,
+                                         float far_plane, const float* rays_o,
+                                         const float* rays_d, int32_t n_rays, int32_t n_bins,
+                                         float* out_edges, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(grid, "txs_disparity_bins: null grid");
+  TXS_REQUIRE(grid->n_levels >= 1 && grid->n_levels <= 8, "txs_disparity_bins: bad n_levels");
+  TXS_REQUIRE(std::isfinite(grid->half_extent0) && grid->half_extent0 > 0,
+              "txs_disparity_bins: bad half_extent0");
+  TXS_REQUIRE(n_rays >= 0 && n_bins >= 1 && n_bins <= (1 << 24), "txs_disparity_bins: bad size");
+  TXS_REQUIRE(near_plane > 0.0f && far_plane > near_plane,
+              "txs_disparity_bins: near_plane must be > 0 and below far_plane");
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(rays_o && rays_d && out_edges, "txs_disparity_bins: null array");
+  launch_edges<kDisparity>(ChordEnds{*grid, near_plane, far_plane, rays_o, rays_d}, n_rays,
+                           n_bins, out_edges, as_stream(stream));
+  return launch_status("txs_disparity_bins");
+}
+
 extern "C" txs_status txs_span_bins(int32_t n_rays, const float* span, int32_t n_bins,
                                     float* out_edges, void* stream) {
   using namespace txs;
@@ -257,4 +350,20 @@ extern "C" txs_status txs_span_bins(int32_t n_rays, const float* span, int32_t n
   TXS_REQUIRE(span && out_edges, "txs_span_bins: null array");
   launch_edges(SpanEnds{span}, n_rays, n_bins, out_edges, as_stream(stream));
   return launch_status("txs_span_bins");
+}
+
+extern "C" txs_status txs_merge_edges(int32_t n_rays, int32_t na, const float* a, int32_t nb,
+                                      const float* b, float* out, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(n_rays >= 0 && na >= 1 && nb >= 1 && na <= kMaxMergeRow && nb <= kMaxMergeRow,
+              "txs_merge_edges: row lengths must be in [1,%d]", kMaxMergeRow);
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(a && b && out, "txs_merge_edges: null array");
+  const int32_t rows = merge_rows(na, nb);
+  const int64_t blocks = ((int64_t)n_rays + rows - 1) / rows;
+  hipLaunchKernelGGL(merge_kernel, dim3((unsigned)blocks), dim3(256),
+                     (size_t)rows * (na + nb) * sizeof(float), as_stream(stream), n_rays, na, nb,
+                     rows, FastDiv((uint32_t)na), FastDiv((uint32_t)nb), a, b, out);
+  return launch_status("txs_merge_edges");
 }

@@ -157,6 +157,27 @@ def proposal_render(est: ProposalEstimator, rays_o, rays_d, edges, n_out, field_
     return out[0], out[1], out[2]
 
 
+# ---------------------------------------------------------------- two rounds
+def two_round_intervals(est1: ProposalEstimator, est2: ProposalEstimator, rays_o, rays_d, edges,
+                        n_mid, n_out):
+    """Two proposal rounds (as Mip-NeRF 360 stacks them): est1 on `edges` ->
+    inverse CDF to n_mid intervals -> est2 on those -> inverse CDF to n_out
+    dense intervals (t0, t1)."""
+    e1 = est1.sample(rays_o, rays_d, edges, n_mid)
+    return est2.sample_intervals(rays_o, rays_d, e1, n_out)
+
+
+def train_two_rounds(est1: ProposalEstimator, est2: ProposalEstimator, rays_o, rays_d, edges,
+                     target: GridRender, lr, n_mid, t0=None, t1=None):
+    """One update of both rounds against the same target weights: est1 on the
+    fixed `edges`, then est2 on the n_mid intervals est1 now draws (no
+    gradient flows through the resampling).  Returns both losses."""
+    l1 = est1.train_step(rays_o, rays_d, edges, target, lr, t0, t1)
+    e1 = est1.sample(rays_o, rays_d, edges, n_mid)
+    l2 = est2.train_step(rays_o, rays_d, e1, target, lr)
+    return l1, l2
+
+
 # ---------------------------------------------------------------- combined
 @dataclass
 class OccupiedSpan:

@@ -11,13 +11,14 @@ from dataclasses import dataclass
 
 import torch
 
-from ._lib import TXS_PDF_SIGMA, TXS_PDF_WEIGHTS, Grid, MarchParams, check, load
+from ._lib import TXS_PDF_SIGMA, TXS_PDF_SIGMA_EXP, TXS_PDF_WEIGHTS, Grid, MarchParams, check, load
 
 __all__ = ["GridSpec", "march_count", "exclusive_scan", "march_fill", "transmittance_prefix",
            "gather_prefix", "render_fwd", "render_bwd", "weights_bwd", "resample",
            "uniform_bins", "edges_to_intervals", "resample_intervals", "blob_field",
-           "march_span", "compact_rows", "expand_rows", "span_bins", "TXS_PDF_SIGMA",
-           "TXS_PDF_WEIGHTS"]
+           "march_span", "compact_rows", "expand_rows", "span_bins", "merge_edges", "disparity_bins",
+           "TXS_PDF_SIGMA",
+           "TXS_PDF_WEIGHTS", "TXS_PDF_SIGMA_EXP"]
 
 
 def _stream():
@@ -274,6 +275,17 @@ def uniform_bins(grid: GridSpec, rays_o, rays_d, n_bins, *, near=0.0, far=float(
     return out
 
 
+def disparity_bins(grid: GridSpec, rays_o, rays_d, n_bins, *, near, far=float("inf")):
+    """Chord bins of equal width in 1/t (near > 0) -> edges [N, n_bins+1]."""
+    n = _rays(rays_o, rays_d)
+    out = torch.empty((n, n_bins + 1), dtype=torch.float32, device=rays_o.device)
+    g = grid.struct()
+    check(load().txs_disparity_bins(C.byref(g), float(near), float(far), _ptr(rays_o),
+                                    _ptr(rays_d), n, n_bins, _ptr(out), _stream()),
+          "txs_disparity_bins")
+    return out
+
+
 def blob_field(params, n_blobs, rays_o, rays_d, t0, t1, ray_id=None, fixed_count=0,
                want_rgb=True):
     """Support: analytic stand-in radiance field at interval midpoints."""
@@ -470,4 +482,15 @@ def span_bins(span, n_bins):
     _need(span, "span", torch.float32, (n, 2))
     out = torch.empty((n, n_bins + 1), dtype=torch.float32, device=span.device)
     check(load().txs_span_bins(n, _ptr(span), n_bins, _ptr(out), _stream()), "txs_span_bins")
+    return out
+
+
+def merge_edges(a, b):
+    """Sorted union of two ascending edge rows per ray: [N, na] + [N, nb] -> [N, na+nb]."""
+    n = a.shape[0]
+    _need(a, "a", torch.float32, (n, a.shape[1]))
+    _need(b, "b", torch.float32, (n, b.shape[1]))
+    out = torch.empty((n, a.shape[1] + b.shape[1]), dtype=torch.float32, device=a.device)
+    check(load().txs_merge_edges(n, a.shape[1], _ptr(a), b.shape[1], _ptr(b), _ptr(out),
+                                 _stream()), "txs_merge_edges")
     return out

@@ -4,6 +4,8 @@ sampling:  march_count -> exclusive_scan -> (one host read of the total) ->
            march_fill -> density (no grad) -> transmittance_prefix ->
            exclusive_scan -> gather_prefix
 rendering: render_fwd, with render_bwd as the autograd backward.
+pdf_render: the coarse-to-fine PDF estimator (uniform bins -> field density ->
+           resample -> merge_edges -> field -> render_fwd).
 Only argument plumbing lives here; every step runs in the HIP library.
 """
 from __future__ import annotations
@@ -107,6 +109,31 @@ def rendering(p: Packed, sigma, rgb, bg=None):
 
 def rendering_dense(t0, t1, sigma, rgb, n_rays, fixed_count, bg=None):
     return RenderFn.apply(sigma, rgb, None, t0, t1, bg, n_rays, fixed_count)
+
+
+def pdf_render(density_fn: Callable, field_fn: Callable, rays_o, rays_d, edges, n_fine, *,
+               union=True, keep=False):
+    """Coarse-to-fine PDF estimator (Table 1, third row, as vanilla NeRF runs it):
+    the radiance field's own density on the coarse bins `edges` [N, n_c+1]
+    (no gradient) -> inverse CDF of its transmittance to n_fine intervals ->
+    with union=True the coarse and fine edges together -> field -> render.
+    density_fn(rays_o, rays_d, t0, t1, n) -> sigma and field_fn(...) ->
+    (sigma, rgb) evaluate the field on n dense intervals per ray.  Returns
+    (rgb, opacity, depth), or with keep=True (t0, t1, sigma, rgb,
+    optical_depth, n) for a backward."""
+    n, nc = edges.shape[0], edges.shape[1] - 1
+    t0c, t1c = ops.edges_to_intervals(edges)
+    sig_c = density_fn(rays_o, rays_d, t0c, t1c, nc)
+    fine = ops.resample(edges, sig_c.view(n, nc), n_fine, mode=ops.TXS_PDF_SIGMA)
+    e = ops.merge_edges(edges, fine) if union else fine
+    m = e.shape[1] - 1
+    t0, t1 = ops.edges_to_intervals(e)
+    sig, rgb = field_fn(rays_o, rays_d, t0, t1, m)
+    out = ops.render_fwd(None, t0, t1, sig, rgb, n_rays=n, fixed_count=m,
+                         want_optical_depth=keep)
+    if keep:
+        return t0, t1, sig, rgb, out[4], m
+    return out[0], out[1], out[2]
 
 
 class OccupancyGrid:

@@ -415,6 +415,52 @@ def test_resample(gpu_lib, mode, use_u):
     assert np.array_equal(host(t1).reshape(n, n_out), out[:, 1:])
 
 
+@pytest.mark.parametrize("use_u", [False, True])
+def test_resample_exponential_in_bin(gpu_lib, use_u):
+    """Mode TXS_PDF_SIGMA_EXP.  Checked where the inverse is well conditioned:
+    mapped back through the binary64 piecewise-exponential CDF, every GPU edge
+    must sit at its quantile u' = u F_n within the binary32 CDF's error (the
+    bound of the linear mode, 4e-6 F_n) plus the CDF's slope times the edge's
+    own rounding; this needs no band, the CDF being continuous in t.  Edges in
+    bins of optical depth <= 4 must also match the oracle's within the linear
+    mode's bar scaled by the slope factor exp(tau)."""
+    g = scenes.rng(70 + use_u)
+    n, nb, n_out = 4000, 128, 32
+    a = g.uniform(1.0, 2.0, (n, 1))
+    edges = (a + np.concatenate([np.zeros((n, 1)), np.cumsum(g.uniform(0.005, 0.03, (n, nb)), 1)],
+                                1)).astype(np.float32)
+    vals = (g.exponential(1.0, (n, nb)) * (g.random((n, nb)) < 0.3) *
+            g.choice([1.0, 30.0, 300.0], (n, 1))).astype(np.float32)
+    vals[:10] = 0.0  # zero-mass rays fall back to the uniform estimator
+    u = np.sort(g.random((n, n_out + 1)), 1).astype(np.float32) if use_u else None
+    mode = gpu_lib.TXS_PDF_SIGMA_EXP
+    out = host(gpu_lib.resample(dev(edges), dev(vals), n_out, mode, None if u is None else dev(u)))
+    ref, bins, band = oracle.resample(edges, vals, n_out, mode, u)
+    e64, v64 = edges.astype(np.float64), vals.astype(np.float64)
+    P = np.concatenate([np.zeros((n, 1)), np.cumsum(v64 * np.diff(e64, axis=1), 1)], 1)
+    Fn = -np.expm1(-P[:, -1])
+    uu = (np.arange(n_out + 1) / n_out)[None, :].repeat(n, 0) if u is None else u.astype(np.float64)
+    live = Fn > 1e-12
+    rows = np.flatnonzero(live)
+    i = np.stack([np.clip(np.searchsorted(e64[r], out[r], side="right") - 1, 0, nb - 1)
+                  for r in rows])
+    ei = np.take_along_axis(e64[rows], i, 1)
+    vi = np.take_along_axis(v64[rows], i, 1)
+    Pt = np.take_along_axis(P[rows], i, 1) + vi * (out[rows] - ei)
+    F_t, T_t = -np.expm1(-Pt), np.exp(-Pt)
+    span = (e64[rows, -1] - e64[rows, 0])[:, None]
+    tolF = 4e-6 * Fn[rows, None] + vi * T_t * (2e-7 * np.abs(out[rows]) + 1e-6 * span)
+    bad = np.abs(F_t - uu[rows] * Fn[rows, None]) > tolF
+    assert not bad.any(), (bad.sum(), np.argwhere(bad)[:5])
+    # the uniform fallback is the uniform lattice, as in the linear mode
+    assert np.allclose(out[~live], ref[~live], rtol=1e-6, atol=1e-6)
+    # direct comparison where the bin's optical depth is moderate
+    tau = np.take_along_axis(v64 * np.diff(e64, axis=1), np.minimum(bins, nb - 1), 1)
+    tol = resample_tol(edges, vals, 0, ref, bins) * np.exp(np.minimum(tau, 4.0))
+    ok = (tau <= 4.0) & ~band[:, None]
+    assert not ((np.abs(out - ref) > tol) & ok).any()
+
+
 def test_uniform_bins(gpu_lib, tiny):
     o, d = tiny.rays_o, tiny.rays_d
     g = grid_spec(gpu_lib, tiny.bits, 64)
@@ -425,6 +471,22 @@ def test_uniform_bins(gpu_lib, tiny):
     ref = tn[:, None].astype(np.float64) + (tf - tn)[:, None].astype(np.float64) * k
     assert_close(e[hit], ref[hit], rel=1e-6, name="uniform edges")
     assert np.all(e[~hit] == 0.0)
+
+
+def test_disparity_bins(gpu_lib, tiny):
+    """Binary32 reciprocals of an interpolation of positive reciprocals: a few
+    roundings, no cancellation (rel 1e-6); the end edges are the chord's."""
+    o, d = tiny.rays_o, tiny.rays_d
+    g = grid_spec(gpu_lib, tiny.bits, 64)
+    for near in (0.05, 2.0):
+        e = host(gpu_lib.disparity_bins(g, dev(o), dev(d), 128, near=near))
+        ref = oracle.disparity_bins(o, d, np.full(3, -1.5, np.float32), np.full(3, 1.5, np.float32),
+                                    128, near)
+        assert_close(e, ref, rel=1e-6, floor_scale=0.0, name="disparity edges")
+        tn, tf = oracle.clip(o, d, np.full(3, -1.5, np.float32), np.full(3, 1.5, np.float32),
+                             near)
+        hit = tn < tf
+        assert np.array_equal(e[hit, 0], tn[hit]) and np.array_equal(e[hit, -1], tf[hit])
 
 
 def test_blob_field(gpu_lib):

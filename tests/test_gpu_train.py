@@ -162,3 +162,41 @@ def test_grid_judge_matches_oracle(gpu_lib):
     err = np.abs(host(judge.rgb) - ref["rgb"])
     assert err.max() <= 1e-4, err.max()
     assert ref["opacity"].mean() > 0.5  # the rays do see the scene
+
+
+def test_two_proposal_rounds_train(gpu_lib):
+    """Two rounds: the second network, trained on the intervals the first one
+    draws, fits the same targets (its loss falls by 10x in 150 steps), and the
+    trained two-round sampler renders far closer to the grid renderer than the
+    untrained one at equal final samples (every 64th ray of the 2^20-ray
+    unbounded rig)."""
+    from paper_2305_04966_amd.learned import (ProposalEstimator, cosine_lr, grid_render,
+                                              train_two_rounds, two_round_intervals)
+    w = scenes.unbounded()
+    idx = np.arange(0, w.n_rays, 64)
+    o, d = dev(w.rays_o[idx]), dev(w.rays_d[idx])
+    grid = gpu_lib.GridSpec(dev(w.bits.view(np.int32)), w.res, w.n_levels, (0.0, 0.0, 0.0),
+                            w.half_extent0)
+    fp = dev(w.fld.packed_params().astype(np.float32))
+    nb = w.fld.n_blobs
+    judge = grid_render(grid, o, d, fp, nb, dt0=w.dt0, t_min=w.t_min)
+    edges = gpu_lib.disparity_bins(grid, o, d, 64, near=1.0)
+    est1 = ProposalEstimator(dev(scenes.mlp_init(64)), 64, scale=1.5, contract=True)
+    est2 = ProposalEstimator(dev(scenes.mlp_init(64, seed=scenes.SEED_MLP + 16)), 64, scale=1.5,
+                             contract=True)
+    t0, t1 = est1.dense_intervals(edges)
+
+    def err(a, b, n):
+        sig, rgb = gpu_lib.blob_field(fp, nb, o, d, a, b, fixed_count=n)
+        out = gpu_lib.render_fwd(None, a, b, sig, rgb, n_rays=len(idx), fixed_count=n)
+        return float((out[0] - judge.rgb).abs().mean())
+
+    before = err(*two_round_intervals(est1, est2, o, d, edges, 32, 32), 32)
+    first = None
+    for step in range(1, 151):
+        l1, l2 = train_two_rounds(est1, est2, o, d, edges, judge, cosine_lr(step, 150), 32, t0, t1)
+        if step == 1:
+            first = float(l2.mean())
+    assert float(l2.mean()) < 0.1 * first, (first, float(l2.mean()))
+    after = err(*two_round_intervals(est1, est2, o, d, edges, 32, 32), 32)
+    assert after < 0.2 * before, (before, after)

@@ -689,3 +689,78 @@ def test_span_bins_closed_form():
     assert e[0].tolist() == [1.0, 1.5, 2.0, 2.5, 3.0]
     assert e[1].tolist() == [0.5] * 5
     assert np.allclose(np.diff(e[2]), 0.1875, rtol=0, atol=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# coarse-to-fine PDF estimator: the merged edge rows
+# ----------------------------------------------------------------------------
+def test_merge_edges_hand_case_and_invariants():
+    a = np.array([[0.0, 2.0, 4.0], [1.0, 1.0, 1.0]], np.float32)
+    b = np.array([[1.0, 2.0, 3.0, 5.0], [0.0, 1.0, 2.0, 3.0]], np.float32)
+    m = oracle.merge_edges(a, b)
+    assert m[0].tolist() == [0.0, 1.0, 2.0, 2.0, 3.0, 4.0, 5.0]
+    assert m[1].tolist() == [0.0, 1.0, 1.0, 1.0, 1.0, 2.0, 3.0]
+    g = scenes.rng(66)
+    a = np.sort(g.integers(0, 50, (100, 33)), 1).astype(np.float32)
+    b = np.sort(g.integers(0, 50, (100, 17)), 1).astype(np.float32)
+    m = oracle.merge_edges(a, b)
+    assert np.all(np.diff(m, axis=1) >= 0)
+    for r in range(100):  # same multiset of values
+        vals, cnt = np.unique(np.concatenate([a[r], b[r]]), return_counts=True)
+        mv, mc = np.unique(m[r], return_counts=True)
+        assert np.array_equal(vals, mv) and np.array_equal(cnt, mc)
+
+
+# ----------------------------------------------------------------------------
+# inverse CDF, exponential inside the bin (a density constant per bin)
+# ----------------------------------------------------------------------------
+def test_resample_exponential_single_bin_is_truncated_exponential_quantile():
+    # one bin [a, a + L] of density s: the samples are the quantiles of an
+    # exponential distribution truncated to the bin
+    a, L, s, n = 1.25, 2.0, float(np.float32(1.7)), 16  # exact in binary32
+    out, _, _ = oracle.resample(np.float32([[a, a + L]]), np.float32([[s]]), n,
+                                oracle.MODE_SIGMA_EXP)
+    Fn = -math.expm1(-s * L)
+    ref = [a - math.log1p(-(k / n) * Fn) / s for k in range(n + 1)]
+    assert np.allclose(out[0], ref, rtol=0, atol=1e-12)
+
+
+def test_resample_exponential_inverts_the_piecewise_exponential_cdf():
+    g = scenes.rng(68)
+    n_rays, nb, n_out = 50, 24, 40
+    e = np.cumsum(g.uniform(0.01, 0.2, (n_rays, nb + 1)), 1).astype(np.float32)
+    v = (g.exponential(3.0, (n_rays, nb)) * (g.random((n_rays, nb)) < 0.6)).astype(np.float32)
+    out, bins, _ = oracle.resample(e, v, n_out, oracle.MODE_SIGMA_EXP)
+    e64, v64 = e.astype(np.float64), v.astype(np.float64)
+    P = np.concatenate([np.zeros((n_rays, 1)), np.cumsum(v64 * np.diff(e64, axis=1), 1)], 1)
+    Fn = -np.expm1(-P[:, -1])
+    for r in range(n_rays):
+        for k in range(n_out + 1):
+            t = out[r, k]
+            i = min(np.searchsorted(e64[r], t, side="right") - 1, nb - 1)
+            Pt = P[r, i] + v64[r, i] * (t - e64[r, i])  # optical depth up to t
+            assert abs(-math.expm1(-Pt) - (k / n_out) * Fn[r]) <= 1e-12, (r, k)
+
+
+def test_resample_exponential_tends_to_linear_for_thin_bins():
+    g = scenes.rng(69)
+    e = np.cumsum(g.uniform(0.01, 0.2, (20, 33)), 1).astype(np.float32)
+    v = (g.uniform(0.5, 1.5, (20, 32)) * 1e-4).astype(np.float32)  # tau ~ 1e-5 per bin
+    lin, _, _ = oracle.resample(e, v, 17, oracle.MODE_SIGMA)
+    ex, _, _ = oracle.resample(e, v, 17, oracle.MODE_SIGMA_EXP)
+    width = np.diff(e.astype(np.float64), axis=1).max()
+    assert np.abs(lin - ex).max() <= 1e-4 * width
+
+
+def test_disparity_bins_closed_form():
+    # a ray along +x from x = -3 through the cube [-1.5, 1.5]^3: chord t in [1.5, 4.5];
+    # disparity edges 1/(2/3 + (2/9 - 2/3) k/4) = 1.5, 1.8, 2.25, 3, 4.5
+    o = np.float32([[-3.0, 0.1, 0.2], [0.0, 0.0, 0.0], [0.0, 5.0, 0.0]])
+    d = np.float32([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0.0, 1.0, 0.0]])
+    e = oracle.disparity_bins(o, d, BMIN, BMAX, 4, near=0.05)
+    assert np.allclose(e[0], [1.5, 1.8, 2.25, 3.0, 4.5], rtol=0, atol=1e-12)
+    # origin inside the cube: from the near plane to the exit at 1.5
+    assert e[1, 0] == np.float32(0.05) and abs(e[1, -1] - 1.5) < 1e-12
+    assert np.all(np.diff(1.0 / e[1]) < 0) and np.allclose(np.diff(np.diff(1.0 / e[1])), 0)
+    # a ray that misses: every edge at the near plane
+    assert np.allclose(e[2], np.float32(0.05), rtol=0, atol=0)

@@ -22,8 +22,12 @@ the combined estimator (Section 5, "Combined Sampling"): the grid first drops
 the rays that cross no occupied cell and narrows every other ray to its
 occupied span, and the proposal network bins only that span.
 
-`python train_proposal.py` prints one JSON line (`--combined` for the second
-experiment); --save writes the trained parameters (.npy).
+`run_pdf` runs the coarse-to-fine PDF estimator of vanilla NeRF (Table 1,
+third row) on the image scene: the field's density on coarse uniform bins,
+inverse CDF, the field on the coarse and fine edges together.
+
+`python train_proposal.py` prints one JSON line (`--combined`, `--pdf` for the
+other experiments); --save writes the trained parameters (.npy).
 """
 from __future__ import annotations
 
@@ -88,13 +92,14 @@ def _train(est, steps, lr0, lr1, log_every, log, step_fn):
 
 def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
         sweep=(32, 48, 64, 96, 128, 192, 256), err_bar=1e-3, lr0=1e-2, lr1=1e-4,
-        log_every=50, time_reps=5, untrained=True, log=print):
+        log_every=50, time_reps=5, untrained=True, spacing="linear", near=1.0, rounds=1,
+        n_mid=64, log=print):
     import torch
 
     import paper_2305_04966_amd as txs
     import scenes
     from paper_2305_04966_amd.learned import (ProposalEstimator, cosine_lr, grid_render,
-                                              proposal_render)
+                                              train_two_rounds, two_round_intervals)
 
     txs.load()
     w = scenes.unbounded()
@@ -112,7 +117,15 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
     N = len(ev)
     rec = {"workload": f"unbounded: 64 blobs + shell, 4x128^3 cascade, 8 cameras; "
                        f"{N} evaluation rays, {len(tr)} training rays",
-           "hidden": hidden, "bins": bins, "train_steps": steps, "err_bar": err_bar}
+           "hidden": hidden, "bins": bins, "train_steps": steps, "err_bar": err_bar,
+           "spacing": spacing if spacing == "linear" else f"disparity from t = {near}"}
+
+    def bins_of(ro, rd):
+        """The proposal's bins over the chord through the outermost cube:
+        equal in t, or equal in disparity 1/t from `near`."""
+        if spacing == "disparity":
+            return txs.disparity_bins(grid, ro, rd, bins, near=near)
+        return txs.uniform_bins(grid, ro, rd, bins)
 
     # 1. judge (evaluation rays) and targets (training rays)
     judge = grid_render(grid, o, d, fp, nb, dt0=w.dt0, t_min=w.t_min)
@@ -123,13 +136,29 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
     log(f"[judge] {N} rays, {judge.samples.n_samples} grid samples")
 
     # 2. train
-    edges = txs.uniform_bins(grid, o, d, bins)
-    edges_t = edges if train_stride == ray_stride else txs.uniform_bins(grid, ot, dt, bins)
+    edges = bins_of(o, d)
+    edges_t = edges if train_stride == ray_stride else bins_of(ot, dt)
     est = ProposalEstimator(dev(scenes.mlp_init(hidden)), hidden, scale=1.5, contract=True)
+    # a second round: its own network, drawn from a second seed
+    est2 = (ProposalEstimator(dev(scenes.mlp_init(hidden, seed=scenes.SEED_MLP + 16)), hidden,
+                              scale=1.5, contract=True) if rounds == 2 else None)
+    if rounds == 2:
+        rec["rounds"] = f"2 ({bins} bins, then {n_mid} intervals)"
+
+    def intervals(ro, rd, e, n_out):
+        if rounds == 2:
+            return two_round_intervals(est, est2, ro, rd, e, n_mid, n_out)
+        return est.sample_intervals(ro, rd, e, n_out)
+
+    def render_learned(ro, rd, e, n_out, keep=False):
+        a, b = intervals(ro, rd, e, n_out)
+        sg, rgb = field(ro, rd, a, b, n_out)
+        out = txs.render_fwd(None, a, b, sg, rgb, n_rays=e.shape[0], fixed_count=n_out,
+                             want_optical_depth=keep)
+        return (a, b, sg, rgb, out[4]) if keep else out[0]
 
     def err(n_out):
-        rgb = proposal_render(est, o, d, edges, n_out, field)[0]
-        return float((rgb - judge.rgb).abs().mean())
+        return float((render_learned(o, d, edges, n_out) - judge.rgb).abs().mean())
 
     if untrained:
         rec["untrained_err"] = {n: err(n) for n in sweep}
@@ -138,8 +167,11 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
     torch.cuda.synchronize()
     t_train = time.perf_counter()
     for step in range(1, steps + 1):
-        loss = est.train_step(ot, dt, edges_t, target, cosine_lr(step, steps, lr0, lr1),
-                              t0d, t1d)
+        lr = cosine_lr(step, steps, lr0, lr1)
+        if rounds == 2:
+            loss = train_two_rounds(est, est2, ot, dt, edges_t, target, lr, n_mid, t0d, t1d)[1]
+        else:
+            loss = est.train_step(ot, dt, edges_t, target, lr, t0d, t1d)
         if step == 1 or step % log_every == 0 or step == steps:
             lm = float(loss.mean())
             losses.append((step, lm))
@@ -168,8 +200,7 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
         txs.render_bwd(q.packed_info, q.t0, q.t1, sg, rgb, g_rgb, optical_depth=out[4])
 
     def learned_step():
-        e0 = txs.uniform_bins(grid, o, d, bins)
-        a, b, sg, rgb, od = proposal_render(est, o, d, e0, n_star, field, keep=True)
+        a, b, sg, rgb, od = render_learned(o, d, bins_of(o, d), n_star, keep=True)
         txs.render_bwd(None, a, b, sg, rgb, g_rgb, n_rays=N, fixed_count=n_star,
                        optical_depth=od)
 
@@ -290,6 +321,62 @@ def run_combined(*, steps=300, hidden=128, bins=128, eval_bins=(64, 128), ray_st
     return rec
 
 
+def run_pdf(*, coarse=(32, 64, 128), fine=(16, 32, 64, 128), ray_stride=1, err_bar=1e-3,
+            time_reps=5, log=print):
+    """The coarse-to-fine PDF estimator (Table 1, third row, as vanilla NeRF
+    runs it) on the image scene: the field's own density on n_c uniform bins
+    over each ray's chord through the grid cube, inverse CDF to n_f intervals,
+    the field rendered on the coarse and fine edges together.  For each n_c
+    the fewest n_f within `err_bar` of the grid renderer's colours is timed end
+    to end (coarse density, fine field, render fwd + bwd); the fastest such
+    configuration is the estimator's result.  Nothing is trained: the coarse
+    density is the field itself (the ideal coarse network)."""
+    import torch
+
+    import paper_2305_04966_amd as txs
+    import scenes
+    from paper_2305_04966_amd.learned import grid_render
+
+    txs.load()
+    sc = _Scene(torch, txs, scenes.image())
+    w, dev, grid = sc.w, sc.dev, sc.grid
+    ev = np.arange(0, w.n_rays, ray_stride)
+    o, d = dev(w.rays_o[ev]), dev(w.rays_d[ev])
+    N = len(ev)
+    nb = w.fld.n_blobs
+    dens = lambda o_, d_, t0, t1, n: txs.blob_field(sc.fp, nb, o_, d_, t0, t1, fixed_count=n,
+                                                    want_rgb=False)[0]
+    judge = grid_render(grid, o, d, sc.fp, nb, dt0=w.dt0, t_min=w.t_min)
+    g_rgb = dev(w.grads[ev])
+    rec = {"workload": f"image: 32 blobs, 128^3 grid over [-1.5,1.5]^3, 1024x1024 pinhole; "
+                       f"{N} evaluation rays", "err_bar": err_bar}
+
+    def render(nc, nf):
+        e = txs.uniform_bins(grid, o, d, nc)
+        return txs.pdf_render(dens, sc.field, o, d, e, nf)[0]
+
+    def step(nc, nf):
+        e = txs.uniform_bins(grid, o, d, nc)
+        a, b, sg, rgb, od, m = txs.pdf_render(dens, sc.field, o, d, e, nf, keep=True)
+        txs.render_bwd(None, a, b, sg, rgb, g_rgb, n_rays=N, fixed_count=m, optical_depth=od)
+
+    err = {nc: {nf: float((render(nc, nf) - judge.rgb).abs().mean()) for nf in fine}
+           for nc in coarse}
+    log(f"[eval] pdf {err}")
+    timed = {}
+    for nc in coarse:
+        ok = [nf for nf in fine if err[nc][nf] <= err_bar]
+        if ok:
+            timed[(nc, min(ok))] = _timed(torch, lambda: step(nc, min(ok)), time_reps)
+    best = min(timed, key=timed.get) if timed else None
+    rec.update({"err": {str(nc): {str(nf): e for nf, e in err[nc].items()} for nc in err},
+                "timed_ms": {f"{nc}+{nf}": ms for (nc, nf), ms in timed.items()},
+                "n_coarse": best[0] if best else None, "n_fine": best[1] if best else None,
+                "ms": timed[best] if best else None,
+                "rays_per_s": N / (timed[best] * 1e-3) if best else None})
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=1000)
@@ -306,7 +393,20 @@ def main():
     ap.add_argument("--save", default="")
     ap.add_argument("--combined", action="store_true",
                     help="proposal alone vs combined grid + proposal on the image scene")
+    ap.add_argument("--spacing", default="linear", choices=["linear", "disparity"],
+                    help="proposal bins equal in t or in 1/t over the chord")
+    ap.add_argument("--near", type=float, default=1.0, help="near plane of disparity bins")
+    ap.add_argument("--rounds", type=int, default=1, choices=[1, 2],
+                    help="proposal rounds (2: a second network on the first one's intervals)")
+    ap.add_argument("--n-mid", type=int, default=64, help="intervals the first round draws")
+    ap.add_argument("--pdf", action="store_true",
+                    help="the coarse-to-fine PDF estimator on the image scene")
     args = ap.parse_args()
+    if args.pdf:
+        rec = run_pdf(ray_stride=args.ray_stride, err_bar=args.err_bar,
+                      time_reps=args.time_reps, log=lambda s: print(s, flush=True))
+        print(json.dumps(rec), flush=True)
+        return
     if args.combined:
         rec = run_combined(steps=args.steps, hidden=args.hidden, bins=args.bins,
                            ray_stride=args.ray_stride, train_stride=args.train_stride,
@@ -319,7 +419,9 @@ def main():
                    ray_stride=args.ray_stride, train_stride=args.train_stride,
                    sweep=[int(s) for s in args.sweep.split(",")], err_bar=args.err_bar,
                    lr0=args.lr0, lr1=args.lr1, log_every=args.log_every,
-                   time_reps=args.time_reps, log=lambda s: print(s, flush=True))
+                   time_reps=args.time_reps, spacing=args.spacing, near=args.near,
+                   rounds=args.rounds, n_mid=args.n_mid,
+                   log=lambda s: print(s, flush=True))
     if args.save:
         np.save(args.save, est.params.cpu().numpy())
     print(json.dumps(rec), flush=True)
