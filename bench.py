@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--learned-spacing", default="disparity", choices=["linear", "disparity"],
                     help="proposal bins equal in t, or equal in 1/t from --learned-near")
     ap.add_argument("--learned-near", type=float, default=0.5)
+    ap.add_argument("--learned-bins", type=int, default=64,
+                    help="proposal bins per ray")
     ap.add_argument("--combined-steps", type=int, default=300,
                     help="train the proposal network alone and inside the grid's occupied "
                          "spans this many steps each on the image scene and report both "
@@ -213,15 +215,16 @@ def gpu_bench(args, w):
 
 def learned_vs_grid(args):
     """The learned estimator against the occupancy grid on the unbounded scene:
-    train the proposal network (untimed) on bins spaced equally in disparity
-    from t = 0.5 (below the closest content, ~1 from every camera), then time
+    train the proposal network (untimed) on 64 bins spaced equally in
+    disparity from t = 0.5 (below the closest content, ~1 from every camera),
+    then time
     both samplers end to end (fwd + bwd, the field stand-in on both sides) on
     all 2^20 rays, the learned one at the fewest final samples within 1e-3
     mean rgb error of the grid."""
     from train_proposal import run
     rec, _ = run(steps=args.learned_steps, train_stride=args.learned_train_stride,
                  sweep=[int(s) for s in args.learned_sweep.split(",")], untrained=False,
-                 spacing=args.learned_spacing, near=args.learned_near,
+                 spacing=args.learned_spacing, near=args.learned_near, bins=args.learned_bins,
                  log_every=max(args.learned_steps, 1), time_reps=3,
                  log=lambda s: print(s, file=sys.stderr, flush=True))
     keep = ("workload", "hidden", "bins", "spacing", "train_steps", "ms_per_train_step", "err_bar",

@@ -10,6 +10,9 @@
 // P_i = P_total - Q_i, with P_total the ray's total optical depth from the
 // forward (or from a tau-only pre-pass), so T_i = exp(-P_i) needs no forward
 // walk and nothing per sample is stored between the two directions.
+// Windows of 4 samples per lane: the adjoint's state per sample is larger
+// than the forward's, and half the window keeps three waves per SIMD.
+#define TXS_RENDER_K 4
 #include "render_window.h"
 
 namespace txs {

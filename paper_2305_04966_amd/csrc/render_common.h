@@ -20,7 +20,10 @@
 namespace txs {
 namespace {
 
-constexpr int K = 8;               // samples per lane per window
+#ifndef TXS_RENDER_K
+#define TXS_RENDER_K 8
+#endif
+constexpr int K = TXS_RENDER_K;    // samples per lane per window (a multiple of 4)
 constexpr int W = kWave * K;       // samples per window
 constexpr int kWaves = 4;          // waves per block
 constexpr int kBlock = kWave * kWaves;
