@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # dense bf16 matrix-core peak of MI355X (published)
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic.json")
 
 # algorithmic HBM bytes of each library entry point (N rays, Sm marched, S kept)
@@ -64,6 +65,9 @@ def parse():
     ap.add_argument("--pdf", type=int, default=1,
                     help="run the coarse-to-fine PDF estimator on the image scene and report "
                          "it (0 = skip)")
+    ap.add_argument("--proposal-config", type=int, default=1,
+                    help="time one proposal round at its own configuration (2^18 rays, hidden "
+                         "64, 128 bins -> 32) (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run a plain device copy of this many MiB (counter "
                          "calibration for profiler byte counts)")
@@ -228,7 +232,10 @@ def learned_vs_grid(args):
                  log_every=max(args.learned_steps, 1), time_reps=3,
                  log=lambda s: print(s, file=sys.stderr, flush=True))
     keep = ("workload", "hidden", "bins", "spacing", "train_steps", "ms_per_train_step", "err_bar",
-            "n_final", "within_err_bar", "trained_err", "grid_samples", "grid_ms",
+            "mlp_fwd_points", "mlp_fwd_ms", "mlp_bwd_points", "mlp_bwd_ms",
+            "mlp_fwd_flop_per_point", "mlp_bwd_flop_per_point",
+            "n_final", "within_err_bar", "trained_err", "trained_err_seen", "rays_seen",
+            "grid_samples", "grid_ms",
             "learned_ms", "grid_rays_per_s", "learned_rays_per_s", "learned_over_grid")
     out = {k: rec[k] for k in keep}
     out["final_loss"] = rec["loss"][-1][1]
@@ -247,6 +254,23 @@ def combined_vs_proposal(args):
                        log_every=max(args.combined_steps, 1), time_reps=3,
                        log=lambda s: print(s, file=sys.stderr, flush=True))
     return rec
+
+
+def mfma_roofline(lv, pc):
+    """Matrix-core rooflines of the proposal network's kernels (algorithmic
+    bf16 FLOP per launch / its mean duration, against the dense bf16 peak)."""
+    out = []
+    for name, rec, key in (("prop_mlp_fwd (hidden 128, learned step)", lv, "fwd"),
+                           ("prop_mlp_bwd (hidden 128, training batch)", lv, "bwd"),
+                           ("prop_mlp_fwd (hidden 64, proposal round)", pc, "fwd")):
+        if not rec or f"mlp_{key}_ms" not in rec:
+            continue
+        flop = rec[f"mlp_{key}_points"] * rec[f"mlp_{key}_flop_per_point"]
+        tf = flop / (rec[f"mlp_{key}_ms"] * 1e-3) / 1e12
+        out.append({"kernel": name, "bound": "mfma", "achieved": tf, "peak": BF16_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": tf / BF16_PEAK_TFLOPS,
+                    "flop_per_launch": flop, "ms": rec[f"mlp_{key}_ms"]})
+    return out
 
 
 def pdf_estimator(args):
@@ -367,6 +391,14 @@ def main():
         rec["combined_vs_proposal"] = combined_vs_proposal(args)
     if args.pdf:
         rec["pdf_estimator"] = pdf_estimator(args)
+    if args.proposal_config:
+        from train_proposal import run_proposal_config
+        rec["proposal_config"] = run_proposal_config(
+            time_reps=3, log=lambda s: print(s, file=sys.stderr, flush=True))
+    lv = rec.get("learned_vs_grid")
+    pc = rec.get("proposal_config")
+    if lv or pc:
+        rec["mfma_roofline"] = mfma_roofline(lv, pc)
     if rank == 0 and args.cpu_sample > 0:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     if rank == 0:

@@ -90,6 +90,14 @@ def _train(est, steps, lr0, lr1, log_every, log, step_fn):
     return time.perf_counter() - t, losses
 
 
+def mlp_flops(hidden, adjoint=False):
+    """Algorithmic FLOP per point of the proposal network: forward 2 (39 H + H^2
+    + H); the adjoint adds the recomputed forward, W2^T d2 (2 H^2) and the
+    weight gradients of W2 (2 H^2) and W1 (2 . 39 H)."""
+    f = 2 * (39 * hidden + hidden * hidden + hidden)
+    return f + 2 * hidden * hidden * 2 + 2 * 39 * hidden if adjoint else f
+
+
 def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
         sweep=(32, 48, 64, 96, 128, 192, 256), err_bar=1e-3, lr0=1e-2, lr1=1e-4,
         log_every=50, time_reps=5, untrained=True, spacing="linear", near=1.0, rounds=1,
@@ -187,6 +195,10 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
     n_star = min(ok) if ok else max(sweep)
     rec["n_final"] = n_star
     rec["within_err_bar"] = bool(ok)
+    seen = judge.opacity > 0.01  # the rays where the judge sees the scene
+    rec["trained_err_seen"] = float((render_learned(o, d, edges, n_star)[seen] -
+                                     judge.rgb[seen]).abs().mean())
+    rec["rays_seen"] = int(seen.sum())
 
     # 4. timing, fwd + bwd, field included on both sides
     g_rgb = dev(w.grads[ev])
@@ -209,7 +221,64 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
         rec[f"{name}_ms"] = ms
         rec[f"{name}_rays_per_s"] = N / (ms * 1e-3)
     rec["learned_over_grid"] = rec["learned_rays_per_s"] / rec["grid_rays_per_s"]
+
+    # the proposal network's kernels alone: the forward on every evaluation
+    # ray's bins (as in the learned step), the adjoint on the training batch
+    e_ev = bins_of(o, d)
+    ds = torch.ones((edges_t.shape[0], bins), dtype=torch.float32, device=e_ev.device)
+    rec["mlp_fwd_points"] = N * bins
+    rec["mlp_fwd_ms"] = _timed(torch, lambda: est.density(o, d, e_ev), time_reps)
+    rec["mlp_bwd_points"] = edges_t.shape[0] * bins
+    rec["mlp_bwd_ms"] = _timed(torch, lambda: txs.prop_mlp_bwd(est.spec, ot, dt, edges_t, ds,
+                                                               workspace=est.workspace),
+                               time_reps)
+    rec["mlp_fwd_flop_per_point"] = mlp_flops(hidden)
+    rec["mlp_bwd_flop_per_point"] = mlp_flops(hidden, adjoint=True)
     return rec, est
+
+
+def run_proposal_config(*, n_rays=1 << 18, hidden=64, bins=128, n_out=32, time_reps=5, log=print):
+    """The proposal round at its own configuration, timed end to end: 2^18 rays
+    from a radius-3 sphere into the [-1.5, 1.5]^3 box, 128 uniform bins, the
+    hidden-64 network (seeded initialisation: timing does not depend on the
+    weights), inverse CDF to 32 intervals, the 64-blob field without the
+    background shell, render fwd + bwd.  Parity of each step at this size is
+    in the test-suite."""
+    import torch
+
+    import paper_2305_04966_amd as txs
+    import scenes
+    from paper_2305_04966_amd.learned import ProposalEstimator
+
+    txs.load()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    o_np, d_np = scenes.sphere_rays(n_rays)
+    o, d = dev(o_np), dev(d_np)
+    fld = scenes.blob_field(64)
+    fp = dev(fld.packed_params().astype(np.float32))
+    grid = txs.GridSpec(torch.zeros(max(1, 64 ** 3 // 32), dtype=torch.int32, device="cuda"), 64)
+    est = ProposalEstimator(dev(scenes.mlp_init(hidden)), hidden, scale=1.5)
+    g_rgb = dev(scenes.upstream_grads(n_rays))
+
+    def step():
+        e = txs.uniform_bins(grid, o, d, bins)
+        a, b = est.sample_intervals(o, d, e, n_out)
+        sg, rgb = txs.blob_field(fp, fld.n_blobs, o, d, a, b, fixed_count=n_out)
+        out = txs.render_fwd(None, a, b, sg, rgb, n_rays=n_rays, fixed_count=n_out,
+                             want_optical_depth=True)
+        txs.render_bwd(None, a, b, sg, rgb, g_rgb, n_rays=n_rays, fixed_count=n_out,
+                       optical_depth=out[4])
+
+    e0 = txs.uniform_bins(grid, o, d, bins)
+    ms = _timed(torch, step, time_reps)
+    fwd_ms = _timed(torch, lambda: est.density(o, d, e0), time_reps)
+    rec = {"workload": f"proposal round: {n_rays} sphere rays, {bins} uniform bins, hidden "
+                       f"{hidden}, inverse CDF to {n_out} intervals, 64-blob field, render "
+                       f"fwd + bwd", "ms": ms, "rays_per_s": n_rays / (ms * 1e-3),
+           "mlp_fwd_points": n_rays * bins, "mlp_fwd_ms": fwd_ms,
+           "mlp_fwd_flop_per_point": mlp_flops(hidden)}
+    log(f"[proposal config] {rec}")
+    return rec
 
 
 def run_combined(*, steps=300, hidden=128, bins=128, eval_bins=(64, 128), ray_stride=1,
