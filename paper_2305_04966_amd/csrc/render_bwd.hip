@@ -23,15 +23,15 @@ namespace {
 // sums entering from the right for the chain that crosses the window end;
 // replaced by the sums leaving to the left.
 //
-// xt0, xt1, xsg hold this window's t0, t1, sigma (loaded one window ahead);
-// when p_next >= 0 they are refilled with those of the window [p_next,
-// lim_next) while this one computes.  The colour loads of a whole window are
-// issued first, so that waiting for them never waits for the prefetch.
+// xt0, xt1, xsg hold this window's t0, t1, sigma and rg its colour rows
+// (whole windows only), all loaded one window ahead: when p_next >= 0 they are
+// refilled with those of the window [p_next, lim_next) -- always whole --
+// while this one computes.
 template <int kMode>
 __device__ void bwd_window(const Args& a, WaveLds& L, float4* stage, int64_t p, int64_t lim,
                            int seg_in, double& cQ, double& cS, float (&xt0)[K],
-                           float (&xt1)[K], float (&xsg)[K], int64_t p_next,
-                           int64_t lim_next) {
+                           float (&xt1)[K], float (&xsg)[K], float4 (&rg)[3 * K / 4],
+                           int64_t p_next, int64_t lim_next) {
   const int ln = lane();
   const int64_t pos0 = p + (int64_t)K * ln;
   float tau[K], delta[K], mid[K];
@@ -42,14 +42,6 @@ __device__ void bwd_window(const Args& a, WaveLds& L, float4* stage, int64_t p, 
     mid[j] = 0.5f * (xt0[j] + xt1[j]);
   }
   const bool full = p + W <= lim;  // wave-uniform
-  float4 rg[3 * K / 4];
-#pragma unroll
-  for (int q = 0; q < 3 * K / 4; ++q) rg[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  if (kMode == kBwd && full) {
-    const float4* s4 = reinterpret_cast<const float4*>(a.rgb + 3 * p);
-#pragma unroll
-    for (int q = 0; q < 3 * K / 4; ++q) rg[q] = s4[q * kWave + ln];
-  }
   if (p_next >= 0) {
     const int64_t pn = p_next + (int64_t)K * ln;
     load_k(a.t0, pn, lim_next, xt0);
@@ -102,6 +94,11 @@ __device__ void bwd_window(const Args& a, WaveLds& L, float4* stage, int64_t p, 
     if (kMode == kBwd) {
       if (full) unstage_rgb(rg, stage, c);
       else load_rgb(a.rgb, pos0, lim, c);
+      if (p_next >= 0) {  // the next window's colour rows, while this one computes
+        const float4* s4 = reinterpret_cast<const float4*>(a.rgb + 3 * p_next);
+#pragma unroll
+        for (int q = 0; q < 3 * K / 4; ++q) rg[q] = s4[q * kWave + ln];
+      }
     } else {
       load_k(a.g_w, pos0, lim, gwv);
     }
@@ -219,11 +216,19 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(Args a) {
   const int64_t nwin = (R.hi - p0 + W - 1) / W;
   double cQ = 0.0, cS = 0.0;
   float xt0[K], xt1[K], xsg[K];
+  float4 rg[3 * K / 4];
+#pragma unroll
+  for (int q = 0; q < 3 * K / 4; ++q) rg[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   {
     const int64_t p = p0 + (nwin - 1) * W, lim = min(p + W, R.hi);
     load_k(a.t0, p + (int64_t)K * ln, lim, xt0);
     load_k(a.t1, p + (int64_t)K * ln, lim, xt1);
     load_k(a.sigma, p + (int64_t)K * ln, lim, xsg);
+    if (kMode == kBwd && p + W <= lim) {
+      const float4* s4 = reinterpret_cast<const float4*>(a.rgb + 3 * p);
+#pragma unroll
+      for (int q = 0; q < 3 * K / 4; ++q) rg[q] = s4[q * kWave + ln];
+    }
   }
   for (int64_t i = nwin - 1; i >= 0; --i) {
     const int64_t p = p0 + i * W;
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(Args a) {
     const int seg_in = cover ? __builtin_ctzll(cover) : -1;
     write_marks(L, p, R.st, R.en, R.active);
     // the window to the left, [p - W, p), is whole and inside [p0, R.hi)
-    bwd_window<kMode>(a, L, stage, p, min(p + W, R.hi), seg_in, cQ, cS, xt0, xt1, xsg,
+    bwd_window<kMode>(a, L, stage, p, min(p + W, R.hi), seg_in, cQ, cS, xt0, xt1, xsg, rg,
                       i > 0 ? p - W : -1, p);
   }
 }
