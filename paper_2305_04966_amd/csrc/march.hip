@@ -112,9 +112,9 @@ __device__ __forceinline__ bool probe(const Lattice& p, const float o[3], const 
     for (int c = 0; c < 3; ++c) {
       const float x = o[c] + m * d[c];
       const float u = (x - p.box.bmin[c]) * p.box.scale[c];
-      float f = floorf(u);
-      f = fminf(fmaxf(f, 0.0f), p.resf - 1.0f);
-      cell[c] = (int)f;
+      // clamp of the floor to [0, res - 1] as one median-of-three (u is
+      // never NaN here, so it equals min(max(floor(u), 0), res - 1))
+      cell[c] = (int)__builtin_amdgcn_fmed3f(floorf(u), 0.0f, p.resf - 1.0f);
     }
     const int32_t idx = cell[0] + p.res * (cell[1] + p.res * cell[2]);
     word = p.bits[idx >> 5];
