@@ -8,7 +8,7 @@ The field is the analytic stand-in for the user's radiance field (support,
 not part of the library's roofline).  Two device->host reads per step (the
 sample totals that size the packed tensors) are part of the step.
 
-Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints ONE JSON line.  --gpus above 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -335,8 +335,8 @@ def cpu_baseline(w, every):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not "
-              "supported (rays shard with no exchange; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the library runs on exactly one GPU; --gpus {args.gpus} is not "
+              "supported (rays would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     w, desc = make_workload(args.workload)
