@@ -179,7 +179,7 @@ def target_histograms(n_rays, seed):
     return info, t0, t1, w
 
 
-@pytest.mark.parametrize("nb", [16, 128])
+@pytest.mark.parametrize("nb", [1, 16, 128, 1024])
 def test_hist_loss(gpu_lib, nb):
     n = 1500
     info, t0, t1, w = target_histograms(n, 3 + nb)
@@ -193,6 +193,15 @@ def test_hist_loss(gpu_lib, nb):
     np.testing.assert_allclose(host(loss), rl, rtol=2e-5, atol=1e-7)
     np.testing.assert_allclose(host(d), rd, rtol=2e-5, atol=1e-9)
     assert (rl > 0).mean() > 0.3
+
+
+def test_hist_loss_rejects_more_bins_than_its_limit(gpu_lib):
+    n, nb = 4, 1025
+    info, t0, t1, w = target_histograms(n, 9)
+    edges = np.tile(np.linspace(1.5, 4.5, nb + 1, dtype=np.float32), (n, 1))
+    pw = np.full((n, nb), 1.0 / nb, np.float32)
+    with pytest.raises(gpu_lib.TxsError):
+        gpu_lib.hist_loss(dev(info), dev(t0), dev(t1), dev(w), dev(edges), dev(pw))
 
 
 def test_weights_only_render(gpu_lib):

@@ -415,6 +415,27 @@ def test_resample(gpu_lib, mode, use_u):
     assert np.array_equal(host(t1).reshape(n, n_out), out[:, 1:])
 
 
+@pytest.mark.parametrize("nb,n_out", [(1, 1), (1, 7), (1024, 1), (1024, 500), (3, 2000)])
+def test_resample_size_limits(gpu_lib, nb, n_out):
+    """One bin, the largest bin count (1024), a single output interval and far
+    more outputs than bins, against the oracle; 1025 bins are refused."""
+    g = scenes.rng(72 + nb)
+    n = 300
+    edges = (1.0 + np.concatenate([np.zeros((n, 1)),
+                                   np.cumsum(g.uniform(0.001, 0.01, (n, nb)), 1)], 1)
+             ).astype(np.float32)
+    vals = (g.exponential(1.0, (n, nb)) * (g.random((n, nb)) < 0.5) * 20.0).astype(np.float32)
+    vals[:3] = 0.0
+    for mode in (0, 1):
+        out = host(gpu_lib.resample(dev(edges), dev(vals), n_out, mode))
+        ref, bins, band = oracle.resample(edges, vals, n_out, mode)
+        tol = resample_tol(edges, vals, mode, ref, bins)
+        assert not ((np.abs(out - ref) > tol) & ~band[:, None]).any()
+    big = np.tile(np.linspace(1.0, 2.0, 1026, dtype=np.float32), (2, 1))
+    with pytest.raises(gpu_lib.TxsError):
+        gpu_lib.resample(dev(big), dev(np.ones((2, 1025), np.float32)), 4)
+
+
 @pytest.mark.parametrize("use_u", [False, True])
 def test_resample_exponential_in_bin(gpu_lib, use_u):
     """Mode TXS_PDF_SIGMA_EXP.  Checked where the inverse is well conditioned:
