@@ -417,9 +417,9 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc1[r][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   }
-  float db2p[RO], db1p[RO];
+  float db2p[RO];
 #pragma unroll
-  for (int r = 0; r < RO; ++r) db2p[r] = db1p[r] = 0.0f;
+  for (int r = 0; r < RO; ++r) db2p[r] = 0.0f;
   float acc3[MT][4];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
@@ -537,10 +537,7 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
         AD2[r] = *reinterpret_cast<const bf16x8*>(&sD2[row * RS + kp]);
         AD1[r] = *reinterpret_cast<const bf16x8*>(&sD1[row * RS + kp]);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          db2p[r] += (float)AD2[r][j];
-          db1p[r] += (float)AD1[r][j];
-        }
+        for (int j = 0; j < 8; ++j) db2p[r] += (float)AD2[r][j];
       }
 #pragma unroll
       for (int mf = 0; mf < MT; ++mf) {
@@ -575,16 +572,14 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
         const int f = feature_of(gf, col);
         if (f >= 0) out[po.W1 + (int64_t)o * kNF + f] = acc1[r][gf][i];
       }
+      // feature slot 13 of lane group 0 is the constant 1 that carries b1, so
+      // its column of dW1 is db1 = sum over points of d1
+      if (col == 13) out[po.b1 + o] = acc1[r][0][i];
     }
-    float s2 = db2p[r], s1 = db1p[r];
+    float s2 = db2p[r];
     s2 += __shfl_xor(s2, 16, kWave);
     s2 += __shfl_xor(s2, 32, kWave);
-    s1 += __shfl_xor(s1, 16, kWave);
-    s1 += __shfl_xor(s1, 32, kWave);
-    if (g == 0) {
-      out[po.b2 + 16 * (RO * w + r) + col] = s2;
-      out[po.b1 + 16 * (RO * w + r) + col] = s1;
-    }
+    if (g == 0) out[po.b2 + 16 * (RO * w + r) + col] = s2;
   }
   // dw3, db3: sum over the 16 point columns, then over the 4 waves in order
 #pragma unroll
