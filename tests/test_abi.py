@@ -49,3 +49,21 @@ def test_version_and_error_without_gpu(lib):
     assert b"n_bins" in lib.txs_last_error()
     lib.txs_scan_workspace_size.restype = C.c_size_t
     assert lib.txs_scan_workspace_size(C.c_int32(1 << 20)) >= 8 * 256
+
+
+def test_plain_c_consumer(lib, tmp_path):
+    """The header is valid C99 under -Wall -Wextra -Werror -pedantic, the
+    library links from C, and host-side validation answers without a GPU."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = os.path.join(ROOT, "tests", "cpp", "abi_consumer.c")
+    exe = str(tmp_path / "abi_consumer")
+    libdir = os.path.dirname(LIB)
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                           "-I", os.path.join(ROOT, "include"), src, "-L", libdir, "-ltxs",
+                           f"-Wl,-rpath,{libdir}", "-o", exe])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, (out.returncode, out.stdout, out.stderr)
+    assert out.stdout.strip() == "ok"
