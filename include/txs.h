@@ -120,6 +120,34 @@ txs_status txs_march_fill(const txs_grid* grid, const txs_march_params* params,
                           int32_t* ray_id, void* stream);
 
 /*
+ * Grid estimator over contracted space (a variant for unbounded scenes, next
+ * to the cascade of nested cubes; Section 3.2, "Handling Unbounded Scenes",
+ * leaves the parameterisation of far space to the works it cites, of which
+ * Mip-NeRF 360's contraction is one): the same lattice,
+ * segments, steps, outputs and errors as txs_march_count / txs_march_fill,
+ * but the occupancy of a sample is read from ONE grid of res^3 bits
+ * (grid->bits, x fastest) covering the contracted cube [-2, 2]^3 around
+ * grid->center.  The midpoint x of a sample maps, in binary32 and in this
+ * order, to
+ *   y  = (x - center) * s,  s = 1 / contract_scale (one rounding),
+ *   r2 = y0 y0 + y1 y1 + y2 y2;  if r2 > 1: r = sqrt(r2), q = 1 / r,
+ *        y = y * ((2 - q) * q)   (Mip-NeRF 360's contraction into radius 2),
+ *   cell_c = clamp(floor((y_c + 2) * (res / 4)), 0, res - 1),
+ * with correctly rounded division and square root.  grid->n_levels and
+ * grid->half_extent0 still define the cubes whose segments set the lattice
+ * steps (dt0 2^l on level l); contract_scale > 0.
+ */
+txs_status txs_march_count_contracted(const txs_grid* grid, const txs_march_params* params,
+                                      float contract_scale, const float* rays_o,
+                                      const float* rays_d, int32_t n_rays, int32_t* counts,
+                                      void* stream);
+txs_status txs_march_fill_contracted(const txs_grid* grid, const txs_march_params* params,
+                                     float contract_scale, const float* rays_o,
+                                     const float* rays_d, int32_t n_rays,
+                                     const int32_t* packed_info, int64_t capacity, float* t0,
+                                     float* t1, int32_t* ray_id, void* stream);
+
+/*
  * No-gradient filtering (Section 4.2): with tau_i = sigma_i (t1_i - t0_i) and
  * T_i = exp(-sum_{j<i} tau_j) over the samples of a ray, kept_counts[r] is
  * the number of leading samples with T_i >= t_min (the paper uses 1e-4).
@@ -401,6 +429,20 @@ txs_status txs_blob_field(const float* params, int32_t n_blobs, const float* ray
  * n_cells must be a multiple of 32 (res >= 4).  Binary32 arithmetic.
  */
 txs_status txs_grid_points(const txs_grid* grid, const float* u, float* points, void* stream);
+
+/*
+ * Cell points of a grid over contracted space (the grid that
+ * txs_march_count_contracted reads; update it with txs_grid_ema as any
+ * other): for cell (x, y, z) of the res^3 grid over [-2, 2]^3, the point
+ * z = -2 + (index + u) (4 / res) per axis, mapped back through the
+ * contraction -- unchanged for |z| <= 1, radius 1 / (2 - |z|) for
+ * 1 < |z| < 2 -- then scaled by contract_scale and moved to grid->center.
+ * Cells with |z| >= 2 have no preimage and are never read by the march; their
+ * point is placed 1e4 contract_scale out along z.  points float [res^3, 3],
+ * binary32; u float [res^3, 3] in [0, 1) or NULL (cell centres).
+ */
+txs_status txs_grid_points_contracted(const txs_grid* grid, float contract_scale, const float* u,
+                                      float* points, void* stream);
 txs_status txs_grid_ema(int64_t n_cells, float* density, const float* sigma, float gamma,
                         float tau, uint32_t* bits, void* stream);
 

@@ -84,8 +84,11 @@ def clip(o, d, bmin, bmax, near=0.0, far=float("inf")):
 
 
 def march(o, d, bits, res, *, n_levels=1, center=(0.0, 0.0, 0.0), half_extent0=1.5,
-          near=0.0, far=float("inf"), dt0=0.005, max_per_ray=0, want_level=False):
-    """Dense-definition occupancy march.
+          near=0.0, far=float("inf"), dt0=0.005, max_per_ray=0, want_level=False,
+          contract_scale=0.0):
+    """Dense-definition occupancy march.  contract_scale > 0: the occupancy of
+    every sample comes from one res^3 grid over contracted space (the lattice
+    is still that of the n_levels cubes).
 
     Returns dict(packed_info [N,2] int32, t0, t1 float32 [S], ray_id int32 [S],
     counts [N], total, level (optional)).
@@ -93,11 +96,11 @@ def march(o, d, bits, res, *, n_levels=1, center=(0.0, 0.0, 0.0), half_extent0=1
     o, d = _f32(o), _f32(d)
     bits = np.ascontiguousarray(bits, dtype=np.uint32)
     n = o.shape[0]
-    assert bits.size * 32 >= n_levels * res ** 3
+    assert bits.size * 32 >= (1 if contract_scale > 0 else n_levels) * res ** 3
     cen = _f32(center)
     args_head = (C.c_int32(n), _p(o), _p(d), _p(bits), C.c_int32(res), C.c_int32(n_levels),
                  _p(cen), C.c_float(half_extent0), C.c_float(near), C.c_float(far),
-                 C.c_float(dt0), C.c_int32(max_per_ray))
+                 C.c_float(dt0), C.c_int32(max_per_ray), C.c_float(contract_scale))
     counts = np.zeros(n, np.int32)
     L = lib()
     L.oracle_march(*args_head, _p(counts), None, None, None, None, None)
@@ -306,6 +309,15 @@ def grid_points(res, n_levels=1, center=(0.0, 0.0, 0.0), half_extent0=1.5, u=Non
     lib().oracle_grid_points(C.c_int32(res), C.c_int32(n_levels), _p(_f32(center)),
                              C.c_double(half_extent0), _p(None if u is None else _f32(u)),
                              _p(out))
+    return out
+
+
+def grid_points_contracted(res, contract_scale, center=(0.0, 0.0, 0.0), u=None):
+    """One point per cell of a grid over contracted space -> [res^3, 3] (binary64)."""
+    out = np.zeros((res ** 3, 3), np.float64)
+    lib().oracle_grid_points_contracted(C.c_int32(res), _p(_f32(center)),
+                                        C.c_double(contract_scale),
+                                        _p(None if u is None else _f32(u)), _p(out))
     return out
 
 

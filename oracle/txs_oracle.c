@@ -93,7 +93,39 @@ typedef struct {
   float half_extent0;
   float near_plane, far_plane, dt0;
   int32_t max_per_ray; /* 0 = no cap */
+  float inv_scale;     /* > 0: one grid over contracted space, 1/contract_scale */
 } march_cfg;
+
+/* Occupancy in the grid over contracted space: the point, relative to the
+ * centre and divided by the scene scale, is contracted into the ball of
+ * radius 2 (Mip-NeRF 360: unchanged inside the unit ball, radius 2 - 1/|y|
+ * outside), and the bit of its cell in the res^3 grid over [-2, 2]^3 is read.
+ * binary32, one rounding per operation, in the order written. */
+static int occupied_contracted(const march_cfg* c, const float o[3], const float d[3],
+                               float m) {
+  const int res = c->res;
+  float y[3];
+  for (int a = 0; a < 3; ++a) {
+    float x = o[a] + m * d[a];
+    y[a] = (x - c->center[a]) * c->inv_scale;
+  }
+  float r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+  if (r2 > 1.0f) {
+    float r = sqrtf(r2);
+    float q = 1.0f / r;
+    float f = (2.0f - q) * q;
+    for (int a = 0; a < 3; ++a) y[a] = y[a] * f;
+  }
+  const float scale = (float)res * 0.25f;
+  int cell[3];
+  for (int a = 0; a < 3; ++a) {
+    float u = floorf((y[a] + 2.0f) * scale);
+    u = fminf(fmaxf(u, 0.0f), (float)(res - 1));
+    cell[a] = (int)u;
+  }
+  int64_t idx = (int64_t)cell[0] + (int64_t)res * ((int64_t)cell[1] + (int64_t)res * cell[2]);
+  return (int)((c->bits[idx >> 5] >> (idx & 31)) & 1u);
+}
 
 #define LATTICE_LIMIT (1 << 24) /* k stays exactly representable in binary32 */
 
@@ -160,7 +192,8 @@ static int32_t march_one(const march_cfg* c, const float o[3], const float d[3],
     for (int32_t k = 0; k < LATTICE_LIMIT; ++k) {
       float m = a + ((float)k + 0.5f) * dt;
       if (!(m < b)) break;
-      if (!occupied(c, l, o, d, m)) continue;
+      if (c->inv_scale > 0.0f ? !occupied_contracted(c, o, d, m) : !occupied(c, l, o, d, m))
+        continue;
       if (t0) {
         t0[n] = a + (float)k * dt;
         t1[n] = fminf(a + (float)(k + 1) * dt, b);
@@ -178,10 +211,12 @@ static int32_t march_one(const march_cfg* c, const float o[3], const float d[3],
 EXPORT void oracle_march(int32_t n_rays, const float* o, const float* d, const uint32_t* bits,
                          int32_t res, int32_t n_levels, const float* center,
                          float half_extent0, float near_plane, float far_plane, float dt0,
-                         int32_t max_per_ray, int32_t* counts, const int64_t* offsets,
-                         float* t0, float* t1, int32_t* ray_id, int32_t* level) {
+                         int32_t max_per_ray, float contract_scale, int32_t* counts,
+                         const int64_t* offsets, float* t0, float* t1, int32_t* ray_id,
+                         int32_t* level) {
   march_cfg c = {bits, res, n_levels, {center[0], center[1], center[2]}, half_extent0,
-                 near_plane, far_plane, dt0, max_per_ray};
+                 near_plane, far_plane, dt0, max_per_ray,
+                 contract_scale > 0.0f ? 1.0f / contract_scale : 0.0f};
 #pragma omp parallel for schedule(dynamic, 64)
   for (int32_t r = 0; r < n_rays; ++r) {
     if (offsets) {
@@ -492,6 +527,23 @@ EXPORT void oracle_grid_points(int32_t res, int32_t n_levels, const float* cente
         out[3 * c + a] = ((double)center[a] - h) + ((double)idx[a] + ua) * cs;
       }
     }
+  }
+}
+
+/* Cell points of a grid over contracted space: the cell point in [-2, 2]^3
+ * mapped back through the contraction (inverse radius 1 / (2 - r) for
+ * 1 < r < 2), scaled and centred; cells with r >= 2 go 1e4 scale out.      */
+EXPORT void oracle_grid_points_contracted(int32_t res, const float* center, double scale,
+                                          const float* u, double* out) {
+  const int64_t n = (int64_t)res * res * res;
+  const double cs = 4.0 / res;
+  for (int64_t c = 0; c < n; ++c) {
+    const int64_t idx[3] = {c % res, (c / res) % res, c / ((int64_t)res * res)};
+    double z[3];
+    for (int a = 0; a < 3; ++a) z[a] = -2.0 + ((double)idx[a] + (u ? (double)u[3 * c + a] : 0.5)) * cs;
+    const double r = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+    const double f = r <= 1.0 ? 1.0 : (r < 2.0 ? 1.0 / ((2.0 - r) * r) : 1.0e4 / r);
+    for (int a = 0; a < 3; ++a) out[3 * c + a] = (double)center[a] + z[a] * f * scale;
   }
 }
 

@@ -9,11 +9,13 @@ from ._lib import (TXS_EHIP, TXS_EINVAL, TXS_ECAPACITY, TXS_EOVERFLOW, TXS_OK,
                    exported_symbols, load)
 from .ops import (GridSpec, MlpSpec, adam_step, blob_field, compact_rows, disparity_bins,
                   edges_to_intervals,
-                  exclusive_scan, expand_rows, gather_prefix, grid_ema, grid_points, hist_loss,
-                  march_count, march_fill, march_span, merge_edges, mlp_param_count, prop_mlp_bwd,
+                  exclusive_scan, expand_rows, gather_prefix, grid_ema, grid_points,
+                  grid_points_contracted, hist_loss,
+                  march_count, march_count_contracted, march_fill, march_fill_contracted,
+                  march_span, merge_edges, mlp_param_count, prop_mlp_bwd,
                   prop_mlp_fwd, render_bwd, render_fwd, resample, resample_intervals,
                   span_bins, stream_probe, transmittance_prefix, uniform_bins, weights_bwd)
-from .pipeline import (OccupancyGrid, Packed, RenderFn, filter_transmittance, march, pdf_render,
-                       rendering, rendering_dense, sampling)
+from .pipeline import (OccupancyGrid, Packed, RenderFn, filter_transmittance, march,
+                       march_contracted, pdf_render, rendering, rendering_dense, sampling)
 
 __all__ = [n for n in dir() if not n.startswith("_")]

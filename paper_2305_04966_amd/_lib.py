@@ -73,6 +73,9 @@ SIGNATURES = {
     "txs_span_bins": (I32, [I32, P, I32, P, P]),
     "txs_merge_edges": (I32, [I32, I32, P, I32, P, P, P]),
     "txs_disparity_bins": (I32, [GP, F32, F32, P, P, I32, I32, P, P]),
+    "txs_march_count_contracted": (I32, [GP, MP, F32, P, P, I32, P, P]),
+    "txs_march_fill_contracted": (I32, [GP, MP, F32, P, P, I32, P, I64, P, P, P, P]),
+    "txs_grid_points_contracted": (I32, [GP, F32, P, P, P]),
 }
 
 _lock = threading.Lock()

@@ -28,6 +28,31 @@ __global__ __launch_bounds__(256) void grid_points_kernel(int32_t res, int32_t n
   }
 }
 
+// point of every cell of a grid over contracted space: the cell point
+// z = -2 + (index + u) * 4 / res, mapped back through the contraction
+// (|z| <= 1: unchanged; 1 < |z| < 2: radius 1 / (2 - |z|)), scaled and
+// centred.  Cells with |z| >= 2 have no preimage (no sample ever reads them):
+// their point is put kFar scene units out along z.
+constexpr float kFar = 1.0e4f;
+
+__global__ __launch_bounds__(256) void grid_points_contracted_kernel(
+    int32_t res, float cx, float cy, float cz, float scale, const float* __restrict__ u,
+    float* __restrict__ out) {
+  const int64_t n = (int64_t)res * res * res;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int64_t idx[3] = {c % res, (c / res) % res, c / ((int64_t)res * res)};
+  const float cs = 4.0f / (float)res;
+  float z[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) z[a] = -2.0f + ((float)idx[a] + (u ? u[3 * c + a] : 0.5f)) * cs;
+  const float r = sqrtf(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+  const float f = r <= 1.0f ? 1.0f : (r < 2.0f ? 1.0f / ((2.0f - r) * r) : kFar / r);
+  const float ctr[3] = {cx, cy, cz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[3 * c + a] = ctr[a] + z[a] * f * scale;
+}
+
 // D <- gamma D + (1 - gamma) sigma; bit c of the grid = D_c > tau.  One lane
 // per cell; a wave's 64 decisions become two grid words by ballot.
 __global__ __launch_bounds__(256) void grid_ema_kernel(int64_t n, float* __restrict__ density,
@@ -79,4 +104,21 @@ extern "C" txs_status txs_grid_ema(int64_t n_cells, float* density, const float*
   hipLaunchKernelGGL(grid_ema_kernel, dim3(grid_1d(n_cells, 256)), dim3(256), 0,
                      as_stream(stream), n_cells, density, sigma, gamma, tau, bits);
   return launch_status("txs_grid_ema");
+}
+
+extern "C" txs_status txs_grid_points_contracted(const txs_grid* grid, float contract_scale,
+                                                 const float* u, float* points, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(grid, "txs_grid_points_contracted: null grid");
+  const int res = grid->res;
+  TXS_REQUIRE(res >= 2 && res <= 1024 && (res & (res - 1)) == 0,
+              "txs_grid_points_contracted: res must be a power of two in [2,1024], got %d", res);
+  TXS_REQUIRE(contract_scale > 0.0f, "txs_grid_points_contracted: contract_scale must be > 0");
+  TXS_REQUIRE(points, "txs_grid_points_contracted: null points");
+  const int64_t n = (int64_t)res * res * res;
+  hipLaunchKernelGGL(grid_points_contracted_kernel, dim3(grid_1d(n, 256)), dim3(256), 0,
+                     as_stream(stream), res, grid->center[0], grid->center[1], grid->center[2],
+                     contract_scale, u, points);
+  return launch_status("txs_grid_points_contracted");
 }

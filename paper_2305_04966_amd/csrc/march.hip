@@ -30,6 +30,7 @@ struct MarchArgs {
   float half_extent0;
   float near_plane, far_plane, dt0;
   int32_t max_per_ray;
+  float inv_scale;  // contracted lookup: 1 / contract_scale
 };
 
 // Level-l box and grid scale, evaluated exactly as the recipe defines them.
@@ -86,20 +87,50 @@ struct Lattice {
   const uint32_t* bits;
   float a, b, dt, resf;
   int res;
+  float center[3], inv_scale;  // contracted lookup
 };
 
+template <bool kContract>
 __device__ __forceinline__ Lattice lattice(const MarchArgs& g, float a, float b, int l) {
   Lattice p;
   p.box = level_box(g, l);
-  p.bits = g.bits + (int64_t)l * g.level_words;
+  p.bits = kContract ? g.bits : g.bits + (int64_t)l * g.level_words;
   p.a = a;
   p.b = b;
   p.dt = g.dt0 * (float)(1 << l);
   p.res = g.res;
   p.resf = (float)g.res;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p.center[c] = g.center[c];
+  p.inv_scale = g.inv_scale;
   return p;
 }
 
+// Cell of point x in the grid over contracted space: y = (x - center) / scale
+// (times the binary32 reciprocal), y' = y if |y|^2 <= 1, else y (2 - 1/|y|)/|y|
+// (Mip-NeRF 360's contraction, into the ball of radius 2), then the cell of y'
+// in [-2, 2]^3.  Every operation is one binary32 rounding, in this order.
+__device__ __forceinline__ int32_t contracted_cell(const Lattice& p, const float x[3]) {
+  float y[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) y[c] = (x[c] - p.center[c]) * p.inv_scale;
+  const float r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+  if (r2 > 1.0f) {
+    const float r = sqrtf(r2);
+    const float inv_r = 1.0f / r;
+    const float f = (2.0f - inv_r) * inv_r;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c] = y[c] * f;
+  }
+  const float scale = p.resf * 0.25f;
+  int cell[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    cell[c] = (int)__builtin_amdgcn_fmed3f(floorf((y[c] + 2.0f) * scale), 0.0f, p.resf - 1.0f);
+  return cell[0] + p.res * (cell[1] + p.res * cell[2]);
+}
+
+template <bool kContract>
 __device__ __forceinline__ bool probe(const Lattice& p, const float o[3], const float d[3],
                                       int32_t k, uint32_t& word, int32_t& sh) {
   const float m = p.a + ((float)k + 0.5f) * p.dt;
@@ -107,16 +138,24 @@ __device__ __forceinline__ bool probe(const Lattice& p, const float o[3], const 
   word = 0u;
   sh = 0;
   if (valid) {
-    int cell[3];
+    int32_t idx;
+    if (kContract) {
+      float x[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float x = o[c] + m * d[c];
-      const float u = (x - p.box.bmin[c]) * p.box.scale[c];
-      // clamp of the floor to [0, res - 1] as one median-of-three (u is
-      // never NaN here, so it equals min(max(floor(u), 0), res - 1))
-      cell[c] = (int)__builtin_amdgcn_fmed3f(floorf(u), 0.0f, p.resf - 1.0f);
+      for (int c = 0; c < 3; ++c) x[c] = o[c] + m * d[c];
+      idx = contracted_cell(p, x);
+    } else {
+      int cell[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float x = o[c] + m * d[c];
+        const float u = (x - p.box.bmin[c]) * p.box.scale[c];
+        // clamp of the floor to [0, res - 1] as one median-of-three (u is
+        // never NaN here, so it equals min(max(floor(u), 0), res - 1))
+        cell[c] = (int)__builtin_amdgcn_fmed3f(floorf(u), 0.0f, p.resf - 1.0f);
+      }
+      idx = cell[0] + p.res * (cell[1] + p.res * cell[2]);
     }
-    const int32_t idx = cell[0] + p.res * (cell[1] + p.res * cell[2]);
     word = p.bits[idx >> 5];
     sh = idx & 31;
   }
@@ -130,18 +169,19 @@ __device__ __forceinline__ bool probe(const Lattice& p, const float o[3], const 
 // point, records its t0 in em.lo and returns a non-zero count.
 constexpr int kGroups = 2;
 
-template <int kMode>
+template <int kMode, bool kContract>
 __device__ __forceinline__ int32_t march_segment(const MarchArgs& g, const float o[3],
                                                  const float d[3], float a, float b, int l,
                                                  int32_t n, int32_t cap, Emit& em) {
-  const Lattice p = lattice(g, a, b, l);
+  const Lattice p = lattice<kContract>(g, a, b, l);
   const int ln = lane();
   for (int32_t k0 = 0; k0 < kLatticeLimit; k0 += kWave * kGroups) {
     bool valid[kGroups], occ[kGroups];
     uint32_t word[kGroups];
     int32_t sh[kGroups];
 #pragma unroll
-    for (int q = 0; q < kGroups; ++q) valid[q] = probe(p, o, d, k0 + kWave * q + ln, word[q], sh[q]);
+    for (int q = 0; q < kGroups; ++q)
+      valid[q] = probe<kContract>(p, o, d, k0 + kWave * q + ln, word[q], sh[q]);
 #pragma unroll
     for (int q = 0; q < kGroups; ++q) occ[q] = valid[q] && ((word[q] >> sh[q]) & 1u);
 #pragma unroll
@@ -188,9 +228,10 @@ __device__ __forceinline__ int32_t last_lattice_point(float a, float b, float dt
 // Highest occupied lattice point of segment [a, b) on level l, scanning k
 // downwards from the last point kGroups groups of 64 at a time; on success
 // em.hi = the fill pass's binary32 t1 of that sample.
+template <bool kContract>
 __device__ __forceinline__ bool span_back(const MarchArgs& g, const float o[3], const float d[3],
                                           float a, float b, int l, Emit& em) {
-  const Lattice p = lattice(g, a, b, l);
+  const Lattice p = lattice<kContract>(g, a, b, l);
   const int32_t kmax = last_lattice_point(a, b, p.dt);
   const int ln = lane();
   for (int32_t k0 = 0; k0 <= kmax; k0 += kWave * kGroups) {
@@ -199,7 +240,7 @@ __device__ __forceinline__ bool span_back(const MarchArgs& g, const float o[3], 
     int32_t sh[kGroups];
 #pragma unroll
     for (int q = 0; q < kGroups; ++q)
-      occ[q] = probe(p, o, d, kmax - (k0 + kWave * q + ln), word[q], sh[q]);
+      occ[q] = probe<kContract>(p, o, d, kmax - (k0 + kWave * q + ln), word[q], sh[q]);
 #pragma unroll
     for (int q = 0; q < kGroups; ++q) occ[q] = occ[q] && ((word[q] >> sh[q]) & 1u);
 #pragma unroll
@@ -215,7 +256,7 @@ __device__ __forceinline__ bool span_back(const MarchArgs& g, const float o[3], 
   return false;
 }
 
-template <int kMode>
+template <int kMode, bool kContract>
 __device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const float o[3], const float d[3],
                                              Emit& em) {
   float inv[3];
@@ -264,22 +305,22 @@ __device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const float o[3
     // the first occupied point going forward, then the last one going back
     int s_first = -1;
     for (int s = 0; s < 2 * L - 1 && s_first < 0; ++s)
-      if (segment(s, l, a, b) && march_segment<kSpan>(g, o, d, a, b, l, 0, 0, em) > 0)
+      if (segment(s, l, a, b) && march_segment<kSpan, kContract>(g, o, d, a, b, l, 0, 0, em) > 0)
         s_first = s;
     if (s_first < 0) return 0;
     for (int s = 2 * L - 2; s >= s_first; --s)
-      if (segment(s, l, a, b) && span_back(g, o, d, a, b, l, em)) break;
+      if (segment(s, l, a, b) && span_back<kContract>(g, o, d, a, b, l, em)) break;
     return 1;
   }
   for (int s = 0; s < 2 * L - 1; ++s) {
     if (!segment(s, l, a, b)) continue;
-    n = march_segment<kMode>(g, o, d, a, b, l, n, cap, em);
+    n = march_segment<kMode, kContract>(g, o, d, a, b, l, n, cap, em);
     if (cap > 0 && n >= cap) break;
   }
   return n;
 }
 
-template <int kMode>
+template <int kMode, bool kContract>
 __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float* __restrict__ ro,
                                                        const float* __restrict__ rd,
                                                        int32_t n_rays, int32_t* counts,
@@ -298,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float*
   }
   Emit em{t0, t1, ray_id, kMode == kFill ? (int64_t)info[2 * (int64_t)r] : 0, capacity, r,
           0.0f, 0.0f};
-  const int32_t n = march_ray<kMode>(g, o, d, em);
+  const int32_t n = march_ray<kMode, kContract>(g, o, d, em);
   if (kMode == kCount && lane() == 0) counts[r] = n;
   if (kMode == kSpan && lane() == 0) {
     span[2 * (int64_t)r] = em.lo;
@@ -335,6 +376,7 @@ txs_status make_args(const txs_grid* grid, const txs_march_params* p, MarchArgs&
   g.far_plane = p->far_plane;
   g.dt0 = p->dt0;
   g.max_per_ray = p->max_per_ray;
+  g.inv_scale = 0.0f;
   return TXS_OK;
 }
 
@@ -355,7 +397,7 @@ extern "C" txs_status txs_march_count(const txs_grid* grid, const txs_march_para
   TXS_REQUIRE(n_rays >= 0, "txs_march_count: n_rays < 0");
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && counts, "txs_march_count: null array");
-  hipLaunchKernelGGL(march_kernel<kCount>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
+  hipLaunchKernelGGL((march_kernel<kCount, false>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
                      as_stream(stream), g, rays_o, rays_d, n_rays, counts, nullptr, 0, nullptr,
                      nullptr, nullptr, nullptr);
   return launch_status("txs_march_count");
@@ -373,7 +415,7 @@ extern "C" txs_status txs_march_fill(const txs_grid* grid, const txs_march_param
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && packed_info, "txs_march_fill: null array");
   TXS_REQUIRE(capacity == 0 || (t0 && t1), "txs_march_fill: null output");
-  hipLaunchKernelGGL(march_kernel<kFill>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
+  hipLaunchKernelGGL((march_kernel<kFill, false>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
                      as_stream(stream), g, rays_o, rays_d, n_rays, nullptr, packed_info, capacity,
                      t0, t1, ray_id, nullptr);
   return launch_status("txs_march_fill");
@@ -390,8 +432,53 @@ extern "C" txs_status txs_march_span(const txs_grid* grid, const txs_march_param
   TXS_REQUIRE(n_rays >= 0, "txs_march_span: n_rays < 0");
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && span && hit, "txs_march_span: null array");
-  hipLaunchKernelGGL(march_kernel<kSpan>, dim3(march_blocks(n_rays)), dim3(kBlock), 0,
+  hipLaunchKernelGGL((march_kernel<kSpan, false>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
                      as_stream(stream), g, rays_o, rays_d, n_rays, hit, nullptr, 0, nullptr,
                      nullptr, nullptr, span);
   return launch_status("txs_march_span");
+}
+
+extern "C" txs_status txs_march_count_contracted(const txs_grid* grid,
+                                                 const txs_march_params* params,
+                                                 float contract_scale, const float* rays_o,
+                                                 const float* rays_d, int32_t n_rays,
+                                                 int32_t* counts, void* stream) {
+  using namespace txs;
+  clear_error();
+  MarchArgs g;
+  if (txs_status s = make_args(grid, params, g)) return s;
+  TXS_REQUIRE(std::isfinite(contract_scale) && contract_scale > 0.0f,
+              "txs_march_count_contracted: contract_scale must be finite and > 0");
+  g.inv_scale = 1.0f / contract_scale;
+  TXS_REQUIRE(n_rays >= 0, "txs_march_count_contracted: n_rays < 0");
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(rays_o && rays_d && counts, "txs_march_count_contracted: null array");
+  hipLaunchKernelGGL((march_kernel<kCount, true>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
+                     as_stream(stream), g, rays_o, rays_d, n_rays, counts, nullptr, 0, nullptr,
+                     nullptr, nullptr, nullptr);
+  return launch_status("txs_march_count_contracted");
+}
+
+extern "C" txs_status txs_march_fill_contracted(const txs_grid* grid,
+                                                const txs_march_params* params,
+                                                float contract_scale, const float* rays_o,
+                                                const float* rays_d, int32_t n_rays,
+                                                const int32_t* packed_info, int64_t capacity,
+                                                float* t0, float* t1, int32_t* ray_id,
+                                                void* stream) {
+  using namespace txs;
+  clear_error();
+  MarchArgs g;
+  if (txs_status s = make_args(grid, params, g)) return s;
+  TXS_REQUIRE(std::isfinite(contract_scale) && contract_scale > 0.0f,
+              "txs_march_fill_contracted: contract_scale must be finite and > 0");
+  g.inv_scale = 1.0f / contract_scale;
+  TXS_REQUIRE(n_rays >= 0 && capacity >= 0, "txs_march_fill_contracted: negative size");
+  if (n_rays == 0) return TXS_OK;
+  TXS_REQUIRE(rays_o && rays_d && packed_info, "txs_march_fill_contracted: null array");
+  TXS_REQUIRE(capacity == 0 || (t0 && t1), "txs_march_fill_contracted: null output");
+  hipLaunchKernelGGL((march_kernel<kFill, true>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
+                     as_stream(stream), g, rays_o, rays_d, n_rays, nullptr, packed_info, capacity,
+                     t0, t1, ray_id, nullptr);
+  return launch_status("txs_march_fill_contracted");
 }

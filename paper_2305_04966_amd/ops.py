@@ -16,7 +16,8 @@ from ._lib import TXS_PDF_SIGMA, TXS_PDF_SIGMA_EXP, TXS_PDF_WEIGHTS, Grid, March
 __all__ = ["GridSpec", "march_count", "exclusive_scan", "march_fill", "transmittance_prefix",
            "gather_prefix", "render_fwd", "render_bwd", "weights_bwd", "resample",
            "uniform_bins", "edges_to_intervals", "resample_intervals", "blob_field",
-           "march_span", "compact_rows", "expand_rows", "span_bins", "merge_edges", "disparity_bins",
+           "march_span", "compact_rows", "expand_rows", "span_bins", "merge_edges", "disparity_bins", "march_count_contracted",
+           "march_fill_contracted", "grid_points_contracted",
            "TXS_PDF_SIGMA",
            "TXS_PDF_WEIGHTS", "TXS_PDF_SIGMA_EXP"]
 
@@ -56,11 +57,20 @@ class GridSpec:
     center: tuple = (0.0, 0.0, 0.0)
     half_extent0: float = 1.5
 
+    def struct_contracted(self) -> Grid:
+        """The descriptor of a grid over contracted space (one res^3 level of bits)."""
+        _need(self.bits, "grid.bits", torch.int32)
+        if self.bits.numel() * 32 < self.res ** 3:
+            raise ValueError("grid.bits holds fewer than res^3 bits")
+        return self._fill(Grid())
+
     def struct(self) -> Grid:
         _need(self.bits, "grid.bits", torch.int32)
         if self.bits.numel() * 32 < self.n_levels * self.res ** 3:
             raise ValueError("grid.bits holds fewer than n_levels*res^3 bits")
-        g = Grid()
+        return self._fill(Grid())
+
+    def _fill(self, g: Grid) -> Grid:
         g.bits = self.bits.data_ptr()
         g.res = self.res
         g.n_levels = self.n_levels
@@ -124,6 +134,35 @@ def march_fill(grid: GridSpec, rays_o, rays_d, packed_info, n_samples, *, near=0
     check(load().txs_march_fill(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d), n,
                                 _ptr(packed_info), n_samples, _ptr(t0), _ptr(t1), _ptr(rid),
                                 _stream()), "txs_march_fill")
+    return t0, t1, rid
+
+
+def march_count_contracted(grid: GridSpec, rays_o, rays_d, contract_scale, *, near=0.0,
+                           far=float("inf"), dt0, max_per_ray=0):
+    """Counts of the lattice march with occupancy from a grid over contracted space."""
+    n = _rays(rays_o, rays_d)
+    counts = torch.empty(n, dtype=torch.int32, device=rays_o.device)
+    g, p = grid.struct_contracted(), _params(near, far, dt0, max_per_ray)
+    check(load().txs_march_count_contracted(C.byref(g), C.byref(p), float(contract_scale),
+                                            _ptr(rays_o), _ptr(rays_d), n, _ptr(counts),
+                                            _stream()), "txs_march_count_contracted")
+    return counts
+
+
+def march_fill_contracted(grid: GridSpec, rays_o, rays_d, contract_scale, packed_info,
+                          n_samples, *, near=0.0, far=float("inf"), dt0, max_per_ray=0,
+                          want_ray_id=True):
+    n = _rays(rays_o, rays_d)
+    _need(packed_info, "packed_info", torch.int32, (n, 2))
+    dev = rays_o.device
+    t0 = torch.empty(n_samples, dtype=torch.float32, device=dev)
+    t1 = torch.empty(n_samples, dtype=torch.float32, device=dev)
+    rid = torch.empty(n_samples, dtype=torch.int32, device=dev) if want_ray_id else None
+    g, p = grid.struct_contracted(), _params(near, far, dt0, max_per_ray)
+    check(load().txs_march_fill_contracted(C.byref(g), C.byref(p), float(contract_scale),
+                                           _ptr(rays_o), _ptr(rays_d), n, _ptr(packed_info),
+                                           n_samples, _ptr(t0), _ptr(t1), _ptr(rid), _stream()),
+          "txs_march_fill_contracted")
     return t0, t1, rid
 
 
@@ -410,6 +449,17 @@ def grid_points(grid: GridSpec, u=None):
     _opt(u, "u", torch.float32, (n, 3))
     out = torch.empty((n, 3), dtype=torch.float32, device=grid.bits.device)
     check(load().txs_grid_points(C.byref(g), _ptr(u), _ptr(out), _stream()), "txs_grid_points")
+    return out
+
+
+def grid_points_contracted(grid: GridSpec, contract_scale, u=None):
+    """One point per cell of a grid over contracted space -> [res^3, 3]."""
+    n = grid.res ** 3
+    g = grid.struct_contracted()
+    _opt(u, "u", torch.float32, (n, 3))
+    out = torch.empty((n, 3), dtype=torch.float32, device=grid.bits.device)
+    check(load().txs_grid_points_contracted(C.byref(g), float(contract_scale), _ptr(u), _ptr(out),
+                                            _stream()), "txs_grid_points_contracted")
     return out
 
 

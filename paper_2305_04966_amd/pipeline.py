@@ -52,6 +52,19 @@ def march(grid: ops.GridSpec, rays_o, rays_d, *, dt0, near=0.0, far=float("inf")
     return Packed(info, t0, t1, rid)
 
 
+def march_contracted(grid: ops.GridSpec, rays_o, rays_d, contract_scale, *, dt0, near=0.0,
+                     far=float("inf"), max_per_ray=0) -> Packed:
+    """The lattice march with occupancy from a grid over contracted space."""
+    counts = ops.march_count_contracted(grid, rays_o, rays_d, contract_scale, near=near,
+                                        far=far, dt0=dt0, max_per_ray=max_per_ray)
+    info, total = ops.exclusive_scan(counts)
+    s = _host_total(total)
+    t0, t1, rid = ops.march_fill_contracted(grid, rays_o, rays_d, contract_scale, info, s,
+                                            near=near, far=far, dt0=dt0,
+                                            max_per_ray=max_per_ray)
+    return Packed(info, t0, t1, rid)
+
+
 def filter_transmittance(p: Packed, sigma, t_min=1e-4) -> Packed:
     """No-gradient filtering: keep each ray's prefix with T >= t_min."""
     kept = ops.transmittance_prefix(p.packed_info, p.t0, p.t1, sigma, t_min)
@@ -145,16 +158,26 @@ class OccupancyGrid:
     it in (Section 3.1, Spatial Skipping; Table 1, occupancy-grid row).
     """
 
-    def __init__(self, grid: ops.GridSpec, density: Optional[torch.Tensor] = None):
-        n = grid.n_levels * grid.res ** 3
+    def __init__(self, grid: ops.GridSpec, density: Optional[torch.Tensor] = None,
+                 contract_scale: Optional[float] = None):
+        """contract_scale: the grid is one res^3 level over contracted space (read
+        by march_contracted) instead of the cascade of cubes."""
+        n = (1 if contract_scale else grid.n_levels) * grid.res ** 3
         self.grid = grid
+        self.contract_scale = contract_scale
         self.density = (density if density is not None else
                         torch.zeros(n, dtype=torch.float32, device=grid.bits.device))
 
+    def points(self, u=None):
+        """The cell points the update evaluates the field at."""
+        if self.contract_scale:
+            return ops.grid_points_contracted(self.grid, self.contract_scale, u)
+        return ops.grid_points(self.grid, u)
+
     def update(self, density_fn: Callable, gamma=0.95, tau=0.01, u=None):
-        pts = ops.grid_points(self.grid, u)
-        sigma = density_fn(pts)
-        ops.grid_ema(self.density, sigma, gamma, tau, self.grid.bits)
+        sigma = density_fn(self.points(u))
+        n = self.density.shape[0]
+        ops.grid_ema(self.density, sigma, gamma, tau, self.grid.bits[:n // 32])
 
     def update_every_n_steps(self, step, density_fn: Callable, n=16, gamma=0.95, tau=0.01,
                              u=None):

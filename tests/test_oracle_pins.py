@@ -764,3 +764,85 @@ def test_disparity_bins_closed_form():
     assert np.all(np.diff(1.0 / e[1]) < 0) and np.allclose(np.diff(np.diff(1.0 / e[1])), 0)
     # a ray that misses: every edge at the near plane
     assert np.allclose(e[2], np.float32(0.05), rtol=0, atol=0)
+
+
+# ----------------------------------------------------------------------------
+# grid over contracted space
+# ----------------------------------------------------------------------------
+def contract64(x, scale):
+    """Mip-NeRF 360's contraction of x / scale, binary64 (independent of the oracle)."""
+    y = np.asarray(x, np.float64) / scale
+    r = np.linalg.norm(y, axis=-1, keepdims=True)
+    return np.where(r <= 1.0, y, (2.0 - 1.0 / np.maximum(r, 1e-300)) * y / np.maximum(r, 1e-300))
+
+
+def test_contracted_march_along_an_axis_closed_form():
+    # ray from the centre along +x; res 8 over [-2, 2]^3: x-cell 7 holds
+    # contracted radii [1.5, 2), i.e. distances t >= 2 scale (2 - 1/t = 1.5)
+    res, scale, dt = 8, 1.0, 0.01
+    occ = np.zeros(res ** 3, bool)
+    occ[7 + res * (4 + res * 4)] = True
+    o = np.float32([[0.0, 0.01, 0.01]])
+    d = np.float32([[1.0, 0.0, 0.0]])
+    kw = dict(n_levels=3, half_extent0=1.5, dt0=dt)
+    m = oracle.march(o, d, scenes.pack_bits(occ), res, contract_scale=scale, **kw)
+    full = oracle.march(o, d, scenes.pack_bits(np.ones(res ** 3, bool)), res, contract_scale=scale,
+                        **kw)
+    mid = 0.5 * (full["t0"].astype(np.float64) + full["t1"])
+    mk = 0.5 * (m["t0"].astype(np.float64) + m["t1"])
+    assert m["total"] > 0 and np.all(mk >= 2.0 - 1e-5)
+    assert np.isin(mid[mid >= 2.0 + 1e-5], mk).all()
+
+
+def test_contracted_march_full_grid_is_the_cascade_lattice():
+    res = 8
+    o, d = scenes.sphere_rays(200, radius=3.0, target_half=0.5, seed=44)
+    kw = dict(n_levels=3, half_extent0=1.5, dt0=0.02)
+    full = np.ones(res ** 3, bool)
+    c = oracle.march(o, d, scenes.pack_bits(full), res, contract_scale=1.5, **kw)
+    q = oracle.march(o, d, np.concatenate([scenes.pack_bits(full)] * 3), res, **kw)
+    for k in ("counts", "t0", "t1"):
+        assert np.array_equal(c[k], q[k])
+    e = oracle.march(o, d, scenes.pack_bits(np.zeros(res ** 3, bool)), res, contract_scale=1.5,
+                     **kw)
+    assert e["total"] == 0
+
+
+def test_contracted_march_selects_the_samples_in_occupied_cells():
+    # random cells of a 16^3 contracted grid: a sample is kept iff its midpoint,
+    # contracted in binary64, lies in an occupied cell (up to 1e-5 of a face)
+    res, scale = 16, 1.5
+    g = scenes.rng(45)
+    occ = g.random(res ** 3) < 0.3
+    o, d = scenes.sphere_rays(300, radius=3.0, target_half=1.0, seed=46)
+    kw = dict(n_levels=4, half_extent0=1.5, dt0=0.03, contract_scale=scale)
+    full = oracle.march(o, d, scenes.pack_bits(np.ones(res ** 3, bool)), res, want_level=True,
+                        **kw)
+    kept = oracle.march(o, d, scenes.pack_bits(occ), res, **kw)
+    rid = full["ray_id"]
+    # the lattice midpoint t0 + dt_l / 2 (the last interval of a segment is cut
+    # at the segment end, so (t0 + t1) / 2 is not its test point)
+    tm = full["t0"].astype(np.float64) + 0.5 * 0.03 * 2.0 ** full["level"]
+    x = o[rid].astype(np.float64) + tm[:, None] * d[rid].astype(np.float64)
+    u = (contract64(x, scale) + 2.0) * (res / 4.0)
+    cell = np.clip(np.floor(u), 0, res - 1).astype(np.int64)
+    near_face = (np.abs(u - np.round(u)) < 1e-4).any(axis=1)
+    want = occ[cell[:, 0] + res * (cell[:, 1] + res * cell[:, 2])]
+    key = lambda r, t: r.astype(np.int64) * (1 << 40) + np.round(t * 1e6).astype(np.int64)
+    got = np.isin(key(rid, full["t0"]), key(kept["ray_id"], kept["t0"]))
+    assert kept["total"] > 100
+    assert np.array_equal(got[~near_face], want[~near_face])
+
+
+def test_contracted_cell_points_map_back_into_their_cells():
+    res, scale = 16, 1.5
+    u = scenes.rng(47).random((res ** 3, 3)).astype(np.float32) * np.float32(0.98) + np.float32(0.01)
+    for uu in (None, u):
+        p = oracle.grid_points_contracted(res, scale, center=(0.25, -0.125, 0.375), u=uu)
+        idx = np.arange(res ** 3)
+        cell = np.stack([idx % res, (idx // res) % res, idx // (res * res)], 1)
+        zc = -2.0 + (cell + (0.5 if uu is None else uu.astype(np.float64))) * (4.0 / res)
+        inside = np.linalg.norm(zc, axis=1) < 2.0 - 1e-9
+        back = contract64(p - np.array([0.25, -0.125, 0.375]), scale)
+        assert np.allclose(back[inside], zc[inside], rtol=0, atol=1e-9)
+        assert np.all(np.linalg.norm(p[~inside], axis=1) > 1e3)
