@@ -27,13 +27,29 @@ __global__ __launch_bounds__(kFieldBlock) void blob_field_kernel(
   // exp(-r2/(2w^2)) = exp2(-r2 * log2(e)/(2 w^2))
   const float k2 = 1.4426950408889634f / (2.0f * wd * wd);
   const float* cen = p + 32;
+  // Blobs in order, four centres per group of (wave-uniform) loads.  The
+  // hardware exp2 has no subnormal results, so each factor is taken as
+  // 2^(y + 32) and the sum scaled by 2^-32 at the end: factors down to 2^-158
+  // stay normal until that final (exact or once-rounded) scaling, as with a
+  // subnormal-preserving exp2.  Rounding the offset exponent costs at most
+  // 2^-20 absolute, 7e-7 relative in each factor.
   float sb = 0.0f;
-  for (int b = 0; b < nb; ++b) {
-    const float dx = x[0] - cen[3 * b], dy = x[1] - cen[3 * b + 1], dz = x[2] - cen[3 * b + 2];
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    sb += exp2f(-r2 * k2);
+  int b = 0;
+  for (; b + 4 <= nb; b += 4) {
+    float c[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c[k] = cen[3 * b + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float dx = x[0] - c[3 * k], dy = x[1] - c[3 * k + 1], dz = x[2] - c[3 * k + 2];
+      sb += __builtin_amdgcn_exp2f(fmaf(-(dx * dx + dy * dy + dz * dz), k2, 32.0f));
+    }
   }
-  sb *= peak;
+  for (; b < nb; ++b) {
+    const float dx = x[0] - cen[3 * b], dy = x[1] - cen[3 * b + 1], dz = x[2] - cen[3 * b + 2];
+    sb += __builtin_amdgcn_exp2f(fmaf(-(dx * dx + dy * dy + dz * dz), k2, 32.0f));
+  }
+  sb = (sb * peak) * 0x1p-32f;
   float ss = 0.0f;
   const float nrm = sqrtf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
   if (p[3] != 0.0f) {
