@@ -60,10 +60,13 @@ struct Args {
   float* d_rgb;
 };
 
-// Per-wave LDS: boundary marks of the current window, per-ray cotangents and
-// total optical depths (adjoint).
-struct WaveLds {
+// Per-wave LDS: boundary marks of the current window (every kernel), and for
+// the adjoint the per-ray cotangents and total optical depths.  The forward
+// kernels hold the marks alone (33 KB per block with the colour staging).
+struct MarkLds {
   int marks[kMarks];
+};
+struct WaveLds : MarkLds {
   float cot[kWave][8];  // g_rgb(3), h, q, bg(3) of each owned ray
   double ptot[kWave];
 };
@@ -343,7 +346,7 @@ __device__ __forceinline__ void store_k(float* __restrict__ dst, int64_t pos0, c
 // ----------------------------------------------------------- window marks
 // Marks, for window start p, the first sample (lane+1) and the end (-1) of
 // every ray in the set that falls in window positions [0, W].
-__device__ __forceinline__ void write_marks(WaveLds& L, int64_t p, int64_t st, int64_t en,
+__device__ __forceinline__ void write_marks(MarkLds& L, int64_t p, int64_t st, int64_t en,
                                             bool in_set) {
   const int ln = lane();
 #pragma unroll
@@ -356,7 +359,7 @@ __device__ __forceinline__ void write_marks(WaveLds& L, int64_t p, int64_t st, i
   wave_sync();
 }
 
-__device__ __forceinline__ void read_marks(const WaveLds& L, int (&mk)[K + 1]) {
+__device__ __forceinline__ void read_marks(const MarkLds& L, int (&mk)[K + 1]) {
   const int base = K * lane();
 #pragma unroll
   for (int j = 0; j <= K; ++j) mk[j] = L.marks[base + j];

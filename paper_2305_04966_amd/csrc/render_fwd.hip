@@ -7,9 +7,9 @@ namespace {
 
 template <int kMode>
 __global__ __launch_bounds__(kBlock) void fwd_kernel(Args a) {
-  __shared__ WaveLds lds[kWaves];
+  __shared__ MarkLds lds[kWaves];
   __shared__ float4 stage_mem[kWaves][StageSize<kMode>::value];
-  WaveLds& L = lds[threadIdx.x / kWave];
+  MarkLds& L = lds[threadIdx.x / kWave];
   float4* stage = stage_mem[threadIdx.x / kWave];
   const int64_t wave = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
   const int32_t r0 = (int32_t)(wave * kWave);

@@ -36,8 +36,8 @@ __device__ __forceinline__ void emit_ray(const Args& a, int32_t r, const Acc5& s
 
 // One window of the forward direction: samples [p, p+W) clipped to lim, the
 // window's marks already in LDS, cin the state entering the window.
-template <int kMode>
-__device__ FwdCarry fwd_window(const Args& a, WaveLds& L, float4* stage, int32_t r0, int64_t p,
+template <int kMode, class Lds>
+__device__ FwdCarry fwd_window(const Args& a, Lds& L, float4* stage, int32_t r0, int64_t p,
                                int64_t lim, const FwdCarry& cin) {
   const int ln = lane();
   const int64_t pos0 = p + (int64_t)K * ln;
@@ -69,7 +69,17 @@ __device__ FwdCarry fwd_window(const Args& a, WaveLds& L, float4* stage, int32_t
   const int cp = lane_prev(max_scan_incl(lastm), -1);
   int cur = (cp >= 0) ? decode_mark(L.marks[cp]) : cin.seg;
 
-  // pass 2: transmittance, weights, per-ray sums
+  // pass 2: transmittance, weights, per-ray sums.  Inside the lane the
+  // optical depth of sample j is P_s + loc_j: P_s (binary64) where the lane's
+  // current segment starts, loc_j (binary32) the sum of the segment's taus in
+  // this lane before j, at most K of them.  The transmittance takes
+  // fl(fl(P_s) + loc_j): at most K + 2 binary32 roundings, each < 2^-24 P, and
+  // one more in the scaling by log2(e), so T is within (K + 3) 2^-24 P
+  // relative besides the exp2's own rounding (6.6e-7 P for K = 8), which the
+  // weights' relative bar admits wherever T is not negligible.  The per-ray
+  // totals (the adjoint subtracts suffix sums from them) and the filter's
+  // decisions keep the binary64 sum P per sample.
+  float Psf = (float)P, loc = 0.0f;
   Acc5 acc = (ln == 0) ? cin.acc : Acc5{0.f, 0.f, 0.f, 0.f, 0.f};
   int cnt = (ln == 0) ? cin.cnt : 0;
   bool first = true;
@@ -92,6 +102,8 @@ __device__ FwdCarry fwd_window(const Args& a, WaveLds& L, float4* stage, int32_t
     if (mk[j] != 0) {
       cur = decode_mark(mk[j]);
       P = 0.0;
+      Psf = 0.0f;
+      loc = 0.0f;
       acc = Acc5{0.f, 0.f, 0.f, 0.f, 0.f};
       cnt = 0;
       first = false;
@@ -99,7 +111,7 @@ __device__ FwdCarry fwd_window(const Args& a, WaveLds& L, float4* stage, int32_t
     const bool live = cur >= 0 && (pos0 + j) < lim;
     own[j] = live;
     if (kMode == kFwd) {
-      const float T = exp_neg(P);
+      const float T = __builtin_amdgcn_exp2f((Psf + loc) * -1.44269504f);
       const float alpha = one_minus_exp_neg(tau[j]);
       const float w = live ? T * alpha : 0.0f;
       wv[j] = w;
@@ -113,9 +125,10 @@ __device__ FwdCarry fwd_window(const Args& a, WaveLds& L, float4* stage, int32_t
       if (live && P <= a.p_max) ++cnt;
     }
     P += (double)tau[j];
+    loc += tau[j];
     if (mk[j + 1] != 0 && cur >= 0) {  // last sample of ray `cur`
       if (kMode == kFwd && a.out_optical) a.out_optical[r0 + cur] = P;
-      if (kMode == kTotal) L.ptot[cur] = P;
+      if constexpr (kMode == kTotal) L.ptot[cur] = P;
       if (first) {
         first_acc = acc;
         first_cnt = cnt;

@@ -92,20 +92,24 @@ __global__ __launch_bounds__(kScanBlock) void write_packed(const int32_t* __rest
 // with all lanes (contiguous loads and stores).
 constexpr int kGatherWaves = 4;
 
-// The wave's 64 rays are copied as one walk over their output positions, 64
-// consecutive positions per chunk (one per lane), kGatherUnroll chunks per
-// step: stores are contiguous and coalesced, loads contiguous within a ray.
-// A chunk that lies inside the ray carried from the previous chunk (the
-// common case: rays are hundreds of samples long) takes a wave-uniform fast
-// path; otherwise each lane finds the ray of its position from the ray starts
-// that fall in the chunk (marked in LDS, inclusive max scan over lanes).
-constexpr int kGatherUnroll = 4;
+// The wave's 64 rays are copied as one walk over their output positions in
+// steps of kGatherSpan (kGatherUnroll chunks of 64 consecutive positions, one
+// per lane): stores are contiguous and coalesced, loads contiguous within a
+// ray, and the loads of a step's chunks are in flight together.  A step that
+// lies inside the ray carried from the previous step (rays are hundreds of
+// samples long) takes a wave-uniform path; otherwise each lane finds the ray
+// of each of its positions from the ray starts that fall in the step (marked
+// in LDS; inclusive max scan over lanes per chunk, the ray of a chunk's last
+// position carried into the next chunk).  Rows are in ray-major order, so a
+// later start belongs to a higher lane and the max is the latest ray started.
+constexpr int kGatherUnroll = 8;
+constexpr int kGatherSpan = kWave * kGatherUnroll;
 
 __global__ __launch_bounds__(kWave* kGatherWaves) void gather_prefix_kernel(
     const int32_t* __restrict__ info_in, const int32_t* __restrict__ info_out, int32_t n_rays,
     int64_t n_in, const float* __restrict__ t0, const float* __restrict__ t1, int64_t capacity,
     float* __restrict__ t0o, float* __restrict__ t1o, int32_t* __restrict__ rido) {
-  __shared__ int marks[kGatherWaves][kWave];
+  __shared__ int marks[kGatherWaves][kGatherSpan];
   const int ln = lane(), wv = threadIdx.x / kWave;
   const int64_t r0 = ((int64_t)blockIdx.x * kGatherWaves + wv) * kWave;
   if (r0 >= n_rays) return;
@@ -126,15 +130,14 @@ __global__ __launch_bounds__(kWave* kGatherWaves) void gather_prefix_kernel(
   const int64_t lo = wave_min(cnt > 0 ? (int64_t)so : INT64_MAX);
   if (lo == INT64_MAX) return;
   const int64_t hi = wave_max(cnt > 0 ? (int64_t)so + cnt : INT64_MIN);
-  // ray carried into the next chunk (lane index, -1 none) and its row, uniform
+  // ray carried into the next step (lane index, -1 none) and its row, uniform
   int cur = -1;
   int64_t c_so = 0, c_si = 0, c_end = 0;  // c_end = c_so + count
   int64_t base = lo;
   while (base < hi) {
     if (cur >= 0 && c_end > base) {
-      // positions [base, end) all belong to the carried ray (wave-uniform
-      // branch): up to kGatherUnroll chunks with their loads in flight together
-      const int64_t end = min(min(c_end, hi), base + (int64_t)kWave * kGatherUnroll);
+      // positions [base, end) all belong to the carried ray (wave-uniform)
+      const int64_t end = min(min(c_end, hi), base + (int64_t)kGatherSpan);
       float v0[kGatherUnroll], v1[kGatherUnroll];
 #pragma unroll
       for (int u = 0; u < kGatherUnroll; ++u) {
@@ -157,35 +160,57 @@ __global__ __launch_bounds__(kWave* kGatherWaves) void gather_prefix_kernel(
       base = end;
       continue;
     }
-    // a chunk where rays start (or a gap): ray of each position by lane scan
-    const int64_t p = base + ln;
-    marks[wv][ln] = -1;
+    // a step where rays start (or a gap): ray of each position by lane scans
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) marks[wv][kWave * u + ln] = -1;
     wave_sync();
     {
       const int64_t d = (int64_t)so - base;
-      if (cnt > 0 && d >= 0 && d < kWave) marks[wv][d] = ln;
+      if (cnt > 0 && d >= 0 && d < kGatherSpan) marks[wv][d] = ln;
     }
     wave_sync();
-    int m = max_scan_incl(marks[wv][ln]);
-    if (m < 0) m = cur;
-    const int q = m < 0 ? 0 : m;
-    const int32_t so_r = __shfl(so, q, kWave), si_r = __shfl(si, q, kWave),
-                  c_r = __shfl(cnt, q, kWave);
-    if (m >= 0 && p < (int64_t)so_r + c_r) {
-      const int64_t src = (int64_t)si_r + (p - so_r);
-      t0o[p] = t0[src];
-      t1o[p] = t1[src];
-      if (rido) rido[p] = (int32_t)(r0 + m);
+    int m[kGatherUnroll];
+    int carry = cur;
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      int mu = max_scan_incl(marks[wv][kWave * u + ln]);
+      if (mu < 0) mu = carry;
+      m[u] = mu;
+      carry = readlane(mu, kWave - 1);
     }
-    // carry the ray of the chunk's last position
-    cur = readlane(m, kWave - 1);
+    float v0[kGatherUnroll], v1[kGatherUnroll];
+    bool ok[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const int q = m[u] < 0 ? 0 : m[u];
+      const int32_t so_r = __shfl(so, q, kWave), si_r = __shfl(si, q, kWave),
+                    c_r = __shfl(cnt, q, kWave);
+      const int64_t p = base + (int64_t)kWave * u + ln;
+      ok[u] = m[u] >= 0 && p < (int64_t)so_r + c_r;
+      if (ok[u]) {
+        const int64_t src = (int64_t)si_r + (p - so_r);
+        v0[u] = t0[src];
+        v1[u] = t1[src];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const int64_t p = base + (int64_t)kWave * u + ln;
+      if (ok[u]) {
+        t0o[p] = v0[u];
+        t1o[p] = v1[u];
+        if (rido) rido[p] = (int32_t)(r0 + m[u]);
+      }
+    }
+    // carry the ray of the step's last position
+    cur = carry;
     if (cur >= 0) {
       c_so = readlane(so, cur);
       c_si = readlane(si, cur);
       c_end = c_so + readlane(cnt, cur);
     }
     wave_sync();
-    base += kWave;
+    base += kGatherSpan;
   }
 }
 

@@ -184,6 +184,31 @@ def test_filter_and_gather(gpu_lib, tiny):
     assert np.array_equal(host(rido), r_rid)
 
 
+@pytest.mark.parametrize("case", ["short", "mixed", "long"])
+def test_gather_random_rows(gpu_lib, case):
+    """Repack of random ragged rows, exact: kept prefixes of 0..count samples,
+    empty rows, rows far shorter and far longer than the kernel's 512-position
+    steps, with and without the ray index output."""
+    seed, n, cmax = {"short": (70, 5000, 6), "mixed": (71, 3000, 400),
+                     "long": (72, 300, 3000)}[case]
+    g = scenes.rng(seed)
+    counts = g.integers(0, cmax + 1, n).astype(np.int32)
+    counts[g.random(n) < 0.25] = 0
+    kept = np.minimum(counts, g.integers(0, cmax + 1, n)).astype(np.int32)
+    info, S = oracle.exclusive_scan(counts)
+    t0, t1 = g.random(S, dtype=np.float32), g.random(S, dtype=np.float32)
+    rid = np.repeat(np.arange(n), counts).astype(np.int32)
+    info2, total2 = gpu_lib.exclusive_scan(dev(kept))
+    s2 = int(total2.item())
+    r_info, r_t0, r_t1, r_rid = oracle.gather_prefix(info, kept, t0, t1, rid)
+    assert s2 == len(r_t0)
+    a, b, c = gpu_lib.gather_prefix(dev(info), info2, s2, dev(t0), dev(t1))
+    assert np.array_equal(host(a), r_t0) and np.array_equal(host(b), r_t1)
+    assert np.array_equal(host(c), r_rid)
+    a, b, c = gpu_lib.gather_prefix(dev(info), info2, s2, dev(t0), dev(t1), want_ray_id=False)
+    assert c is None and np.array_equal(host(a), r_t0) and np.array_equal(host(b), r_t1)
+
+
 def test_filter_thresholds(gpu_lib):
     # constant-density rays: kept = #{i : i sigma Delta <= ln(1e4)}
     counts = np.array([400, 400, 400, 5, 1, 0], np.int32)
