@@ -24,15 +24,17 @@ __global__ __launch_bounds__(kFieldBlock) void blob_field_kernel(
 #pragma unroll
   for (int a = 0; a < 3; ++a) x[a] = ro[3 * r + a] + tm * rd[3 * r + a];
   const float peak = p[1], wd = p[2];
-  // exp(-r2/(2w^2)) = exp2(-r2 * log2(e)/(2 w^2))
+  // exp(-r2/(2w^2)) = exp2(-r2 k2), k2 = log2(e)/(2w^2); with s = sqrt(k2) the
+  // exponent is -|x s - c s|^2, each difference one fused x s - c s
   const float k2 = 1.4426950408889634f / (2.0f * wd * wd);
+  const float sk = sqrtf(k2);
+  const float xs[3] = {x[0] * sk, x[1] * sk, x[2] * sk};
   const float* cen = p + 32;
   // Blobs in order, four centres per group of (wave-uniform) loads.  The
   // hardware exp2 has no subnormal results, so each factor is taken as
   // 2^(y + 32) and the sum scaled by 2^-32 at the end: factors down to 2^-158
   // stay normal until that final (exact or once-rounded) scaling, as with a
-  // subnormal-preserving exp2.  Rounding the offset exponent costs at most
-  // 2^-20 absolute, 7e-7 relative in each factor.
+  // subnormal-preserving exp2.
   float sb = 0.0f;
   int b = 0;
   for (; b + 4 <= nb; b += 4) {
@@ -41,13 +43,15 @@ __global__ __launch_bounds__(kFieldBlock) void blob_field_kernel(
     for (int k = 0; k < 12; ++k) c[k] = cen[3 * b + k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const float dx = x[0] - c[3 * k], dy = x[1] - c[3 * k + 1], dz = x[2] - c[3 * k + 2];
-      sb += __builtin_amdgcn_exp2f(fmaf(-(dx * dx + dy * dy + dz * dz), k2, 32.0f));
+      const float dx = fmaf(-c[3 * k], sk, xs[0]), dy = fmaf(-c[3 * k + 1], sk, xs[1]),
+                  dz = fmaf(-c[3 * k + 2], sk, xs[2]);
+      sb += __builtin_amdgcn_exp2f(fmaf(-dz, dz, fmaf(-dy, dy, fmaf(-dx, dx, 32.0f))));
     }
   }
   for (; b < nb; ++b) {
-    const float dx = x[0] - cen[3 * b], dy = x[1] - cen[3 * b + 1], dz = x[2] - cen[3 * b + 2];
-    sb += __builtin_amdgcn_exp2f(fmaf(-(dx * dx + dy * dy + dz * dz), k2, 32.0f));
+    const float dx = fmaf(-cen[3 * b], sk, xs[0]), dy = fmaf(-cen[3 * b + 1], sk, xs[1]),
+                dz = fmaf(-cen[3 * b + 2], sk, xs[2]);
+    sb += __builtin_amdgcn_exp2f(fmaf(-dz, dz, fmaf(-dy, dy, fmaf(-dx, dx, 32.0f))));
   }
   sb = (sb * peak) * 0x1p-32f;
   float ss = 0.0f;
