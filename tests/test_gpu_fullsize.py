@@ -3,6 +3,7 @@ and the training driver use, on outputs the oracle can compute one by one.
 
 * render forward / adjoint / filter: 2^20 rays with a ragged seeded layout of
   the image workload's size (~2.6e8 samples), every 4099th ray checked;
+* repack of kept prefixes at that size: every element;
 * inverse CDF: the proposal configuration, 2^18 rays x 128 bins -> 32, every ray;
 * proposal MLP forward: the training shape, 2^20 rays x 128 bins, hidden 128,
   contracted encoding, 4096 sampled points;
@@ -91,6 +92,26 @@ def test_render_and_filter_full_size(gpu_lib):
     cond = bwd_condition(sub, st0, st1, ssig, vb)
     assert_close(host(ds)[idx], rds, floor_scale=cond, name="d_sigma")
     assert_close(host(dr)[idx], rdr, name="d_rgb")
+
+
+def test_gather_full_size(gpu_lib):
+    """The repack in the benchmark's launch: 2^20 ragged rows of the image
+    workload's size, seeded kept prefixes (0..count, a fifth of them whole),
+    every output element compared (data movement: exact)."""
+    info, t0, t1 = ragged_layout(44, N_FULL, 150, 352)
+    g = scenes.rng(45)
+    counts = info[:, 1]
+    kept = np.where(g.random(N_FULL) < 0.2, counts,
+                    g.integers(0, counts + 1)).astype(np.int32)
+    rid = np.repeat(np.arange(N_FULL), counts).astype(np.int32)
+    info2, total2 = gpu_lib.exclusive_scan(dev(kept))
+    s2 = int(total2.item())
+    a, b, c = gpu_lib.gather_prefix(dev(info), info2, s2, dev(t0), dev(t1))
+    r_info, r_t0, r_t1, r_rid = oracle.gather_prefix(info, kept, t0, t1, rid)
+    assert s2 == len(r_t0) > 1e8
+    assert np.array_equal(host(info2), r_info)
+    assert np.array_equal(host(a), r_t0) and np.array_equal(host(b), r_t1)
+    assert np.array_equal(host(c), r_rid)
 
 
 def test_resample_proposal_configuration(gpu_lib):
