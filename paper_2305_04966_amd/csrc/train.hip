@@ -106,8 +106,18 @@ __global__ __launch_bounds__(kWave* kLossWaves) void hist_loss_kernel(
           if (jh[mid] >= j) hi = mid;
           else lo = mid + 1;
         }
+        int end = lo;  // first staged target at or after lo with jlo > j
+        hi = n;
+        while (end < hi) {
+          const int mid = (end + hi) >> 1;
+          if (jl[mid] > j) hi = mid;
+          else end = mid + 1;
+        }
+        // the run [lo, end) in target order; its length is known, so the
+        // LDS reads of the run are issued ahead of the (sequential) sum
         float g = gacc[q];
-        for (int k = lo; k < n && jl[k] <= j; ++k) g += cc[k];
+#pragma unroll 8
+        for (int k = lo; k < end; ++k) g += cc[k];
         gacc[q] = g;
       }
     }
