@@ -219,8 +219,13 @@ __device__ __forceinline__ void features(float xa, int g, bf16x8& b0, bf16x8& b1
 // is w3 (in the K order of the h2 fragments) and whose other rows are zero,
 // times the bf16 h2 fragments as B, accumulates z in row 0 of a 16x16 tile
 // (lanes 0..15, element 0), one point per column.
-template <int H, int NT>
-__global__ __launch_bounds__(256) void mlp_fwd_kernel(FwdArgs a) {
+// kThreads = 512 (eight waves sharing one LDS copy of the weights) for the
+// hidden-128 network: its 54 KB of weights allow three 256-thread blocks per
+// CU (three waves per SIMD); two 512-thread blocks at the 128 registers of a
+// four-wave target give four.
+template <int H, int NT, int kThreads = 256>
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(kThreads == 512 ? 4 : 1))) void mlp_fwd_kernel(FwdArgs a) {
   constexpr int MT = H / 16, KS = H / 32;
   const PackOffsets ko(H);
   const ParamOffsets po(H);
@@ -676,8 +681,8 @@ extern "C" txs_status txs_prop_mlp_fwd(const txs_mlp* mlp, const float* rays_o,
                        as_stream(stream), a);
   } else {
     constexpr int NT = 2;
-    const int64_t blocks = std::min<int64_t>((n_tiles + 4 * NT - 1) / (4 * NT), (int64_t)cus * 8);
-    hipLaunchKernelGGL((mlp_fwd_kernel<128, NT>), dim3((unsigned)blocks), dim3(256), 0,
+    const int64_t blocks = std::min<int64_t>((n_tiles + 8 * NT - 1) / (8 * NT), (int64_t)cus * 4);
+    hipLaunchKernelGGL((mlp_fwd_kernel<128, NT, 512>), dim3((unsigned)blocks), dim3(512), 0,
                        as_stream(stream), a);
   }
   return launch_status("txs_prop_mlp_fwd");
