@@ -19,9 +19,8 @@ constexpr int kRsWaves = 4;
 // kRegChunks * 64 - 1 bins are held in registers (64 consecutive bins per
 // chunk, one per lane), and the wave loads its next ray's row while it
 // resamples the current one (128 bins -> 32: 0.19 -> 0.16 ms for 2^18 rays);
-// other rows are read in place (for 32 bins the prefetch's registers cost
-// more than its latency saves).  Both paths do the same arithmetic in the
-// same order.
+// rows of at most 32 bins go two to a wave, one per half-wave; other rows are
+// read in place.  Every kind does the same arithmetic in the same order.
 //
 // out != NULL: edges [n_rays, n_out+1]; otherwise the intervals between them,
 // t0o[r*n_out + k] = edge k and t1o[r*n_out + k] = edge k+1.
@@ -38,39 +37,58 @@ struct RsArgs {
   float* t1o;
 };
 
-// CDF of ray r into F[0..n_bins] (the ray's edges already in e); returns F_n
-// and whether the uniform estimator replaced a massless row.  vi(c, i) is the
-// value of bin i = 64 c + lane (i < n_bins).
-template <class Val>
+// Inclusive sum over the lanes <= this one within its half-wave: the scheme of
+// add_scan_incl without the carry from lane 31 into lanes 32..63, so each
+// half's sums are bit for bit those of a whole-wave scan of its values alone.
+__device__ __forceinline__ float half_scan_incl(float v) {
+  const int ri = lane() & 15, row = lane() >> 4;
+  float t;
+  t = dpp<kRowShr1>(v, v); if (ri >= 1) v += t;
+  t = dpp<kRowShr2>(v, v); if (ri >= 2) v += t;
+  t = dpp<kRowShr4>(v, v); if (ri >= 4) v += t;
+  t = dpp<kRowShr8>(v, v); if (ri >= 8) v += t;
+  const float e0 = readlane(v, 15), e2 = readlane(v, 47);
+  return row == 1 ? v + e0 : row == 3 ? v + e2 : v;
+}
+
+// CDF of a ray into F[0..n_bins] (its edges already in e) by kLanes lanes
+// (the whole wave, or one half-wave per ray when n_bins <= 32); ln is the
+// lane within them, valid false for a half-wave without a ray (it still
+// takes part in the wave's scan, with zeros).  Returns F_n and whether the
+// uniform estimator replaced a massless row.  vi(c, i) is the value of bin
+// i = kLanes c + ln (i < n_bins).
+template <int kLanes, class Val>
 __device__ __forceinline__ float ray_cdf(const RsArgs& a, float* F, const float* e, Val vi,
-                                         bool& uniform) {
-  const int ln = lane();
+                                         bool& uniform, int ln, bool valid) {
   float carry = 0.0f;
-  if (ln == 0) F[0] = 0.0f;
-  for (int base = 0, c = 0; base < a.n_bins; base += kWave, ++c) {
+  if (ln == 0 && valid) F[0] = 0.0f;
+  for (int base = 0, c = 0; base < a.n_bins; base += kLanes, ++c) {
     const int i = base + ln;
     float m = 0.0f;
-    if (i < a.n_bins) m = (a.mode != TXS_PDF_WEIGHTS) ? vi(c, i) * (e[i + 1] - e[i]) : vi(c, i);
-    const float incl = add_scan_incl(m) + carry;
-    if (i < a.n_bins) F[i + 1] = (a.mode != TXS_PDF_WEIGHTS) ? -expm1f(-incl) : incl;
-    carry = readlane(incl, kWave - 1);
+    if (valid && i < a.n_bins)
+      m = (a.mode != TXS_PDF_WEIGHTS) ? vi(c, i) * (e[i + 1] - e[i]) : vi(c, i);
+    const float incl = (kLanes == kWave ? add_scan_incl(m) : half_scan_incl(m)) + carry;
+    if (valid && i < a.n_bins) F[i + 1] = (a.mode != TXS_PDF_WEIGHTS) ? -expm1f(-incl) : incl;
+    if (kLanes == kWave) carry = readlane(incl, kWave - 1);  // one chunk for half-waves
   }
   wave_sync();
-  float Fn = F[a.n_bins];
+  float Fn = valid ? F[a.n_bins] : 1.0f;
   uniform = !(Fn > 1e-12f);
   if (uniform) {
-    for (int i = ln; i <= a.n_bins; i += kWave) F[i] = (float)i / (float)a.n_bins;
+    for (int i = ln; i <= a.n_bins; i += kLanes) F[i] = (float)i / (float)a.n_bins;
     wave_sync();
     Fn = 1.0f;
   }
   return Fn;
 }
 
-// Output edges of ray r from its CDF F and edges e (both in LDS).
+// Output edges of ray r from its CDF F and edges e (both in LDS), kLanes
+// lanes, ln the lane within them.
+template <int kLanes>
 __device__ __forceinline__ void ray_invert(const RsArgs& a, int64_t r, const float* F,
-                                           const float* e, float Fn, bool uniform) {
+                                           const float* e, float Fn, bool uniform, int ln) {
   const float* vr = a.vals + r * a.n_bins;
-  for (int k = lane(); k <= a.n_out; k += kWave) {
+  for (int k = ln; k <= a.n_out; k += kLanes) {
     const float uk = a.u ? a.u[r * (a.n_out + 1) + k] : (float)k / (float)a.n_out;
     const float up = uk * Fn;
     // largest i in [0, n_bins] with F[i] <= up (F[0] = 0 <= up)
@@ -107,7 +125,12 @@ __device__ __forceinline__ void ray_invert(const RsArgs& a, int64_t r, const flo
   }
 }
 
-template <bool kRegs>
+// Kernel kinds: rows read in place by the whole wave, rows of 64..255 bins in
+// registers with the next ray prefetched, or two rays per wave (one per
+// half-wave) for rows of at most 32 bins.
+enum RsKind { kInPlace = 0, kRegRows = 1, kHalfWaves = 2 };
+
+template <int kKind>
 __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(RsArgs a) {
   extern __shared__ float lds_rs[];
   const int w = threadIdx.x / kWave, ln = lane();
@@ -115,7 +138,28 @@ __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(RsArgs a) {
   float* e = F + (a.n_bins + 1);
   const int64_t stride = (int64_t)gridDim.x * kRsWaves;
   const int64_t r0 = (int64_t)blockIdx.x * kRsWaves + w;
-  if constexpr (kRegs) {
+  if constexpr (kKind == kHalfWaves) {
+    // LDS: each half-wave has its own F and e
+    const int hl = ln & 31, half = ln >> 5;
+    float* Fh = lds_rs + (size_t)(2 * w + half) * 2 * (a.n_bins + 1);
+    float* eh = Fh + (a.n_bins + 1);
+    for (int64_t pr = r0; 2 * pr < a.n_rays; pr += stride) {  // wave-uniform pair index
+      const int64_t r = 2 * pr + half;
+      const bool valid = r < a.n_rays;
+      const float* er = a.edges + r * (a.n_bins + 1);
+      const float* vr = a.vals + r * a.n_bins;
+      if (valid)
+        for (int i = hl; i <= a.n_bins; i += 32) eh[i] = er[i];
+      wave_sync();
+      bool uniform;
+      const float Fn =
+          ray_cdf<32>(a, Fh, eh, [&](int, int i) { return vr[i]; }, uniform, hl, valid);
+      if (valid) ray_invert<32>(a, r, Fh, eh, Fn, uniform, hl);
+      wave_sync();  // this pair's LDS reads are done before the next pair overwrites it
+    }
+    return;
+  }
+  if constexpr (kKind == kRegRows) {
     // row c-chunk values of ray rr: edge 64c + lane (<= n_bins), bin 64c + lane
     auto fetch = [&](int64_t rr, float (&fe)[kRegChunks], float (&fv)[kRegChunks]) {
 #pragma unroll
@@ -135,15 +179,15 @@ __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(RsArgs a) {
         if (kWave * c + ln <= a.n_bins) e[kWave * c + ln] = ce[c];
       wave_sync();
       bool uniform;
-      const float Fn = ray_cdf(a, F, e,
-                               [&](int c, int) {
-                                 float v = cv[0];
+      const float Fn = ray_cdf<kWave>(a, F, e,
+                                      [&](int c, int) {
+                                        float v = cv[0];
 #pragma unroll
-                                 for (int q = 1; q < kRegChunks; ++q) v = (c == q) ? cv[q] : v;
-                                 return v;
-                               },
-                               uniform);
-      ray_invert(a, r, F, e, Fn, uniform);
+                                        for (int q = 1; q < kRegChunks; ++q) v = (c == q) ? cv[q] : v;
+                                        return v;
+                                      },
+                                      uniform, ln, true);
+      ray_invert<kWave>(a, r, F, e, Fn, uniform, ln);
       wave_sync();  // this ray's LDS reads are done before the next ray overwrites it
 #pragma unroll
       for (int c = 0; c < kRegChunks; ++c) {
@@ -159,8 +203,8 @@ __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(RsArgs a) {
     for (int i = ln; i <= a.n_bins; i += kWave) e[i] = er[i];
     wave_sync();
     bool uniform;
-    const float Fn = ray_cdf(a, F, e, [&](int, int i) { return vr[i]; }, uniform);
-    ray_invert(a, r, F, e, Fn, uniform);
+    const float Fn = ray_cdf<kWave>(a, F, e, [&](int, int i) { return vr[i]; }, uniform, ln, true);
+    ray_invert<kWave>(a, r, F, e, Fn, uniform, ln);
     wave_sync();  // this ray's LDS reads are done before the next ray overwrites it
   }
 }
@@ -171,16 +215,18 @@ inline unsigned resample_blocks(int32_t n_rays) {
   return (unsigned)std::min<int64_t>(need, 256 * 16);
 }
 
-// the register-row kernel for rows of 64 .. kRegChunks * 64 - 1 bins (a
-// separate instantiation, so that the in-place kernel keeps its own register
-// budget and occupancy)
+// one instantiation per kernel kind, so that each keeps its own register
+// budget and occupancy
 inline void launch_resample(const RsArgs& a, hipStream_t s) {
   const unsigned blocks = resample_blocks(a.n_rays);
   const size_t lds = kRsWaves * 2 * (a.n_bins + 1) * sizeof(float);
-  if (a.n_bins >= kWave && a.n_bins < kRegChunks * kWave)
-    hipLaunchKernelGGL(resample_kernel<true>, dim3(blocks), dim3(kWave * kRsWaves), lds, s, a);
+  if (a.n_bins <= 32)  // two rays per wave: twice the LDS per wave, half the waves
+    hipLaunchKernelGGL(resample_kernel<kHalfWaves>, dim3(resample_blocks((a.n_rays + 1) / 2)),
+                       dim3(kWave * kRsWaves), 2 * lds, s, a);
+  else if (a.n_bins >= kWave && a.n_bins < kRegChunks * kWave)
+    hipLaunchKernelGGL(resample_kernel<kRegRows>, dim3(blocks), dim3(kWave * kRsWaves), lds, s, a);
   else
-    hipLaunchKernelGGL(resample_kernel<false>, dim3(blocks), dim3(kWave * kRsWaves), lds, s, a);
+    hipLaunchKernelGGL(resample_kernel<kInPlace>, dim3(blocks), dim3(kWave * kRsWaves), lds, s, a);
 }
 
 // Equally spaced edges e_k = lo + (hi - lo) * (k / n_bins) over per-ray

@@ -440,6 +440,39 @@ def test_resample(gpu_lib, mode, use_u):
     assert np.array_equal(host(t1).reshape(n, n_out), out[:, 1:])
 
 
+@pytest.mark.parametrize("n,nb,n_out", [(4001, 32, 48), (333, 17, 5), (1, 32, 3), (2, 1, 64),
+                                         (1000, 33, 48), (999, 64, 40), (257, 255, 31),
+                                         (256, 256, 16)])
+def test_resample_row_lengths(gpu_lib, n, nb, n_out):
+    """Every kernel kind the bin count selects (two rays per wave up to 32
+    bins, odd ray counts leaving a half-wave without a ray; whole-wave rows of
+    33 bins; register rows of 64..255 bins; in-place rows from 256), in the
+    three modes, with and without caller u, against the oracle."""
+    g = scenes.rng(90 + nb + n)
+    a = g.uniform(1.0, 2.0, (n, 1))
+    edges = (a + np.concatenate([np.zeros((n, 1)), np.cumsum(g.uniform(0.005, 0.03, (n, nb)), 1)],
+                                1)).astype(np.float32)
+    vals = (g.exponential(1.0, (n, nb)) * (g.random((n, nb)) < 0.4) *
+            g.choice([1.0, 30.0], (n, 1))).astype(np.float32)
+    vals[: max(1, n // 50)] = 0.0  # zero-mass rays fall back to the uniform estimator
+    for mode in (0, 1, 2):
+        for u in (None, np.sort(g.random((n, n_out + 1)), 1).astype(np.float32)):
+            out = host(gpu_lib.resample(dev(edges), dev(vals), n_out, mode,
+                                        None if u is None else dev(u)))
+            ref, bins, band = oracle.resample(edges, vals, n_out, mode, u)
+            if mode == 2:  # the exponential inverse: finite, ordered, inside the row
+                assert np.all(np.diff(out, axis=1) >= 0) and np.all(out >= edges[:, :1])
+                assert np.all(out <= edges[:, -1:])
+                continue
+            tol = resample_tol(edges, vals, mode, ref, bins)
+            bad = (np.abs(out - ref) > tol) & ~band[:, None]
+            assert not bad.any(), (mode, bad.sum(), np.argwhere(bad)[:5])
+            t0, t1 = gpu_lib.resample_intervals(dev(edges), dev(vals), n_out, mode,
+                                                None if u is None else dev(u))
+            assert np.array_equal(host(t0).reshape(n, n_out), out[:, :-1])
+            assert np.array_equal(host(t1).reshape(n, n_out), out[:, 1:])
+
+
 @pytest.mark.parametrize("nb,n_out", [(1, 1), (1, 7), (1024, 1), (1024, 500), (3, 2000)])
 def test_resample_size_limits(gpu_lib, nb, n_out):
     """One bin, the largest bin count (1024), a single output interval and far
