@@ -281,7 +281,7 @@ def run_proposal_config(*, n_rays=1 << 18, hidden=64, bins=128, n_out=32, time_r
     return rec
 
 
-def run_combined(*, steps=300, hidden=128, bins=128, eval_bins=(64, 128), ray_stride=1,
+def run_combined(*, steps=300, hidden=128, bins=128, eval_bins=(16, 32, 64, 128), ray_stride=1,
                  train_stride=4, sweep=(32, 48, 64, 96, 128, 192, 256), err_bar=1e-3, lr0=1e-2,
                  lr1=1e-4, log_every=50, time_reps=5, log=print):
     """Proposal network alone versus the combined estimator on the image scene.
