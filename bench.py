@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--learned-spacing", default="disparity", choices=["linear", "disparity"],
                     help="proposal bins equal in t, or equal in 1/t from --learned-near")
     ap.add_argument("--learned-near", type=float, default=0.5)
-    ap.add_argument("--learned-bins", type=int, default=32,
+    ap.add_argument("--learned-bins", type=int, default=16,
                     help="proposal bins per ray")
     ap.add_argument("--combined-steps", type=int, default=300,
                     help="train the proposal network alone and inside the grid's occupied "
@@ -219,7 +219,7 @@ def gpu_bench(args, w):
 
 def learned_vs_grid(args):
     """The learned estimator against the occupancy grid on the unbounded scene:
-    train the proposal network (untimed) on 32 bins spaced equally in
+    train the proposal network (untimed) on 16 bins spaced equally in
     disparity from t = 0.5 (below the closest content, ~1 from every camera),
     then time
     both samplers end to end (fwd + bwd, the field stand-in on both sides) on
