@@ -75,6 +75,8 @@ class ProposalEstimator:
     m: Optional[torch.Tensor] = None
     v: Optional[torch.Tensor] = None
     workspace: Optional[torch.Tensor] = None
+    # inverse CDF inside a bin: linear (TXS_PDF_SIGMA) or exponential (TXS_PDF_SIGMA_EXP)
+    sample_mode: int = ops.TXS_PDF_SIGMA
 
     def __post_init__(self):
         self.spec = ops.MlpSpec(self.params, self.hidden, self.scale, self.contract).repack()
@@ -91,12 +93,12 @@ class ProposalEstimator:
     def sample(self, rays_o, rays_d, edges, n_out, u=None):
         """Inverse-CDF intervals from the proposal transmittance -> edges [N, n_out+1]."""
         sig = self.density(rays_o, rays_d, edges)
-        return ops.resample(edges, sig, n_out, mode=ops.TXS_PDF_SIGMA, u=u)
+        return ops.resample(edges, sig, n_out, mode=self.sample_mode, u=u)
 
     def sample_intervals(self, rays_o, rays_d, edges, n_out, u=None):
         """The same intervals in the dense layout -> (t0, t1) [N*n_out]."""
         sig = self.density(rays_o, rays_d, edges)
-        return ops.resample_intervals(edges, sig, n_out, mode=ops.TXS_PDF_SIGMA, u=u)
+        return ops.resample_intervals(edges, sig, n_out, mode=self.sample_mode, u=u)
 
     # ------------------------------------------------------------ update
     @staticmethod

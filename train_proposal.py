@@ -101,7 +101,7 @@ def mlp_flops(hidden, adjoint=False):
 def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
         sweep=(32, 48, 64, 96, 128, 192, 256), err_bar=1e-3, lr0=1e-2, lr1=1e-4,
         log_every=50, time_reps=5, untrained=True, spacing="linear", near=1.0, rounds=1,
-        n_mid=64, log=print):
+        n_mid=64, in_bin="linear", log=print):
     import torch
 
     import paper_2305_04966_amd as txs
@@ -146,12 +146,14 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
     # 2. train
     edges = bins_of(o, d)
     edges_t = edges if train_stride == ray_stride else bins_of(ot, dt)
-    est = ProposalEstimator(dev(scenes.mlp_init(hidden)), hidden, scale=1.5, contract=True)
+    est = ProposalEstimator(dev(scenes.mlp_init(hidden)), hidden, scale=1.5, contract=True,
+                            sample_mode=txs.TXS_PDF_SIGMA_EXP if in_bin == "exp" else txs.TXS_PDF_SIGMA)
     # a second round: its own network, drawn from a second seed
     est2 = (ProposalEstimator(dev(scenes.mlp_init(hidden, seed=scenes.SEED_MLP + 16)), hidden,
                               scale=1.5, contract=True) if rounds == 2 else None)
     if rounds == 2:
         rec["rounds"] = f"2 ({bins} bins, then {n_mid} intervals)"
+    rec["in_bin"] = in_bin
 
     def intervals(ro, rd, e, n_out):
         if rounds == 2:
@@ -532,6 +534,8 @@ def main():
     ap.add_argument("--rounds", type=int, default=1, choices=[1, 2],
                     help="proposal rounds (2: a second network on the first one's intervals)")
     ap.add_argument("--n-mid", type=int, default=64, help="intervals the first round draws")
+    ap.add_argument("--in-bin", default="linear", choices=["linear", "exp"],
+                    help="inverse CDF inside a proposal bin: linear or exponential")
     ap.add_argument("--contracted", action="store_true",
                     help="the grid over contracted space against the cascade (unbounded)")
     ap.add_argument("--pdf", action="store_true",
@@ -559,7 +563,7 @@ def main():
                    sweep=[int(s) for s in args.sweep.split(",")], err_bar=args.err_bar,
                    lr0=args.lr0, lr1=args.lr1, log_every=args.log_every,
                    time_reps=args.time_reps, spacing=args.spacing, near=args.near,
-                   rounds=args.rounds, n_mid=args.n_mid,
+                   rounds=args.rounds, n_mid=args.n_mid, in_bin=args.in_bin,
                    log=lambda s: print(s, flush=True))
     if args.save:
         np.save(args.save, est.params.cpu().numpy())
