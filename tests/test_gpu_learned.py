@@ -244,3 +244,24 @@ def test_edges_to_intervals(gpu_lib):
         t0, t1 = gpu_lib.edges_to_intervals(dev(e))
         assert np.array_equal(host(t0), e[:, :-1].ravel())
         assert np.array_equal(host(t1), e[:, 1:].ravel())
+
+
+@pytest.mark.parametrize("mode_name", ["TXS_PDF_SIGMA", "TXS_PDF_SIGMA_EXP"])
+def test_estimator_sampling_modes(gpu_lib, mode_name):
+    """The estimator's intervals are the resampler's, in the mode it is given,
+    applied to its own density at the bins."""
+    from paper_2305_04966_amd.learned import ProposalEstimator
+    mode = getattr(gpu_lib, mode_name)
+    g = scenes.rng(34)
+    n, nb, n_out = 500, 16, 24
+    o, d = scenes.sphere_rays(n, radius=3.0, seed=7)
+    o, d = dev(o), dev(d)
+    near = g.uniform(1.0, 1.5, (n, 1))
+    e = dev((near + np.linspace(0.0, 2.0, nb + 1)[None, :]).astype(np.float32))
+    est = ProposalEstimator(dev(scenes.mlp_init(64)), 64, scale=1.5, sample_mode=mode)
+    sig = est.density(o, d, e)
+    a, b = est.sample_intervals(o, d, e, n_out)
+    ra, rb = gpu_lib.resample_intervals(e, sig, n_out, mode)
+    assert torch.equal(a, ra) and torch.equal(b, rb)
+    edges = est.sample(o, d, e, n_out)
+    assert torch.equal(edges, gpu_lib.resample(e, sig, n_out, mode))
