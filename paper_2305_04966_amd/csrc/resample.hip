@@ -19,8 +19,9 @@ constexpr int kRsWaves = 4;
 // kRegChunks * 64 - 1 bins are held in registers (64 consecutive bins per
 // chunk, one per lane), and the wave loads its next ray's row while it
 // resamples the current one (128 bins -> 32: 0.19 -> 0.16 ms for 2^18 rays);
-// rows of at most 32 bins go two to a wave, one per half-wave; other rows are
-// read in place.  Every kind does the same arithmetic in the same order.
+// rows of at most 32 bins go two to a wave (one per half-wave), rows of at
+// most 16 four to a wave; other rows are read in place.  Every kind does the
+// same arithmetic in the same order.
 //
 // out != NULL: edges [n_rays, n_out+1]; otherwise the intervals between them,
 // t0o[r*n_out + k] = edge k and t1o[r*n_out + k] = edge k+1.
@@ -51,6 +52,17 @@ __device__ __forceinline__ float half_scan_incl(float v) {
   return row == 1 ? v + e0 : row == 3 ? v + e2 : v;
 }
 
+// The same within each 16-lane row (the row steps of add_scan_incl alone).
+__device__ __forceinline__ float row_scan_incl(float v) {
+  const int ri = lane() & 15;
+  float t;
+  t = dpp<kRowShr1>(v, v); if (ri >= 1) v += t;
+  t = dpp<kRowShr2>(v, v); if (ri >= 2) v += t;
+  t = dpp<kRowShr4>(v, v); if (ri >= 4) v += t;
+  t = dpp<kRowShr8>(v, v); if (ri >= 8) v += t;
+  return v;
+}
+
 // CDF of a ray into F[0..n_bins] (its edges already in e) by kLanes lanes
 // (the whole wave, or one half-wave per ray when n_bins <= 32); ln is the
 // lane within them, valid false for a half-wave without a ray (it still
@@ -67,7 +79,9 @@ __device__ __forceinline__ float ray_cdf(const RsArgs& a, float* F, const float*
     float m = 0.0f;
     if (valid && i < a.n_bins)
       m = (a.mode != TXS_PDF_WEIGHTS) ? vi(c, i) * (e[i + 1] - e[i]) : vi(c, i);
-    const float incl = (kLanes == kWave ? add_scan_incl(m) : half_scan_incl(m)) + carry;
+    const float incl = (kLanes == kWave ? add_scan_incl(m)
+                        : kLanes == 32  ? half_scan_incl(m)
+                                        : row_scan_incl(m)) + carry;
     if (valid && i < a.n_bins) F[i + 1] = (a.mode != TXS_PDF_WEIGHTS) ? -expm1f(-incl) : incl;
     if (kLanes == kWave) carry = readlane(incl, kWave - 1);  // one chunk for half-waves
   }
@@ -126,9 +140,10 @@ __device__ __forceinline__ void ray_invert(const RsArgs& a, int64_t r, const flo
 }
 
 // Kernel kinds: rows read in place by the whole wave, rows of 64..255 bins in
-// registers with the next ray prefetched, or two rays per wave (one per
-// half-wave) for rows of at most 32 bins.
-enum RsKind { kInPlace = 0, kRegRows = 1, kHalfWaves = 2 };
+// registers with the next ray prefetched, two rays per wave (one per
+// half-wave) for rows of at most 32 bins, four (one per 16-lane row) for rows
+// of at most 16.
+enum RsKind { kInPlace = 0, kRegRows = 1, kHalfWaves = 2, kQuarterWaves = 3 };
 
 template <int kKind>
 __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(RsArgs a) {
@@ -138,24 +153,25 @@ __global__ __launch_bounds__(kWave* kRsWaves) void resample_kernel(RsArgs a) {
   float* e = F + (a.n_bins + 1);
   const int64_t stride = (int64_t)gridDim.x * kRsWaves;
   const int64_t r0 = (int64_t)blockIdx.x * kRsWaves + w;
-  if constexpr (kKind == kHalfWaves) {
-    // LDS: each half-wave has its own F and e
-    const int hl = ln & 31, half = ln >> 5;
-    float* Fh = lds_rs + (size_t)(2 * w + half) * 2 * (a.n_bins + 1);
+  if constexpr (kKind == kHalfWaves || kKind == kQuarterWaves) {
+    // kParts rays per wave, kLanes lanes each; each part has its own F and e
+    constexpr int kParts = kKind == kHalfWaves ? 2 : 4, kLanes = kWave / kParts;
+    const int pl = ln % kLanes, part = ln / kLanes;
+    float* Fh = lds_rs + (size_t)(kParts * w + part) * 2 * (a.n_bins + 1);
     float* eh = Fh + (a.n_bins + 1);
-    for (int64_t pr = r0; 2 * pr < a.n_rays; pr += stride) {  // wave-uniform pair index
-      const int64_t r = 2 * pr + half;
+    for (int64_t pr = r0; kParts * pr < a.n_rays; pr += stride) {  // wave-uniform group index
+      const int64_t r = kParts * pr + part;
       const bool valid = r < a.n_rays;
       const float* er = a.edges + r * (a.n_bins + 1);
       const float* vr = a.vals + r * a.n_bins;
       if (valid)
-        for (int i = hl; i <= a.n_bins; i += 32) eh[i] = er[i];
+        for (int i = pl; i <= a.n_bins; i += kLanes) eh[i] = er[i];
       wave_sync();
       bool uniform;
-      const float Fn =
-          ray_cdf<32>(a, Fh, eh, [&](int, int i) { return vr[i]; }, uniform, hl, valid);
-      if (valid) ray_invert<32>(a, r, Fh, eh, Fn, uniform, hl);
-      wave_sync();  // this pair's LDS reads are done before the next pair overwrites it
+      const float Fn = ray_cdf<kLanes>(a, Fh, eh, [&](int, int i) { return vr[i]; }, uniform, pl,
+                                       valid);
+      if (valid) ray_invert<kLanes>(a, r, Fh, eh, Fn, uniform, pl);
+      wave_sync();  // this group's LDS reads are done before the next group overwrites it
     }
     return;
   }
@@ -220,7 +236,11 @@ inline unsigned resample_blocks(int32_t n_rays) {
 inline void launch_resample(const RsArgs& a, hipStream_t s) {
   const unsigned blocks = resample_blocks(a.n_rays);
   const size_t lds = kRsWaves * 2 * (a.n_bins + 1) * sizeof(float);
-  if (a.n_bins <= 32)  // two rays per wave: twice the LDS per wave, half the waves
+  if (a.n_bins <= 16)  // four rays per wave: four times the LDS per wave
+    hipLaunchKernelGGL(resample_kernel<kQuarterWaves>,
+                       dim3(resample_blocks((a.n_rays + 3) / 4)), dim3(kWave * kRsWaves), 4 * lds,
+                       s, a);
+  else if (a.n_bins <= 32)  // two rays per wave: twice the LDS per wave, half the waves
     hipLaunchKernelGGL(resample_kernel<kHalfWaves>, dim3(resample_blocks((a.n_rays + 1) / 2)),
                        dim3(kWave * kRsWaves), 2 * lds, s, a);
   else if (a.n_bins >= kWave && a.n_bins < kRegChunks * kWave)

@@ -441,11 +441,12 @@ def test_resample(gpu_lib, mode, use_u):
 
 
 @pytest.mark.parametrize("n,nb,n_out", [(4001, 32, 48), (333, 17, 5), (1, 32, 3), (2, 1, 64),
+                                         (1003, 16, 64), (5, 9, 7), (3, 16, 1),
                                          (1000, 33, 48), (999, 64, 40), (257, 255, 31),
                                          (256, 256, 16)])
 def test_resample_row_lengths(gpu_lib, n, nb, n_out):
-    """Every kernel kind the bin count selects (two rays per wave up to 32
-    bins, odd ray counts leaving a half-wave without a ray; whole-wave rows of
+    """Every kernel kind the bin count selects (four rays per wave up to 16
+    bins, two up to 32, ray counts leaving parts of a wave without a ray; whole-wave rows of
     33 bins; register rows of 64..255 bins; in-place rows from 256), in the
     three modes, with and without caller u, against the oracle."""
     g = scenes.rng(90 + nb + n)
