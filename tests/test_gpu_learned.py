@@ -179,7 +179,7 @@ def target_histograms(n_rays, seed):
     return info, t0, t1, w
 
 
-@pytest.mark.parametrize("nb", [1, 16, 128, 1024])
+@pytest.mark.parametrize("nb", [1, 16, 17, 32, 33, 128, 1024])
 def test_hist_loss(gpu_lib, nb):
     n = 1500
     info, t0, t1, w = target_histograms(n, 3 + nb)
