@@ -25,7 +25,7 @@ namespace {
 #endif
 constexpr int K = TXS_RENDER_K;    // samples per lane per window (a multiple of 4)
 constexpr int W = kWave * K;       // samples per window
-constexpr int kWaves = 4;          // waves per block
+constexpr int kWaves = 8;          // waves per block
 constexpr int kBlock = kWave * kWaves;
 constexpr int kMarks = W + kWave;  // marks for window positions 0..W (cleared 64 at a time)
 
