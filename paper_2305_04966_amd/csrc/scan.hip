@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kScanBlock) void write_packed(const int32_t* __rest
 
 // Repack: a wave owns 64 consecutive rays and copies the kept prefix of each
 // with all lanes (contiguous loads and stores).
-constexpr int kGatherWaves = 4;
+constexpr int kGatherWaves = 8;
 
 // The wave's 64 rays are copied as one walk over their output positions in
 // steps of kGatherSpan (kGatherUnroll chunks of 64 consecutive positions, one
