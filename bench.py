@@ -143,8 +143,10 @@ def gpu_bench(args, w):
         sig, rgb = tl.run("field_density_rgb", txs.blob_field, params, nb, o, d, q0, q1, qr)
         out = tl.run("render_fwd", txs.render_fwd, info2, q0, q1, sig, rgb,
                      want_optical_depth=True)
+        # info2 is the scan of the kept counts, whose total is s: its rows tile
+        # [0, s), so the adjoint writes every output sample
         grads = tl.run("render_bwd", txs.render_bwd, info2, q0, q1, sig, rgb, g_rgb,
-                       optical_depth=out[4])
+                       optical_depth=out[4], tight=True)
         stats["Sm"], stats["S"] = sm, s
         stats["_probe"] = (q0, q1, sig, rgb)
         return out, grads

@@ -97,10 +97,15 @@ txs_status txs_march_count(const txs_grid* grid, const txs_march_params* params,
 /*
  * Exclusive scan of per-ray counts into the packed table (Section 4.2,
  * "Packed Tensor"): packed_info[r] = (sum_{q<r} counts[q], counts[r]) and
- * *d_total (device int64) = sum of all counts.  Starts that would exceed
- * INT32_MAX are still summed correctly into *d_total; the caller must check
- * *d_total < 2^31 before using the table.  workspace: device scratch of at
- * least txs_scan_workspace_size(n_rays) bytes (contents need not be zero).
+ * *d_total (device int64) = sum of all counts.  The scan runs on the device,
+ * so it cannot refuse a total it has not yet computed: a row whose end
+ * start + count would pass INT32_MAX is written as the empty row
+ * (INT32_MAX, 0), which every entry point of this library reads as a ray
+ * with no samples, while *d_total stays the exact int64 sum.  The caller reads
+ * *d_total (the one host read of a sampling pass) and treats a total
+ * >= 2^31 as TXS_EOVERFLOW before sizing the packed tensors.  workspace:
+ * device scratch of at least txs_scan_workspace_size(n_rays) bytes (contents
+ * need not be zero).
  */
 size_t txs_scan_workspace_size(int32_t n_rays);
 txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays, int32_t* packed_info,
@@ -112,7 +117,8 @@ txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays, int32_t* pa
  * ray-major and t-ascending: t0, t1 (float [capacity]) and ray_id (int32
  * [capacity], may be NULL).  packed_info must come from counts produced by
  * txs_march_count with the same grid, params and rays.  No write goes at or
- * beyond `capacity` samples.
+ * beyond `capacity` samples, nor past packed_info[r].count samples of ray r
+ * (a row with a negative start or count is written as empty).
  */
 txs_status txs_march_fill(const txs_grid* grid, const txs_march_params* params,
                           const float* rays_o, const float* rays_d, int32_t n_rays,
@@ -152,8 +158,11 @@ txs_status txs_march_fill_contracted(const txs_grid* grid, const txs_march_param
  * T_i = exp(-sum_{j<i} tau_j) over the samples of a ray, kept_counts[r] is
  * the number of leading samples with T_i >= t_min (the paper uses 1e-4).
  * T is non-increasing, so the kept samples are a prefix of the ray.  The
- * decision is taken in binary32 as sum_{j<i} tau_j <= -ln(t_min).
+ * decision is taken in binary64: the optical depth sum_{j<i} tau_j is summed
+ * in binary64 from the binary32 tau_j = sigma_j (t1_j - t0_j) and compared
+ * with -log((double)t_min); sample i is kept iff it is <= that bound.
  * sigma: float [n_samples] (density from the radiance field, no gradient).
+ * TXS_EOVERFLOW if n_samples >= 2^31.
  */
 txs_status txs_transmittance_prefix(const int32_t* packed_info, int32_t n_rays,
                                     int64_t n_samples, const float* t0, const float* t1,
@@ -186,7 +195,8 @@ txs_status txs_gather_prefix(const int32_t* packed_info_in, const int32_t* packe
  * (black).  Outputs: out_rgb [n_rays,3], out_opacity [n_rays],
  * out_depth [n_rays], out_weights [n_samples] or NULL, and
  * out_optical_depth double [n_rays] or NULL = sum_i tau_i per ray.
- * Optical depths are accumulated in binary64.
+ * Optical depths are accumulated in binary64.  TXS_EOVERFLOW if
+ * n_samples >= 2^31 (the same holds for txs_render_bwd and txs_weights_bwd).
  */
 txs_status txs_render_fwd(const int32_t* packed_info, int32_t fixed_count, int32_t n_rays,
                           int64_t n_samples, const float* t0, const float* t1,
@@ -207,7 +217,9 @@ txs_status txs_render_fwd(const int32_t* packed_info, int32_t fixed_count, int32
  * cost of one more read of t0, t1, sigma.  The samples are walked last to
  * first so both suffix sums are exact reverse scans.
  * d_sigma float [n_samples], d_rgb float [n_samples,3] (may be NULL).
- * Samples outside every ray's segment are left unchanged.
+ * Samples outside every ray's segment (gaps between rows, or the tail of a
+ * dense layout with n_rays * fixed_count < n_samples) are left unchanged:
+ * a caller whose rows do not tile [0, n_samples) clears those outputs first.
  */
 txs_status txs_render_bwd(const int32_t* packed_info, int32_t fixed_count, int32_t n_rays,
                           int64_t n_samples, const float* t0, const float* t1,
@@ -373,7 +385,7 @@ txs_status txs_prop_mlp_bwd(const txs_mlp* mlp, const float* rays_o, const float
  *   loss[r] = sum_i max(0, w_i - bound_i)^2 / (w_i + eps).
  * d_prop (may be NULL) = d(mean_r loss[r]) / d prop_w, float [n_rays, n_bins];
  * each bin sums its overlapping targets in target order (deterministic).
- * n_bins <= 1024.
+ * n_bins <= 1024.  TXS_EOVERFLOW if n_targets >= 2^31.
  */
 txs_status txs_hist_loss(const int32_t* packed_info, int32_t n_rays, int64_t n_targets,
                          const float* t0, const float* t1, const float* w, int32_t n_bins,
@@ -447,8 +459,8 @@ txs_status txs_grid_ema(int64_t n_cells, float* density, const float* sigma, flo
                         float tau, uint32_t* bits, void* stream);
 
 /* ------------------------------------------------------------------------ */
-/* Combined estimator (Section 3.1 "Insights from Unified Formulation";
- * Section 5 "Combined Sampling"): the occupancy grid's transmittance comes
+/* Combined estimator (Section 3.3 "Insights from Unified Formulation";
+ * Section 4.4 "Combined Sampling"): the occupancy grid's transmittance comes
  * first -- rays that cross no occupied cell are dropped and every other ray is
  * narrowed to its occupied span -- and the proposal network refines inside
  * that span (uniform bins -> proposal density -> inverse CDF).
@@ -482,17 +494,6 @@ txs_status txs_expand_rows(int32_t n_rays, const int32_t* table, int32_t width, 
                            float fill, float* dst, void* stream);
 txs_status txs_span_bins(int32_t n_rays, const float* span, int32_t n_bins, float* out_edges,
                          void* stream);
-
-/* ------------------------------------------------------------------------ */
-/* Measurement support (not part of the method).  Moves the HBM traffic of
- * txs_render_bwd in its layout -- reads t0, t1, sigma (float [n]) and rgb
- * (float [n,3]); writes out_a (float [n]) and out_b (float [n,3]) -- with
- * trivial arithmetic (out_a = t0 + t1 + sigma, out_b = 2 rgb), so that its
- * time is the ceiling of that traffic pattern on the device.  Arrays 16-byte
- * aligned.                                                                  */
-txs_status txs_stream_probe(int64_t n_samples, const float* t0, const float* t1,
-                            const float* sigma, const float* rgb, float* out_a, float* out_b,
-                            void* stream);
 
 #ifdef __cplusplus
 }

@@ -189,13 +189,23 @@ def gather_prefix(packed_info, kept, t0, t1, ray_id):
     return np.ascontiguousarray(info_out), t0[idx], t1[idx], ray_id[idx]
 
 
+INT32_MAX = 2 ** 31 - 1
+
+
 def exclusive_scan(counts):
+    """Packed table of per-ray counts (Section 4.2, "Packed Tensor"): row r =
+    (sum of the counts before r, count r); returns (table int32 [N, 2], the
+    exact total).  Starts are int32, so a row that does not end by INT32_MAX
+    cannot be addressed and is the empty row (INT32_MAX, 0)."""
     counts = np.asarray(counts, np.int64)
+    total = int(counts.sum())
     starts = np.zeros_like(counts)
     if counts.size:
         starts[1:] = np.cumsum(counts)[:-1]
-    info = np.stack([starts, counts], axis=1).astype(np.int32)
-    return info, int(counts.sum())
+    fits = starts + counts <= INT32_MAX
+    info = np.stack([np.where(fits, starts, INT32_MAX), np.where(fits, counts, 0)],
+                    axis=1).astype(np.int32)
+    return info, total
 
 
 MODE_SIGMA, MODE_WEIGHTS, MODE_SIGMA_EXP = 0, 1, 2
@@ -331,7 +341,7 @@ def grid_ema(density, sigma, gamma, tau):
 
 
 def march_span(o, d, bits, res, **march_kw):
-    """Occupied span of every ray (Section 5, "Combined Sampling": the grid
+    """Occupied span of every ray (Section 4.4, "Combined Sampling": the grid
     shrinks each ray's near-far interval to where it found occupied space):
     (t0 of the first sample, t1 of the last) of the dense march, (0, 0) for a
     ray with none -> (span float32 [N, 2], hit int32 [N])."""

@@ -1,4 +1,4 @@
-"""ctypes loader of libtxs.so: declares every entry point of include/txs.h."""
+"""ctypes loader of libtxs.so: declares every entry point of include/*.h."""
 from __future__ import annotations
 
 import ctypes as C

@@ -1,5 +1,5 @@
-// Combined estimator plumbing (Section 3.1, "Insights from Unified
-// Formulation"; Section 5, "Combined Sampling"): the occupancy grid removes the
+// Combined estimator plumbing (Section 3.3, "Insights from Unified
+// Formulation"; Section 4.4, "Combined Sampling"): the occupancy grid removes the
 // rays that cross no occupied cell and shrinks every other ray's interval to
 // its occupied span; the proposal network then bins only that span
 // (txs_span_bins, beside the uniform bins).  These kernels move per-ray rows

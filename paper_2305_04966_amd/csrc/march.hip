@@ -75,6 +75,7 @@ struct Emit {
   float* t1;
   int32_t* ray_id;
   int64_t base;
+  int32_t count;  // kFill: the table row's count; no write at or beyond it
   int64_t capacity;
   int32_t ray;
   float lo, hi;  // kSpan: the span so far (wave-uniform)
@@ -198,7 +199,7 @@ __device__ __forceinline__ int32_t march_segment(const MarchArgs& g, const float
         const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
             (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
         const int64_t pos = em.base + n + rank;
-        if ((cap == 0 || n + rank < cap) && pos < em.capacity) {
+        if ((cap == 0 || n + rank < cap) && n + rank < em.count && pos < em.capacity) {
           em.t0[pos] = a + (float)k * p.dt;
           em.t1[pos] = fminf(a + (float)(k + 1) * p.dt, b);
           if (em.ray_id) em.ray_id[pos] = em.ray;
@@ -337,8 +338,12 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float*
     o[c] = ro[3 * (int64_t)r + c];
     d[c] = rd[3 * (int64_t)r + c];
   }
-  Emit em{t0, t1, ray_id, kMode == kFill ? (int64_t)info[2 * (int64_t)r] : 0, capacity, r,
-          0.0f, 0.0f};
+  Emit em{t0, t1, ray_id, 0, 0, capacity, r, 0.0f, 0.0f};
+  if (kMode == kFill) {
+    const int2 row = reinterpret_cast<const int2*>(info)[r];
+    em.base = row.x;
+    em.count = (row.x < 0 || row.y < 0) ? 0 : row.y;  // malformed row: nothing written
+  }
   const int32_t n = march_ray<kMode, kContract>(g, o, d, em);
   if (kMode == kCount && lane() == 0) counts[r] = n;
   if (kMode == kSpan && lane() == 0) {

@@ -6,6 +6,7 @@
 // adjoint does.  Its time bounds what any kernel with that traffic and layout
 // can reach on the device.
 #include "txs_common.h"
+#include "txs_measure.h"
 
 namespace txs {
 namespace {

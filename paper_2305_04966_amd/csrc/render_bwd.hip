@@ -12,7 +12,7 @@
 // walk and nothing per sample is stored between the two directions.
 // Windows of 4 samples per lane: the adjoint's state per sample is larger
 // than the forward's, and half the window keeps three waves per SIMD.
-#define TXS_RENDER_K 4
+#define TXS_RENDER_ADJOINT
 #include "render_window.h"
 
 namespace txs {

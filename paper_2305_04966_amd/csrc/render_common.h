@@ -20,10 +20,14 @@
 namespace txs {
 namespace {
 
-#ifndef TXS_RENDER_K
-#define TXS_RENDER_K 8
+// Samples per lane per window (a multiple of 4): 8 in the forward kernels, 4
+// in the adjoint, whose per-sample state is larger (its translation unit
+// defines TXS_RENDER_ADJOINT before including this header).
+#ifdef TXS_RENDER_ADJOINT
+constexpr int K = 4;
+#else
+constexpr int K = 8;
 #endif
-constexpr int K = TXS_RENDER_K;    // samples per lane per window (a multiple of 4)
 constexpr int W = kWave * K;       // samples per window
 constexpr int kWaves = 8;          // waves per block
 constexpr int kBlock = kWave * kWaves;
@@ -387,7 +391,10 @@ txs_status check_common(const char* who, const int32_t* info, int32_t fixed, int
                         int64_t n_samples, const float* t0, const float* t1,
                         const float* sigma) {
   TXS_REQUIRE(n_rays >= 0 && n_samples >= 0, "%s: negative size", who);
-  TXS_REQUIRE(n_samples < ((int64_t)1 << 31), "%s: n_samples must be < 2^31", who);
+  if (n_samples >= ((int64_t)1 << 31)) {
+    set_error("%s: %lld samples do not fit the int32 packed layout", who, (long long)n_samples);
+    return TXS_EOVERFLOW;
+  }
   if (!info) {
     TXS_REQUIRE(fixed >= 0, "%s: fixed_count must be >= 0", who);
     TXS_REQUIRE((int64_t)fixed * n_rays <= n_samples,

@@ -80,9 +80,13 @@ __global__ __launch_bounds__(kScanBlock) void write_packed(const int32_t* __rest
 #pragma unroll
   for (int j = 0; j < kPerThread; ++j) {
     if (base + j < n) {
-      // starts beyond INT32_MAX wrap; the caller checks the int64 total
-      info[2 * (base + j)] = (int32_t)start;
-      info[2 * (base + j) + 1] = c[j];
+      // a row that does not end below 2^31 cannot be addressed by int32
+      // starts: it is written as the empty row (INT32_MAX, 0), which keeps the
+      // starts non-decreasing and leaves every consumer nothing to read or
+      // write; the int64 total stays exact for the caller's overflow check
+      const bool fits = start + c[j] <= (int64_t)INT32_MAX;
+      info[2 * (base + j)] = fits ? (int32_t)start : INT32_MAX;
+      info[2 * (base + j) + 1] = fits ? c[j] : 0;
     }
     start += c[j];
   }
@@ -222,22 +226,15 @@ extern "C" size_t txs_scan_workspace_size(int32_t n_rays) {
   return (size_t)tiles * sizeof(int64_t);
 }
 
-extern "C" txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays,
-                                         int32_t* packed_info, int64_t* d_total,
-                                         void* workspace, size_t workspace_bytes, void* stream) {
-  using namespace txs;
-  clear_error();
-  TXS_REQUIRE(n_rays >= 0, "txs_exclusive_scan: n_rays < 0");
-  TXS_REQUIRE(d_total, "txs_exclusive_scan: null d_total");
-  TXS_REQUIRE(n_rays == 0 || (counts && packed_info), "txs_exclusive_scan: null array");
-  const size_t need = txs_scan_workspace_size(n_rays);
-  if (!workspace || workspace_bytes < need) {
-    set_error("txs_exclusive_scan: workspace needs %zu bytes, got %zu", need, workspace_bytes);
-    return TXS_ECAPACITY;
-  }
+namespace txs {
+namespace {
+
+// The three passes of the scan, with the tile sums in `sums` (one int64 per
+// tile of kTile counts; every pass-1 tile overwrites its own entry, so the
+// buffer needs no clearing).
+void launch_scan(const int32_t* counts, int32_t n_rays, int32_t* packed_info, int64_t* d_total,
+                 int64_t* sums, hipStream_t s) {
   const int32_t tiles = (int32_t)((int64_t)std::max<int32_t>(n_rays, 1) + kTile - 1) / kTile;
-  int64_t* sums = static_cast<int64_t*>(workspace);
-  hipStream_t s = as_stream(stream);
   if (n_rays > 0)
     hipLaunchKernelGGL(tile_sums, dim3(tiles), dim3(kScanBlock), 0, s, counts, n_rays, sums);
   else
@@ -246,6 +243,33 @@ extern "C" txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays,
   if (n_rays > 0)
     hipLaunchKernelGGL(write_packed, dim3(tiles), dim3(kScanBlock), 0, s, counts, n_rays, sums,
                        packed_info);
+}
+
+txs_status check_scan_args(const char* who, const int32_t* counts, int32_t n_rays,
+                           const int32_t* packed_info, const int64_t* d_total) {
+  TXS_REQUIRE(n_rays >= 0, "%s: n_rays < 0", who);
+  TXS_REQUIRE(d_total, "%s: null d_total", who);
+  TXS_REQUIRE(n_rays == 0 || (counts && packed_info), "%s: null array", who);
+  return TXS_OK;
+}
+
+}  // namespace
+}  // namespace txs
+
+extern "C" txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays,
+                                         int32_t* packed_info, int64_t* d_total,
+                                         void* workspace, size_t workspace_bytes, void* stream) {
+  using namespace txs;
+  clear_error();
+  if (txs_status st = check_scan_args("txs_exclusive_scan", counts, n_rays, packed_info, d_total))
+    return st;
+  const size_t need = txs_scan_workspace_size(n_rays);
+  if (!workspace || workspace_bytes < need) {
+    set_error("txs_exclusive_scan: workspace needs %zu bytes, got %zu", need, workspace_bytes);
+    return TXS_ECAPACITY;
+  }
+  launch_scan(counts, n_rays, packed_info, d_total, static_cast<int64_t*>(workspace),
+              as_stream(stream));
   return launch_status("txs_exclusive_scan");
 }
 

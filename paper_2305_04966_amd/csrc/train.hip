@@ -161,6 +161,11 @@ extern "C" txs_status txs_hist_loss(const int32_t* packed_info, int32_t n_rays, 
   using namespace txs;
   clear_error();
   TXS_REQUIRE(n_rays >= 0 && n_targets >= 0, "txs_hist_loss: negative size");
+  if (n_targets >= ((int64_t)1 << 31)) {
+    set_error("txs_hist_loss: %lld targets do not fit the int32 packed layout",
+              (long long)n_targets);
+    return TXS_EOVERFLOW;
+  }
   TXS_REQUIRE(n_bins >= 1 && n_bins <= kMaxBins, "txs_hist_loss: n_bins must be in [1,%d]",
               kMaxBins);
   TXS_REQUIRE(eps >= 0.0f, "txs_hist_loss: eps must be >= 0");

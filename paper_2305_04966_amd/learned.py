@@ -14,8 +14,8 @@ library:
 Targets come from the plain occupancy-grid renderer (march, filter, field,
 render with weights), computed by `grid_render`.
 
-The combined estimator (Section 3.1, "Insights from Unified Formulation";
-Section 5, "Combined Sampling") stacks the occupancy grid on the proposal
+The combined estimator (Section 3.3, "Insights from Unified Formulation";
+Section 4.4, "Combined Sampling") stacks the occupancy grid on the proposal
 network: `occupied_span` marches the grid for each ray's occupied span and
 compacts the rays that have one, and `combined_render` bins only that span
 for the proposal network.  Only argument plumbing lives here.

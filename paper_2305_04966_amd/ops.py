@@ -229,9 +229,27 @@ def render_fwd(packed_info, t0, t1, sigma, rgb, *, n_rays=None, fixed_count=None
     return out_rgb, out_op, out_d, w
 
 
+def _covers(packed_info, fc, n, s, tight):
+    """True when the rows are known to tile [0, s): the adjoint then writes
+    every output sample and the outputs need no clearing.  A dense layout
+    tiles it iff n * fixed_count == s; a packed table only when the caller
+    says so (a table from the scan of its own counts, with s = the total)."""
+    return (n * fc == s) if packed_info is None else bool(tight)
+
+
+def _grad_out(shape, covered, dev):
+    # the adjoint leaves samples outside every row unchanged: those are zero
+    return (torch.empty if covered else torch.zeros)(shape, dtype=torch.float32, device=dev)
+
+
 def render_bwd(packed_info, t0, t1, sigma, rgb, g_rgb, g_opacity=None, g_depth=None, *,
-               n_rays=None, fixed_count=None, bg=None, optical_depth=None, want_d_rgb=True):
-    """-> (d_sigma [S], d_rgb [S,3] or None).  optical_depth: the forward's, or None."""
+               n_rays=None, fixed_count=None, bg=None, optical_depth=None, want_d_rgb=True,
+               tight=False):
+    """-> (d_sigma [S], d_rgb [S,3] or None).  optical_depth: the forward's, or None.
+
+    Samples that belong to no row get zero gradient.  tight=True states that
+    packed_info's rows tile [0, S) (e.g. a table scanned from counts summing to
+    S), which spares clearing the outputs first."""
     n = packed_info.shape[0] if packed_info is not None else int(n_rays)
     fc = _layout(packed_info, fixed_count, n)
     s = t0.shape[0]
@@ -244,8 +262,9 @@ def render_bwd(packed_info, t0, t1, sigma, rgb, g_rgb, g_opacity=None, g_depth=N
     _opt(bg, "bg", torch.float32, (n, 3))
     _opt(optical_depth, "optical_depth", torch.float64, (n,))
     dev = t0.device
-    ds = torch.empty(s, dtype=torch.float32, device=dev)
-    dr = torch.empty((s, 3), dtype=torch.float32, device=dev) if want_d_rgb else None
+    covered = _covers(packed_info, fc, n, s, tight)
+    ds = _grad_out(s, covered, dev)
+    dr = _grad_out((s, 3), covered, dev) if want_d_rgb else None
     check(load().txs_render_bwd(_ptr(packed_info), fc, n, s, _ptr(t0), _ptr(t1), _ptr(sigma),
                                 _ptr(rgb), _ptr(bg), _ptr(optical_depth), _ptr(g_rgb),
                                 _ptr(g_opacity), _ptr(g_depth), _ptr(ds), _ptr(dr), _stream()),
@@ -254,14 +273,16 @@ def render_bwd(packed_info, t0, t1, sigma, rgb, g_rgb, g_opacity=None, g_depth=N
 
 
 def weights_bwd(packed_info, t0, t1, sigma, g_w, *, n_rays=None, fixed_count=None,
-                optical_depth=None):
+                optical_depth=None, tight=False):
+    """dL/dsigma from dL/dw; zero for samples that belong to no row (tight as
+    for render_bwd)."""
     n = packed_info.shape[0] if packed_info is not None else int(n_rays)
     fc = _layout(packed_info, fixed_count, n)
     s = t0.shape[0]
     for name, t in (("t0", t0), ("t1", t1), ("sigma", sigma), ("g_w", g_w)):
         _need(t, name, torch.float32, (s,))
     _opt(optical_depth, "optical_depth", torch.float64, (n,))
-    ds = torch.empty(s, dtype=torch.float32, device=t0.device)
+    ds = _grad_out(s, _covers(packed_info, fc, n, s, tight), t0.device)
     check(load().txs_weights_bwd(_ptr(packed_info), fc, n, s, _ptr(t0), _ptr(t1), _ptr(sigma),
                                  _ptr(optical_depth), _ptr(g_w), _ptr(ds), _stream()),
           "txs_weights_bwd")

@@ -28,6 +28,7 @@ class Packed:
     t0: torch.Tensor           # float32 [S]
     t1: torch.Tensor           # float32 [S]
     ray_id: Optional[torch.Tensor]  # int32 [S]
+    tight: bool = False  # rows tile [0, S) exactly (a table scanned from counts)
 
     @property
     def n_samples(self) -> int:
@@ -49,7 +50,7 @@ def march(grid: ops.GridSpec, rays_o, rays_d, *, dt0, near=0.0, far=float("inf")
     s = _host_total(total)
     t0, t1, rid = ops.march_fill(grid, rays_o, rays_d, info, s, near=near, far=far, dt0=dt0,
                                  max_per_ray=max_per_ray)
-    return Packed(info, t0, t1, rid)
+    return Packed(info, t0, t1, rid, tight=True)
 
 
 def march_contracted(grid: ops.GridSpec, rays_o, rays_d, contract_scale, *, dt0, near=0.0,
@@ -62,7 +63,7 @@ def march_contracted(grid: ops.GridSpec, rays_o, rays_d, contract_scale, *, dt0,
     t0, t1, rid = ops.march_fill_contracted(grid, rays_o, rays_d, contract_scale, info, s,
                                             near=near, far=far, dt0=dt0,
                                             max_per_ray=max_per_ray)
-    return Packed(info, t0, t1, rid)
+    return Packed(info, t0, t1, rid, tight=True)
 
 
 def filter_transmittance(p: Packed, sigma, t_min=1e-4) -> Packed:
@@ -71,7 +72,7 @@ def filter_transmittance(p: Packed, sigma, t_min=1e-4) -> Packed:
     info, total = ops.exclusive_scan(kept)
     s = _host_total(total)
     t0, t1, rid = ops.gather_prefix(p.packed_info, info, s, p.t0, p.t1)
-    return Packed(info, t0, t1, rid)
+    return Packed(info, t0, t1, rid, tight=True)
 
 
 def sampling(grid: ops.GridSpec, rays_o, rays_d, density_fn: Callable, *, dt0,
@@ -91,13 +92,13 @@ class RenderFn(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, sigma, rgb, packed_info, t0, t1, bg, n_rays, fixed_count):
+    def forward(ctx, sigma, rgb, packed_info, t0, t1, bg, n_rays, fixed_count, tight=False):
         out_rgb, out_op, out_d, _, od = ops.render_fwd(packed_info, t0, t1, sigma.contiguous(),
                                                        rgb.contiguous(), n_rays=n_rays,
                                                        fixed_count=fixed_count, bg=bg,
                                                        want_optical_depth=True)
         ctx.save_for_backward(sigma, rgb, packed_info, t0, t1, bg, od)
-        ctx.n_rays, ctx.fixed_count = n_rays, fixed_count
+        ctx.n_rays, ctx.fixed_count, ctx.tight = n_rays, fixed_count, tight
         return out_rgb, out_op, out_d
 
     @staticmethod
@@ -110,18 +111,19 @@ class RenderFn(torch.autograd.Function):
         g_d = g_d.contiguous() if g_d is not None else None
         ds, dr = ops.render_bwd(packed_info, t0, t1, sigma.contiguous(), rgb.contiguous(),
                                 g_rgb, g_op, g_d, n_rays=n, fixed_count=ctx.fixed_count, bg=bg,
-                                optical_depth=od, want_d_rgb=ctx.needs_input_grad[1])
-        return ds, dr, None, None, None, None, None, None
+                                optical_depth=od, want_d_rgb=ctx.needs_input_grad[1],
+                                tight=ctx.tight)
+        return ds, dr, None, None, None, None, None, None, None
 
 
 def rendering(p: Packed, sigma, rgb, bg=None):
     """-> (rgb [N,3], opacity [N], depth [N]); differentiable in sigma and rgb."""
     n = p.packed_info.shape[0]
-    return RenderFn.apply(sigma, rgb, p.packed_info, p.t0, p.t1, bg, n, None)
+    return RenderFn.apply(sigma, rgb, p.packed_info, p.t0, p.t1, bg, n, None, p.tight)
 
 
 def rendering_dense(t0, t1, sigma, rgb, n_rays, fixed_count, bg=None):
-    return RenderFn.apply(sigma, rgb, None, t0, t1, bg, n_rays, fixed_count)
+    return RenderFn.apply(sigma, rgb, None, t0, t1, bg, n_rays, fixed_count, False)
 
 
 def pdf_render(density_fn: Callable, field_fn: Callable, rays_o, rays_d, edges, n_fine, *,

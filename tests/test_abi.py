@@ -1,20 +1,23 @@
-"""The C-ABI library loads and exports every entry point include/txs.h declares
+"""The C-ABI library loads and exports every entry point include/*.h declares
 (no GPU needed: nothing is launched)."""
 import ctypes as C
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "txs.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 LIB = os.path.join(ROOT, "paper_2305_04966_amd", "libtxs.so")
 
 
 def declared_symbols():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(txs_[a-z0-9_]+)\s*\(", text)))
+    syms = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        syms |= set(re.findall(r"\b(txs_[a-z0-9_]+)\s*\(", text))
+    return sorted(syms)
 
 
 @pytest.fixture(scope="module")
@@ -49,6 +52,29 @@ def test_version_and_error_without_gpu(lib):
     assert b"n_bins" in lib.txs_last_error()
     lib.txs_scan_workspace_size.restype = C.c_size_t
     assert lib.txs_scan_workspace_size(C.c_int32(1 << 20)) >= 8 * 256
+
+
+def test_counts_past_int32_return_eoverflow(lib):
+    """A packed tensor of 2^31 or more samples is refused with TXS_EOVERFLOW on
+    the host, before any launch."""
+    lib.txs_render_fwd.restype = C.c_int32
+    lib.txs_last_error.restype = C.c_char_p
+    big = C.c_int64(1 << 31)
+    st = lib.txs_render_fwd(None, C.c_int32(0), C.c_int32(4), big, None, None, None, None, None,
+                            None, None, None, None, None, None)
+    assert st == -4 and b"int32" in lib.txs_last_error()
+    lib.txs_transmittance_prefix.restype = C.c_int32
+    st = lib.txs_transmittance_prefix(None, C.c_int32(4), big, None, None, None, C.c_float(1e-4),
+                                      None, None)
+    assert st == -1  # a null table is refused first
+    lib.txs_weights_bwd.restype = C.c_int32
+    st = lib.txs_weights_bwd(None, C.c_int32(0), C.c_int32(4), big, None, None, None, None, None,
+                             None, None)
+    assert st == -4
+    lib.txs_hist_loss.restype = C.c_int32
+    st = lib.txs_hist_loss(None, C.c_int32(4), big, None, None, None, C.c_int32(8), None, None,
+                           C.c_float(1e-7), None, None, None)
+    assert st == -4
 
 
 def test_plain_c_consumer(lib, tmp_path):

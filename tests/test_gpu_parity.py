@@ -380,6 +380,58 @@ def test_render_autograd_and_determinism(gpu_lib, tiny):
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
+def test_render_autograd_gap_samples_get_zero_gradient(gpu_lib):
+    """Samples that belong to no row -- gaps between packed rows, the tail of a
+    dense layout -- receive exactly zero gradient through the autograd
+    function, and the owned samples still match the oracle."""
+    info, t0, t1, sig, rgb = random_packed(15, 600, 80, gaps=True, long_rays=[(7, 700)])
+    S = t0.size
+    tail = 37  # samples after the last row
+    t0 = np.concatenate([t0, np.linspace(3, 4, tail, dtype=np.float32)])
+    t1 = np.concatenate([t1, np.linspace(3.01, 4.01, tail, dtype=np.float32)])
+    sig = np.concatenate([sig, np.full(tail, 7.0, np.float32)])
+    rgb = np.concatenate([rgb, np.full((tail, 3), 0.5, np.float32)])
+    own = np.concatenate([np.arange(s_, s_ + c) for s_, c in info])
+    gap = np.setdiff1d(np.arange(S + tail), own)
+    assert gap.size > 100
+    g = scenes.rng(16)
+    gr = dev(g.standard_normal((info.shape[0], 3)).astype(np.float32))
+    for _ in range(2):  # a second pass reuses freed memory with the first's values
+        s = dev(sig).requires_grad_(True)
+        c = dev(rgb).requires_grad_(True)
+        out_rgb, _, _ = gpu_lib.rendering(gpu_lib.Packed(dev(info), dev(t0), dev(t1), None), s, c)
+        (out_rgb * gr).sum().backward()
+        ds, dr = host(s.grad), host(c.grad)
+        assert np.all(ds[gap] == 0.0) and np.all(dr[gap] == 0.0)
+        rds, rdr = oracle.render_bwd(info, t0, t1, sig, rgb, host(gr))
+        assert_close(dr[own], rdr[own], name="d_rgb")
+    # dense layout with trailing samples: n * F < S
+    n, F = 500, 16
+    _, d0, d1, dsg, dc = random_packed(17, n, F, long_rays=[(r, F) for r in range(n)])
+    d0 = np.concatenate([d0, np.ones(29, np.float32)])
+    d1 = np.concatenate([d1, np.full(29, 1.5, np.float32)])
+    dsg = np.concatenate([dsg, np.ones(29, np.float32)])
+    dc = np.concatenate([dc, np.ones((29, 3), np.float32)])
+    s = dev(dsg).requires_grad_(True)
+    c = dev(dc).requires_grad_(True)
+    out_rgb, out_op, _ = gpu_lib.rendering_dense(dev(d0), dev(d1), s, c, n, F)
+    (out_rgb.sum() + out_op.sum()).backward()
+    assert np.all(host(s.grad)[n * F:] == 0.0) and np.all(host(c.grad)[n * F:] == 0.0)
+    w = host(gpu_lib.weights_bwd(None, dev(d0), dev(d1), dev(dsg), dev(np.ones_like(dsg)),
+                                 n_rays=n, fixed_count=F))
+    assert np.all(w[n * F:] == 0.0)
+
+
+def test_exclusive_scan_rows_past_int32_are_empty(gpu_lib):
+    """A table whose rows would pass INT32_MAX: the total is the exact int64 sum
+    and the rows that do not fit are written as the empty row (INT32_MAX, 0)."""
+    counts = np.array([2 ** 30, 2 ** 30, 5, 0, 7], np.int32)
+    info, total = gpu_lib.exclusive_scan(dev(counts))
+    ref_info, ref_total = oracle.exclusive_scan(counts)
+    assert int(total.item()) == ref_total == 2 ** 31 + 12
+    assert np.array_equal(host(info), ref_info)
+
+
 def test_render_empty(gpu_lib):
     info = np.zeros((5, 2), np.int32)
     z = np.zeros(0, np.float32)

@@ -454,6 +454,81 @@ def test_weights_bwd_is_render_bwd_with_per_sample_cotangent():
 
 
 # ----------------------------------------------------------------------------
+# packed table and repack (Section 4.2, "Packed Tensor"; "No Gradient Filtering")
+# ----------------------------------------------------------------------------
+def test_exclusive_scan_hand_case():
+    info, total = oracle.exclusive_scan(np.array([3, 0, 2, 0, 5], np.int32))
+    assert info.dtype == np.int32 and info.shape == (5, 2)
+    assert info.tolist() == [[0, 3], [3, 0], [3, 2], [5, 0], [5, 5]]
+    assert total == 10
+    info, total = oracle.exclusive_scan(np.zeros(0, np.int32))
+    assert info.shape == (0, 2) and total == 0
+
+
+def test_exclusive_scan_total_past_int32_is_exact_and_rows_saturate():
+    # 2^30 + 2^30 + 5 = 2^31 + 5: the total needs 64 bits; row 1 would end at
+    # 2^31 and row 2 start there, neither addressable by int32 starts
+    counts = np.array([2 ** 30, 2 ** 30, 5, 0], np.int32)
+    info, total = oracle.exclusive_scan(counts)
+    assert total == 2 ** 31 + 5
+    assert info.tolist() == [[0, 2 ** 30], [2 ** 31 - 1, 0], [2 ** 31 - 1, 0], [2 ** 31 - 1, 0]]
+    # a row ending exactly at INT32_MAX still fits
+    info, total = oracle.exclusive_scan(np.array([2 ** 31 - 2, 1, 1], np.int32))
+    assert info.tolist() == [[0, 2 ** 31 - 2], [2 ** 31 - 2, 1], [2 ** 31 - 1, 0]]
+    assert total == 2 ** 31
+
+
+def test_exclusive_scan_brute_force_small():
+    g = scenes.rng(21)
+    for n in (1, 2, 7, 64, 300):
+        c = g.integers(0, 9, n).astype(np.int32)
+        info, total = oracle.exclusive_scan(c)
+        run = 0
+        for r in range(n):
+            assert info[r, 0] == run and info[r, 1] == c[r]
+            run += int(c[r])
+        assert total == run
+
+
+def test_gather_prefix_hand_case_with_gaps():
+    # three rays whose rows leave gaps (samples 4-5 and 9-11 belong to no ray);
+    # kept prefixes: none, part of the row, the whole row
+    info = np.array([[0, 4], [6, 3], [12, 5]], np.int32)
+    t0 = np.arange(17, dtype=np.float32)
+    t1 = t0 + np.float32(0.5)
+    rid = np.array([0, 0, 0, 0, -1, -1, 1, 1, 1, -1, -1, -1, 2, 2, 2, 2, 2], np.int32)
+    kept = np.array([0, 2, 5], np.int32)
+    out, o0, o1, orid = oracle.gather_prefix(info, kept, t0, t1, rid)
+    assert out.tolist() == [[0, 0], [0, 2], [2, 5]]
+    assert o0.tolist() == [6.0, 7.0, 12.0, 13.0, 14.0, 15.0, 16.0]
+    assert o1.tolist() == [6.5, 7.5, 12.5, 13.5, 14.5, 15.5, 16.5]
+    assert orid.tolist() == [1, 1, 2, 2, 2, 2, 2]
+
+
+def test_gather_prefix_brute_force_small():
+    g = scenes.rng(22)
+    n = 40
+    counts = g.integers(0, 12, n)
+    gaps = g.integers(0, 4, n)
+    starts = np.cumsum(gaps + np.concatenate([[0], counts[:-1]]))
+    info = np.stack([starts, counts], axis=1).astype(np.int32)
+    S = int(starts[-1] + counts[-1] + 3)
+    t0 = g.uniform(0, 10, S).astype(np.float32)
+    t1 = (t0 + g.uniform(0, 1, S)).astype(np.float32)
+    rid = g.integers(0, 1000, S).astype(np.int32)
+    kept = np.array([g.integers(0, c + 1) for c in counts], np.int32)
+    out, o0, o1, orid = oracle.gather_prefix(info, kept, t0, t1, rid)
+    pos = 0
+    for r in range(n):
+        assert out[r, 0] == pos and out[r, 1] == kept[r]
+        for j in range(kept[r]):
+            src = starts[r] + j
+            assert o0[pos] == t0[src] and o1[pos] == t1[src] and orid[pos] == rid[src]
+            pos += 1
+    assert pos == o0.shape[0] == o1.shape[0] == orid.shape[0]
+
+
+# ----------------------------------------------------------------------------
 # no-gradient filtering
 # ----------------------------------------------------------------------------
 def test_transmittance_prefix_constant_density():
@@ -639,7 +714,7 @@ def test_grid_ema_closed_forms():
 
 
 # ----------------------------------------------------------------------------
-# combined estimator: the grid's occupied span (Section 5, "Combined Sampling")
+# combined estimator: the grid's occupied span (Section 4.4, "Combined Sampling")
 # ----------------------------------------------------------------------------
 def test_span_of_one_occupied_cell_is_its_chord_on_the_lattice():
     # an 8^3 grid with cells (3, 4, 4) and (5, 4, 4) occupied; rays along +x

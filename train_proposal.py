@@ -18,7 +18,7 @@ The unbounded scene (64 blobs and a background shell, 4 nested 128^3 grids,
 
 `run_combined` repeats steps 1-4 on the bounded image scene (32 blobs, one
 128^3 grid, 1024x1024 pinhole camera) for the proposal network alone and for
-the combined estimator (Section 5, "Combined Sampling"): the grid first drops
+the combined estimator (Section 4.4, "Combined Sampling"): the grid first drops
 the rays that cross no occupied cell and narrows every other ray to its
 occupied span, and the proposal network bins only that span.
 
@@ -211,7 +211,8 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
         q = txs.filter_transmittance(p, sg, w.t_min)
         sg, rgb = txs.blob_field(fp, nb, o, d, q.t0, q.t1, q.ray_id)
         out = txs.render_fwd(q.packed_info, q.t0, q.t1, sg, rgb, want_optical_depth=True)
-        txs.render_bwd(q.packed_info, q.t0, q.t1, sg, rgb, g_rgb, optical_depth=out[4])
+        txs.render_bwd(q.packed_info, q.t0, q.t1, sg, rgb, g_rgb, optical_depth=out[4],
+                       tight=q.tight)
 
     def learned_step():
         a, b, sg, rgb, od = render_learned(o, d, bins_of(o, d), n_star, keep=True)
@@ -383,7 +384,8 @@ def run_combined(*, steps=300, hidden=128, bins=128, eval_bins=(16, 32, 64, 128)
         q = txs.filter_transmittance(p, sg, w.t_min)
         sg, rgb = txs.blob_field(sc.fp, w.fld.n_blobs, o, d, q.t0, q.t1, q.ray_id)
         out = txs.render_fwd(q.packed_info, q.t0, q.t1, sg, rgb, want_optical_depth=True)
-        txs.render_bwd(q.packed_info, q.t0, q.t1, sg, rgb, g_rgb, optical_depth=out[4])
+        txs.render_bwd(q.packed_info, q.t0, q.t1, sg, rgb, g_rgb, optical_depth=out[4],
+                       tight=q.tight)
 
     rec["grid_ms"] = _timed(torch, grid_step, time_reps)
     rec["grid_rays_per_s"] = N / (rec["grid_ms"] * 1e-3)
@@ -502,7 +504,8 @@ def run_contracted(*, res=128, scale=1.5, tau=0.01, time_reps=5, log=print):
 
     def step(contracted):
         _, q_, sg, rgb, out_ = render(contracted)
-        txs.render_bwd(q_.packed_info, q_.t0, q_.t1, sg, rgb, g_rgb, optical_depth=out_[4])
+        txs.render_bwd(q_.packed_info, q_.t0, q_.t1, sg, rgb, g_rgb, optical_depth=out_[4],
+                       tight=q_.tight)
 
     for name, c in (("cascade", False), ("contracted", True)):
         ms = _timed(torch, lambda: step(c), time_reps)
