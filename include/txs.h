@@ -113,6 +113,21 @@ txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays, int32_t* pa
                               void* stream);
 
 /*
+ * Allocation-free variant of txs_exclusive_scan, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): same arguments minus the workspace, same
+ * results bit for bit.  Its tile sums live in a fixed device array of the
+ * library (128 KiB, one copy per GPU, held until the process ends), so
+ * n_rays <= txs_exclusive_scan_noalloc_max_rays() (2^26); larger inputs return
+ * TXS_ECAPACITY.  The call allocates nothing.  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialised by the caller; calls on one stream are ordered.
+ */
+int32_t txs_exclusive_scan_noalloc_max_rays(void);
+txs_status txs_exclusive_scan_noalloc(const int32_t* counts, int32_t n_rays,
+                                      int32_t* packed_info, int64_t* d_total, void* stream);
+
+/*
  * Second marching pass: writes the samples of ray r at packed_info[r].start,
  * ray-major and t-ascending: t0, t1 (float [capacity]) and ray_id (int32
  * [capacity], may be NULL).  packed_info must come from counts produced by

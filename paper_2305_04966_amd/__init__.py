@@ -9,7 +9,8 @@ from ._lib import (TXS_EHIP, TXS_EINVAL, TXS_ECAPACITY, TXS_EOVERFLOW, TXS_OK,
                    exported_symbols, load)
 from .ops import (GridSpec, MlpSpec, adam_step, blob_field, compact_rows, disparity_bins,
                   edges_to_intervals,
-                  exclusive_scan, expand_rows, gather_prefix, grid_ema, grid_points,
+                  exclusive_scan, exclusive_scan_noalloc, exclusive_scan_noalloc_max_rays,
+                  expand_rows, gather_prefix, grid_ema, grid_points,
                   grid_points_contracted, hist_loss,
                   march_count, march_count_contracted, march_fill, march_fill_contracted,
                   march_span, merge_edges, mlp_param_count, prop_mlp_bwd,

@@ -45,6 +45,8 @@ SIGNATURES = {
     "txs_march_count": (I32, [GP, MP, P, P, I32, P, P]),
     "txs_scan_workspace_size": (SZ, [I32]),
     "txs_exclusive_scan": (I32, [P, I32, P, P, P, SZ, P]),
+    "txs_exclusive_scan_noalloc_max_rays": (I32, []),
+    "txs_exclusive_scan_noalloc": (I32, [P, I32, P, P, P]),
     "txs_march_fill": (I32, [GP, MP, P, P, I32, P, I64, P, P, P, P]),
     "txs_transmittance_prefix": (I32, [P, I32, I64, P, P, P, F32, P, P]),
     "txs_gather_prefix": (I32, [P, P, I32, I64, P, P, I64, P, P, P, P]),

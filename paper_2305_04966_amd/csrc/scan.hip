@@ -1,6 +1,8 @@
 // Packed-tensor bookkeeping (Section 4.2 "Packed Tensor"): exclusive scan of
 // per-ray counts into (start, count) rows, and the prefix repack that follows
 // no-gradient filtering.
+#include <mutex>
+
 #include "txs_common.h"
 
 namespace txs {
@@ -253,6 +255,43 @@ txs_status check_scan_args(const char* who, const int32_t* counts, int32_t n_ray
   return TXS_OK;
 }
 
+// Tile sums of the allocation-free scan: a fixed array in device memory
+// (every GPU the library runs on holds its own copy until the process ends).
+constexpr int32_t kScratchTiles = 16384;  // 128 KiB: up to 2^26 rays per call
+static __device__ __align__(256) int64_t scratch[kScratchTiles];
+
+// Device address of `scratch` on each device, taken once per device with that
+// device current.  In host code the array's name is only a stand-in for the
+// symbol, never a device address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int64_t* g_scratch_ptr[kMaxDevices] = {};
+
+txs_status scratch_on_current_device(const char* who, int64_t** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_error("%s: hipGetDevice failed: %s", who, hipGetErrorString(e));
+    return TXS_EHIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("%s: device %d beyond the %d the library tracks", who, dev, kMaxDevices);
+    return TXS_EHIP;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error("%s: hipGetSymbolAddress(scratch) failed: %s", who, hipGetErrorString(e));
+      return TXS_EHIP;
+    }
+    g_scratch_ptr[dev] = static_cast<int64_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return TXS_OK;
+}
+
 }  // namespace
 }  // namespace txs
 
@@ -271,6 +310,29 @@ extern "C" txs_status txs_exclusive_scan(const int32_t* counts, int32_t n_rays,
   launch_scan(counts, n_rays, packed_info, d_total, static_cast<int64_t*>(workspace),
               as_stream(stream));
   return launch_status("txs_exclusive_scan");
+}
+
+extern "C" int32_t txs_exclusive_scan_noalloc_max_rays(void) {
+  return (int32_t)((int64_t)txs::kScratchTiles * txs::kTile);
+}
+
+extern "C" txs_status txs_exclusive_scan_noalloc(const int32_t* counts, int32_t n_rays,
+                                                 int32_t* packed_info, int64_t* d_total,
+                                                 void* stream) {
+  using namespace txs;
+  clear_error();
+  if (txs_status st = check_scan_args("txs_exclusive_scan_noalloc", counts, n_rays, packed_info,
+                                      d_total))
+    return st;
+  if ((int64_t)n_rays > (int64_t)kScratchTiles * kTile) {
+    set_error("txs_exclusive_scan_noalloc: %d rays exceed the static scratch's limit of %lld",
+              n_rays, (long long)kScratchTiles * kTile);
+    return TXS_ECAPACITY;
+  }
+  int64_t* sums = nullptr;
+  if (txs_status st = scratch_on_current_device("txs_exclusive_scan_noalloc", &sums)) return st;
+  launch_scan(counts, n_rays, packed_info, d_total, sums, as_stream(stream));
+  return launch_status("txs_exclusive_scan_noalloc");
 }
 
 extern "C" txs_status txs_gather_prefix(const int32_t* packed_info_in,

@@ -13,7 +13,8 @@ import torch
 
 from ._lib import TXS_PDF_SIGMA, TXS_PDF_SIGMA_EXP, TXS_PDF_WEIGHTS, Grid, MarchParams, check, load
 
-__all__ = ["GridSpec", "march_count", "exclusive_scan", "march_fill", "transmittance_prefix",
+__all__ = ["GridSpec", "march_count", "exclusive_scan", "exclusive_scan_noalloc",
+           "exclusive_scan_noalloc_max_rays", "march_fill", "transmittance_prefix",
            "gather_prefix", "render_fwd", "render_bwd", "weights_bwd", "resample",
            "uniform_bins", "edges_to_intervals", "resample_intervals", "blob_field",
            "march_span", "compact_rows", "expand_rows", "span_bins", "merge_edges", "disparity_bins", "march_count_contracted",
@@ -120,6 +121,22 @@ def exclusive_scan(counts, packed_info=None, total=None):
     check(L.txs_exclusive_scan(_ptr(counts), n, _ptr(packed_info), _ptr(total), _ptr(ws),
                                ws_bytes, _stream()), "txs_exclusive_scan")
     return packed_info, total
+
+
+def exclusive_scan_noalloc(counts, packed_info, total):
+    """txs_exclusive_scan without a workspace: the caller passes the outputs
+    (packed_info int32 [N,2], total int64 [1]) and nothing is allocated."""
+    n = counts.shape[0]
+    _need(counts, "counts", torch.int32, (n,))
+    _need(packed_info, "packed_info", torch.int32, (n, 2))
+    _need(total, "total", torch.int64, (1,))
+    check(load().txs_exclusive_scan_noalloc(_ptr(counts), n, _ptr(packed_info), _ptr(total),
+                                            _stream()), "txs_exclusive_scan_noalloc")
+    return packed_info, total
+
+
+def exclusive_scan_noalloc_max_rays():
+    return int(load().txs_exclusive_scan_noalloc_max_rays())
 
 
 def march_fill(grid: GridSpec, rays_o, rays_d, packed_info, n_samples, *, near=0.0,
