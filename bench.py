@@ -45,12 +45,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="image", choices=["image", "tiny", "unbounded"])
-    ap.add_argument("--cpu-sample", type=int, default=2,
+    ap.add_argument("--cpu-sample", type=int, default=4,
                     help="oracle baseline runs on every k-th ray (0 = skip)")
-    ap.add_argument("--learned-steps", type=int, default=300,
+    ap.add_argument("--learned-steps", type=int, default=1000,
                     help="train the proposal network this many steps on the unbounded scene and "
                          "report learned vs grid sampling (0 = skip)")
-    ap.add_argument("--learned-train-stride", type=int, default=4)
+    ap.add_argument("--learned-train-stride", type=int, default=1,
+                    help="train the proposal network on every k-th ray of the unbounded "
+                         "workload (1 = all 2^20 rays every step)")
+    ap.add_argument("--learned-heldout", default="8,9",
+                    help="rig cameras (beyond the workload's 8) that choose the final sample "
+                         "count and report the held-out error")
     ap.add_argument("--learned-sweep", default="32,40,48,64,96,128")
     ap.add_argument("--learned-spacing", default="disparity", choices=["linear", "disparity"],
                     help="proposal bins equal in t, or equal in 1/t from --learned-near")
@@ -62,6 +67,8 @@ def parse():
                          "spans this many steps each on the image scene and report both "
                          "(0 = skip)")
     ap.add_argument("--combined-sweep", default="32,48,64,96,128,192,256")
+    ap.add_argument("--combined-train-stride", type=int, default=4,
+                    help="the combined-vs-proposal experiment trains on every k-th ray")
     ap.add_argument("--pdf", type=int, default=1,
                     help="run the coarse-to-fine PDF estimator on the image scene and report "
                          "it (0 = skip)")
@@ -176,6 +183,16 @@ def gpu_bench(args, w):
         e1.record()
         torch.cuda.synchronize()
         stats["pattern_ms"] = e0.elapsed_time(e1) / 5
+        # the forward's reads in its layout
+        ro = txs.read_probe(q0, q1, sig, rgb)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            txs.read_probe(q0, q1, sig, rgb, ro)
+        e1.record()
+        torch.cuda.synchronize()
+        stats["read_pattern_ms"] = e0.elapsed_time(e1) / 5
+        del ro
     # occupancy-grid estimator update (EMA) on a copy of the workload's grid:
     # cell points, the field at them, EMA and binarisation
     from paper_2305_04966_amd.pipeline import OccupancyGrid
@@ -228,20 +245,25 @@ def learned_vs_grid(args):
     all 2^20 rays, the learned one at the fewest final samples within 1e-3
     mean rgb error of the grid."""
     from train_proposal import run
-    rec, _ = run(steps=args.learned_steps, train_stride=args.learned_train_stride,
-                 sweep=[int(s) for s in args.learned_sweep.split(",")], untrained=False,
-                 spacing=args.learned_spacing, near=args.learned_near, bins=args.learned_bins,
-                 log_every=max(args.learned_steps, 1), time_reps=3,
-                 log=lambda s: print(s, file=sys.stderr, flush=True))
+    heldout = tuple(int(c) for c in args.learned_heldout.split(",")) if args.learned_heldout \
+        else None
+    rec, _, extras = run(steps=args.learned_steps, train_stride=args.learned_train_stride,
+                         sweep=[int(s) for s in args.learned_sweep.split(",")], untrained=False,
+                         spacing=args.learned_spacing, near=args.learned_near,
+                         bins=args.learned_bins, heldout=heldout,
+                         log_every=max(args.learned_steps // 4, 1), time_reps=3,
+                         log=lambda s: print(s, file=sys.stderr, flush=True))
     keep = ("workload", "hidden", "bins", "spacing", "train_steps", "ms_per_train_step", "err_bar",
             "mlp_fwd_points", "mlp_fwd_ms", "mlp_bwd_points", "mlp_bwd_ms",
             "mlp_fwd_flop_per_point", "mlp_bwd_flop_per_point",
-            "n_final", "within_err_bar", "trained_err", "trained_err_seen", "rays_seen",
+            "mlp_bwd_recompute_flop_per_point", "training_rays",
+            "heldout_cameras", "select_err", "n_final", "within_err_bar", "heldout_err",
+            "heldout_within_err_bar", "trained_err", "trained_err_seen", "rays_seen",
             "grid_samples", "grid_ms",
             "learned_ms", "grid_rays_per_s", "learned_rays_per_s", "learned_over_grid")
-    out = {k: rec[k] for k in keep}
+    out = {k: rec[k] for k in keep if k in rec}
     out["final_loss"] = rec["loss"][-1][1]
-    return out
+    return out, extras
 
 
 def combined_vs_proposal(args):
@@ -251,7 +273,7 @@ def combined_vs_proposal(args):
     stand-in included) on all 2^20 rays at their fewest final samples within
     1e-3 mean rgb error of the grid renderer."""
     from train_proposal import run_combined
-    rec = run_combined(steps=args.combined_steps, train_stride=args.learned_train_stride,
+    rec = run_combined(steps=args.combined_steps, train_stride=args.combined_train_stride,
                        sweep=[int(s) for s in args.combined_sweep.split(",")],
                        log_every=max(args.combined_steps, 1), time_reps=3,
                        log=lambda s: print(s, file=sys.stderr, flush=True))
@@ -309,29 +331,156 @@ def measured_traffic(kernel):
     return float(rec["bytes_per_launch"])
 
 
-def cpu_baseline(w, every):
-    """The oracle on every `every`-th ray of the same workload (same steps)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, every, heldout=None):
+    """The oracle (binary64, plain loops, OpenMP over rays) timed on the host.
+
+    Legs: the headline workload on every `every`-th ray with all threads
+    (`value`) and on a smaller sample with one thread; the tiny workload whole,
+    with all threads and one; the unbounded workload on every 64th ray; the
+    proposal round at its full size (2^18 rays); one learned-estimator
+    training step on 2^10 rays (its cost at 2^20 rays extrapolated, and
+    labelled so); and, given `heldout` (rays of a held-out view), the plain
+    grid renderer's colours on every 4th of its rays, returned for the
+    learned-versus-grid error against the binary64 judge."""
     import oracle
+    import scenes
+    nthreads = oracle.num_threads()
+
+    def grid_path(wl, idx, grads=True):
+        o, d = wl.rays_o[idx], wl.rays_d[idx]
+        p = wl.fld.packed_params()
+        m = oracle.march(o, d, wl.bits, wl.res, n_levels=wl.n_levels,
+                         half_extent0=wl.half_extent0, dt0=wl.dt0)
+        s_ng, _ = oracle.field_at_samples(o, d, m["t0"], m["t1"], m["ray_id"], p)
+        kept, _ = oracle.transmittance_prefix(m["packed_info"], m["t0"], m["t1"],
+                                              s_ng.astype(np.float32), wl.t_min)
+        info, t0, t1, rid = oracle.gather_prefix(m["packed_info"], kept, m["t0"], m["t1"],
+                                                 m["ray_id"])
+        s, c = oracle.field_at_samples(o, d, t0, t1, rid, p)
+        s32, c32 = s.astype(np.float32), c.astype(np.float32)
+        out = oracle.render_fwd(info, t0, t1, s32, c32, want_weights=True)
+        if grads:
+            oracle.render_bwd(info, t0, t1, s32, c32, wl.grads[idx])
+        return out, (info, t0, t1)
+
+    def timed(fn):
+        t = time.perf_counter()
+        r = fn()
+        return time.perf_counter() - t, r
+
+    def leg(wl, idx, what, threads=None):
+        if threads:
+            oracle.set_num_threads(threads)
+        try:
+            dt, _ = timed(lambda: grid_path(wl, idx))
+        finally:
+            oracle.set_num_threads(nthreads)
+        return {"rays": int(len(idx)), "s": dt, "rays_per_s": len(idx) / dt,
+                "threads": threads or nthreads, "what": what}
+
+    legs = {}
     idx = np.arange(0, w.n_rays, every)
-    o, d = w.rays_o[idx], w.rays_d[idx]
-    p = w.fld.packed_params()
-    t = time.perf_counter()
-    m = oracle.march(o, d, w.bits, w.res, n_levels=w.n_levels, half_extent0=w.half_extent0,
-                     dt0=w.dt0)
-    s_ng, _ = oracle.field_at_samples(o, d, m["t0"], m["t1"], m["ray_id"], p)
-    kept, _ = oracle.transmittance_prefix(m["packed_info"], m["t0"], m["t1"],
-                                          s_ng.astype(np.float32), w.t_min)
-    info, t0, t1, rid = oracle.gather_prefix(m["packed_info"], kept, m["t0"], m["t1"],
-                                             m["ray_id"])
-    s, c = oracle.field_at_samples(o, d, t0, t1, rid, p)
-    s32, c32 = s.astype(np.float32), c.astype(np.float32)
-    oracle.render_fwd(info, t0, t1, s32, c32)
-    oracle.render_bwd(info, t0, t1, s32, c32, w.grads[idx])
-    dt = time.perf_counter() - t
-    return {"value": len(idx) / dt, "unit": "rays/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"every {every}th ray ({len(idx)} rays) of the same workload, full path "
-                      f"(dense march, FP64 field, filter, render fwd+bwd), {dt:.1f} s"}
+    head = leg(w, idx, f"1 ray in {every} of the benchmark workload")
+    legs["headline_1thread"] = leg(w, np.arange(0, w.n_rays, every * 32),
+                                   f"1 ray in {every * 32} of the benchmark workload",
+                                   threads=1)
+    tw = scenes.tiny()
+    legs["tiny"] = leg(tw, np.arange(tw.n_rays), "tiny workload, all 4096 rays")
+    legs["tiny_1thread"] = leg(tw, np.arange(tw.n_rays), "tiny workload, all 4096 rays",
+                               threads=1)
+    uw = scenes.unbounded()
+    legs["unbounded"] = leg(uw, np.arange(0, uw.n_rays, 64),
+                            "every 64th ray of the unbounded workload (4 x 128^3 cascade)")
+
+    # proposal round at full size: 128 uniform bins over the chord through the
+    # cube, the hidden-64 network in binary64, inverse CDF to 32 intervals,
+    # the 64-blob field, render fwd + bwd
+    def proposal_round():
+        o, d = scenes.sphere_rays(1 << 18)
+        fld = scenes.blob_field(64)
+        n = o.shape[0]
+        tn, tf = oracle.clip(o, d, (-1.5,) * 3, (1.5,) * 3)
+        hit = tn < tf
+        span = np.stack([np.where(hit, tn, 0), np.where(hit, tf, 0)], 1)
+        e = oracle.span_bins(span, 128).astype(np.float32)
+        sig = oracle.mlp_fwd(oracle.bin_midpoints(o, d, e), scenes.mlp_init(64), 64,
+                             scale=1.5).reshape(n, 128)
+        out, _, _ = oracle.resample(e, sig.astype(np.float32), 32)
+        t0 = out[:, :-1].astype(np.float32).ravel()
+        t1 = out[:, 1:].astype(np.float32).ravel()
+        rid = np.repeat(np.arange(n, dtype=np.int32), 32)
+        info = np.stack([np.arange(n) * 32, np.full(n, 32)], 1).astype(np.int32)
+        s, c = oracle.field_at_samples(o, d, t0, t1, rid, fld.packed_params())
+        s32, c32 = s.astype(np.float32), c.astype(np.float32)
+        oracle.render_fwd(info, t0, t1, s32, c32)
+        oracle.render_bwd(info, t0, t1, s32, c32, scenes.upstream_grads(n))
+        return n
+
+    dt, n = timed(proposal_round)
+    legs["proposal_round"] = {"rays": n, "s": dt, "rays_per_s": n / dt, "threads": nthreads,
+                              "what": "2^18 rays, 128 uniform bins, hidden-64 network, inverse "
+                                      "CDF to 32, field, render fwd + bwd"}
+
+    # one training step of the learned estimator on 2^10 rays of the unbounded
+    # workload: grid renderer targets, 16 disparity bins from t = 0.5, the
+    # hidden-128 network on the contracted encoding, proposal weights, loss,
+    # weights adjoint, network adjoint, Adam
+    def learned_step():
+        idx_t = np.arange(0, uw.n_rays, uw.n_rays >> 10)
+        o, d = uw.rays_o[idx_t], uw.rays_d[idx_t]
+        n, H, nb = len(idx_t), 128, 16
+        tgt, (info, t0, t1) = grid_path(uw, idx_t, grads=False)
+        h = uw.half_extent0 * 2 ** (uw.n_levels - 1)
+        e = oracle.disparity_bins(o, d, (-h,) * 3, (h,) * 3, nb, 0.5).astype(np.float32)
+        prm = scenes.mlp_init(H)
+        x = oracle.bin_midpoints(o, d, e)
+        t = time.perf_counter()
+        sig = oracle.mlp_fwd(x, prm, H, contract=True).reshape(n, nb).astype(np.float32)
+        dinfo = np.stack([np.arange(n) * nb, np.full(n, nb)], 1).astype(np.int32)
+        a, b = e[:, :-1].ravel(), e[:, 1:].ravel()
+        wp = oracle.render_fwd(dinfo, a, b, sig.ravel(), np.zeros((n * nb, 3), np.float32),
+                               want_weights=True)["weights"].reshape(n, nb)
+        _, dwp = oracle.hist_loss(info, t0, t1, tgt["weights"], e, wp)
+        ds = oracle.weights_bwd(dinfo, a, b, sig.ravel(), dwp.ravel())
+        g = oracle.mlp_bwd(x, prm, H, ds, contract=True)
+        z = np.zeros_like(g)
+        oracle.adam(prm, z, z, g, 1e-2)
+        return n, time.perf_counter() - t
+
+    (n_l, step_s) = learned_step()
+    legs["learned_step"] = {"rays": n_l, "s": step_s, "threads": nthreads,
+                            "extrapolated_s_at_2^20_rays": step_s * ((1 << 20) / n_l),
+                            "what": "one training step (network forward, proposal weights, "
+                                    "loss, weights adjoint, network adjoint, Adam) on 2^10 "
+                                    "rays x 16 bins, hidden 128; targets precomputed; the "
+                                    "2^20-ray figure is extrapolated, not measured"}
+    judge = None
+    if heldout is not None:
+        hidx = np.arange(0, heldout["rays_o"].shape[0], 4)
+        hw = scenes.Workload("heldout", uw.fld, uw.bits, uw.res, uw.n_levels, uw.half_extent0,
+                             heldout["rays_o"], heldout["rays_d"], uw.dt0)
+        dt, (out, _) = timed(lambda: grid_path(hw, hidx, grads=False))
+        legs["heldout_judge"] = {"rays": int(len(hidx)), "s": dt, "threads": nthreads,
+                                 "what": "binary64 grid renderer (forward) on every 4th ray of "
+                                         "the held-out report view"}
+        judge = (hidx, out["rgb"])
+    rec = {"value": head["rays_per_s"], "unit": "rays/s", "cores": nthreads, "kind": "oracle",
+           "cpu": _cpu_model(),
+           "sample": f"{head['what']} ({head['rays']} rays), full path (dense march, FP64 "
+                     f"field, filter, render fwd+bwd), {head['s']:.1f} s",
+           "legs": legs}
+    return rec, judge
 
 
 def main():
@@ -387,8 +536,22 @@ def main():
                                               if dom == "render_bwd" and "pattern_ms" in st
                                               else None)},
     }
+    extras = None
+    if "render_fwd" in ker:
+        # the forward render against 8 TB/s and against its own read pattern
+        fwd_bytes = BYTES["render_fwd"](N, st["Sm"], st["S"])
+        fwd_gbps = fwd_bytes / (ker["render_fwd"][0] * 1e-3) / 1e9
+        rec["render_fwd_roofline"] = {
+            "achieved": fwd_gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": fwd_gbps / HBM_PEAK_GBS, "alg_bytes_per_launch": fwd_bytes,
+            # the probe reads 24 B per kept sample (the forward's per-sample bytes)
+            "read_pattern_ceiling_GBps": (24.0 * st["S"] / (st["read_pattern_ms"] * 1e-3) / 1e9
+                                          if "read_pattern_ms" in st else None)}
+        c = rec["render_fwd_roofline"]["read_pattern_ceiling_GBps"]
+        rec["render_fwd_roofline"]["frac_of_ceiling"] = fwd_gbps / c if c else None
+    extras = None
     if args.learned_steps > 0:
-        rec["learned_vs_grid"] = learned_vs_grid(args)
+        rec["learned_vs_grid"], extras = learned_vs_grid(args)
     if args.combined_steps > 0:
         rec["combined_vs_proposal"] = combined_vs_proposal(args)
     if args.pdf:
@@ -402,7 +565,16 @@ def main():
     if lv or pc:
         rec["mfma_roofline"] = mfma_roofline(lv, pc)
     if rank == 0 and args.cpu_sample > 0:
-        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        rec["cpu_baseline"], judge = cpu_baseline(w, args.cpu_sample, extras or None)
+        if judge is not None:
+            # the learned sampler and the GPU grid judge against the binary64
+            # grid renderer on the same held-out rays
+            hidx, rgb64 = judge
+            lv = rec["learned_vs_grid"]
+            lv["oracle_judged_rays"] = int(len(hidx))
+            lv["judge_vs_oracle_err"] = float(np.abs(extras["judge_rgb"][hidx] - rgb64).mean())
+            lv["heldout_err_vs_oracle"] = float(
+                np.abs(extras["learned_rgb"][hidx] - rgb64).mean())
     if rank == 0:
         print(json.dumps(rec), flush=True)
 

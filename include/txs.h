@@ -45,7 +45,7 @@ typedef int32_t txs_status;
 #define TXS_EHIP (-3)      /* a HIP runtime call or kernel launch failed */
 #define TXS_EOVERFLOW (-4) /* a count does not fit the int32 packed layout */
 
-#define TXS_ABI_VERSION 1
+#define TXS_ABI_VERSION 2
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* txs_last_error(void);
@@ -57,14 +57,39 @@ int32_t txs_abi_version(void);
  * res^3 cells; its occupancy bits start at bit l*res^3 of `bits`; the bit of
  * cell (x, y, z) is bit (i & 31) of word i >> 5 with i = x + res*(y + res*z).
  * n_levels > 1 is the cascade used for unbounded scenes (Section 3.2): each
- * level doubles the extent and the marching step.                           */
+ * level doubles the extent and the marching step.
+ *
+ * `coarse` (nullable) is the brick occupancy that lets the march skip empty
+ * space (the point of the spatial-skipping estimator, Section 3.1): bricks of
+ * 8^3 cells, cb = res/8 per axis, brick (bx, by, bz) holding the cells
+ * [8bx, 8bx+8) x [8by, 8by+8) x [8bz, 8bz+8).  Per level two arrays of
+ * txs_grid_coarse_words(res) / 2 words each, brick index j = bx + cb (by +
+ * cb bz), bit (j & 31) of word j >> 5: first "some cell of the brick is
+ * occupied", then "some cell of the 2x2x2 bricks (bx..bx+1, by..by+1,
+ * bz..bz+1) is occupied".  txs_grid_coarsen writes it from `bits`; it must
+ * describe the current bits (rebuild it after every change of bits), or the
+ * march may skip occupied cells.  NULL: every lattice point is tested.       */
 typedef struct {
   const uint32_t* bits; /* device, n_levels * res^3 / 32 words */
   int32_t res;          /* cells per axis: a power of two in [2, 1024] */
   int32_t n_levels;     /* 1 .. 8 */
   float center[3];
   float half_extent0;   /* > 0 */
+  const uint32_t* coarse; /* device, n_levels * txs_grid_coarse_words(res) words, or NULL */
 } txs_grid;
+
+/*
+ * Words of brick occupancy per level (both arrays) for a grid of res cells
+ * per axis: 2 * ceil((res/8)^3 / 32), or 0 for res < 8 (no bricks).
+ */
+int64_t txs_grid_coarse_words(int32_t res);
+
+/*
+ * Writes the brick occupancy of grid->bits into `coarse` (device,
+ * n_levels * txs_grid_coarse_words(res) words; grid->coarse is not read).
+ * res >= 8.
+ */
+txs_status txs_grid_coarsen(const txs_grid* grid, uint32_t* coarse, void* stream);
 
 typedef struct {
   float near_plane; /* rays start at max(near_plane, box entry); >= 0 */
@@ -82,9 +107,17 @@ typedef struct {
  * The occupancy test is evaluated in binary32 with the fixed operation order
  *   m = a + ((float)k + 0.5f)*dt,  u = ((o + m*d) - bmin) * (res / (bmax - bmin)),
  *   cell = clamp(floor(u), 0, res-1)
- * (no fused multiply-add), at every lattice point, so the emitted samples are
- * a deterministic function of the inputs that any binary32 evaluation of the
- * same recipe reproduces bit for bit.
+ * (no fused multiply-add), so the emitted samples are a deterministic
+ * function of the inputs that any binary32 evaluation of the same recipe at
+ * every lattice point reproduces bit for bit.
+ *
+ * Empty-space skipping: with grid->coarse set (res >= 8 and at most 4096
+ * words of brick occupancy over all levels, so that a block holds it in LDS;
+ * otherwise it is ignored), runs of 16 lattice points are first bounded in
+ * cell space from their end points (with a margin that covers every
+ * rounding of the recipe) and skipped when every brick the bound touches is
+ * empty; the points of the other runs are tested one by one.  The emitted
+ * samples are those of testing every point.
  *
  * txs_march_count writes counts[n_rays] (int32).
  * rays_o, rays_d: float [n_rays, 3]; rays_d need not be normalised (the
@@ -261,7 +294,8 @@ txs_status txs_weights_bwd(const int32_t* packed_info, int32_t fixed_count, int3
  *   mode TXS_PDF_WEIGHTS: F_{i+1} = sum_{j<=i} vals_j
  * Per ray: u' = u * F_n, i = the largest i in [0, n_bins] with F_i <= u',
  * t = e_i + (u' - F_i) / (F_{i+1} - F_i) * (e_{i+1} - e_i)  (t = e_n if
- * i = n_bins): the transmittance is taken linear inside a bin (Table 1).
+ * i = n_bins, in particular for u = 1 even when trailing bins carry no
+ * mass): the transmittance is taken linear inside a bin (Table 1).
  *   mode TXS_PDF_SIGMA_EXP: the CDF of TXS_PDF_SIGMA inverted exactly for a
  *   density constant inside each bin (T exponential there): with
  *   x = (u' - F_i) / (F_{i+1} - F_i) * (1 - exp(-tau_i)), tau_i = vals_i

@@ -26,6 +26,13 @@ txs_status txs_stream_probe(int64_t n_samples, const float* t0, const float* t1,
                             const float* sigma, const float* rgb, float* out_a, float* out_b,
                             void* stream);
 
+/* The reads of txs_render_fwd: t0, t1, sigma (float [n]) and rgb (float
+ * [n,3]) in its windowed layout; out (float [txs_read_probe_out_size()])
+ * receives one sum per lane of every wave (it only keeps the loads live). */
+int64_t txs_read_probe_out_size(void);
+txs_status txs_read_probe(int64_t n_samples, const float* t0, const float* t1,
+                          const float* sigma, const float* rgb, float* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,6 +71,12 @@ def num_threads() -> int:
     return int(L.oracle_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's loops over rays (timing only; results do not
+    depend on it)."""
+    lib().oracle_set_num_threads(C.c_int32(int(n)))
+
+
 # ----------------------------------------------------------------------------
 def clip(o, d, bmin, bmax, near=0.0, far=float("inf")):
     """Slab clip in the binary32 recipe -> (t_near, t_far) float32 arrays."""
@@ -338,6 +344,34 @@ def grid_ema(density, sigma, gamma, tau):
     lib().oracle_grid_ema(C.c_int64(d.shape[0]), _p(d), _p(_f64(sigma)), C.c_double(gamma),
                           C.c_double(tau), _p(occ))
     return d, occ.astype(bool)
+
+
+def grid_bricks(bits, res, n_levels=1):
+    """Brick occupancy of a grid (the spatial-skipping estimator's coarse level,
+    Section 3.1): bricks of 8^3 cells, per level (plain [b^3], block [b^3]) with
+    b = res/8, brick (bx, by, bz) at index bx + b (by + b bz); plain = some cell
+    of the brick occupied, block = some cell of the bricks (bx..bx+1, by..by+1,
+    bz..bz+1) occupied (clipped at the far faces).  -> bool [n_levels, 2, b^3]."""
+    b = res // 8
+    words = np.asarray(bits, np.uint32).reshape(-1)
+    occ = ((words[:, None] >> np.arange(32, dtype=np.uint32)) & 1).astype(bool).reshape(-1)
+    out = np.zeros((n_levels, 2, b ** 3), bool)
+    for l in range(n_levels):
+        cells = occ[l * res ** 3:(l + 1) * res ** 3].reshape(res, res, res)  # [z, y, x]
+        plain = np.zeros((b, b, b), bool)
+        for bz in range(b):
+            for by in range(b):
+                for bx in range(b):
+                    plain[bz, by, bx] = cells[8 * bz:8 * bz + 8, 8 * by:8 * by + 8,
+                                              8 * bx:8 * bx + 8].any()
+        block = np.zeros_like(plain)
+        for bz in range(b):
+            for by in range(b):
+                for bx in range(b):
+                    block[bz, by, bx] = plain[bz:bz + 2, by:by + 2, bx:bx + 2].any()
+        out[l, 0] = plain.reshape(-1)
+        out[l, 1] = block.reshape(-1)
+    return out
 
 
 def march_span(o, d, bits, res, **march_kw):

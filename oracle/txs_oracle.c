@@ -500,6 +500,16 @@ EXPORT int32_t oracle_num_threads(void) {
 #endif
 }
 
+/* Threads the loops over rays use from now on (timing of the oracle with one
+ * thread and with all cores; no effect on any result). */
+EXPORT void oracle_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /*
  * Update of the occupancy-grid estimator (Section 3.1 "Spatial Skipping";
  * the update column of Table 1's occupancy-grid row): the density cached per

@@ -15,7 +15,8 @@ from .ops import (GridSpec, MlpSpec, adam_step, blob_field, compact_rows, dispar
                   march_count, march_count_contracted, march_fill, march_fill_contracted,
                   march_span, merge_edges, mlp_param_count, prop_mlp_bwd,
                   prop_mlp_fwd, render_bwd, render_fwd, resample, resample_intervals,
-                  span_bins, stream_probe, transmittance_prefix, uniform_bins, weights_bwd)
+                  read_probe, span_bins, stream_probe, transmittance_prefix, uniform_bins,
+                  weights_bwd)
 from .pipeline import (OccupancyGrid, Packed, RenderFn, filter_transmittance, march,
                        march_contracted, pdf_render, rendering, rendering_dense, sampling)
 

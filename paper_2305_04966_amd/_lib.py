@@ -23,7 +23,8 @@ class TxsError(RuntimeError):
 
 class Grid(C.Structure):
     _fields_ = [("bits", C.c_void_p), ("res", C.c_int32), ("n_levels", C.c_int32),
-                ("center", C.c_float * 3), ("half_extent0", C.c_float)]
+                ("center", C.c_float * 3), ("half_extent0", C.c_float),
+                ("coarse", C.c_void_p)]
 
 
 class MarchParams(C.Structure):
@@ -42,6 +43,8 @@ GP, MP, MLP = C.POINTER(Grid), C.POINTER(MarchParams), C.POINTER(Mlp)
 SIGNATURES = {
     "txs_last_error": (C.c_char_p, []),
     "txs_abi_version": (I32, []),
+    "txs_grid_coarse_words": (I64, [I32]),
+    "txs_grid_coarsen": (I32, [GP, P, P]),
     "txs_march_count": (I32, [GP, MP, P, P, I32, P, P]),
     "txs_scan_workspace_size": (SZ, [I32]),
     "txs_exclusive_scan": (I32, [P, I32, P, P, P, SZ, P]),
@@ -67,6 +70,8 @@ SIGNATURES = {
     "txs_hist_loss": (I32, [P, I32, I64, P, P, P, I32, P, P, F32, P, P, P]),
     "txs_adam_step": (I32, [P, P, P, P, I64, F32, F32, F32, F32, I32, P]),
     "txs_stream_probe": (I32, [I64, P, P, P, P, P, P, P]),
+    "txs_read_probe_out_size": (I64, []),
+    "txs_read_probe": (I32, [I64, P, P, P, P, P, P]),
     "txs_grid_points": (I32, [GP, P, P, P]),
     "txs_grid_ema": (I32, [I64, P, P, F32, F32, P, P]),
     "txs_march_span": (I32, [GP, MP, P, P, I32, P, P, P]),

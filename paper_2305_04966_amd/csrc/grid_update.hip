@@ -72,8 +72,83 @@ __global__ __launch_bounds__(256) void grid_ema_kernel(int64_t n, float* __restr
   if (lane() == 32 && c < n) bits[c0 >> 5 | 1] = (uint32_t)(m >> 32);
 }
 
+// Brick occupancy of the grid (the march's empty-space skipping): bricks of
+// 8^3 cells, per level a plain array (some cell of the brick occupied) and a
+// block array (some cell of the 2x2x2 bricks starting at the brick occupied).
+constexpr int kBrickShift = 3;
+
+__global__ __launch_bounds__(256) void clear_words_kernel(int64_t n, uint32_t* __restrict__ w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = 0u;
+}
+
+// One thread per brick: the OR of its 64 rows of 8 cells (8-aligned runs of
+// x, so each row is one byte of one grid word); an occupied brick sets its
+// plain bit and the block bit of every brick whose 2x2x2 block holds it.
+// Integer OR is order-independent, so the result is deterministic.
+__global__ __launch_bounds__(256) void coarsen_kernel(const uint32_t* __restrict__ bits,
+                                                      int32_t res_shift, int32_t n_levels,
+                                                      int64_t half_words,
+                                                      uint32_t* __restrict__ coarse) {
+  const int cs = res_shift - kBrickShift;
+  const int64_t per_level = (int64_t)1 << (3 * cs);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per_level * n_levels) return;
+  const int l = (int)(i >> (3 * cs));
+  const int64_t j = i & (per_level - 1);
+  const int cmask = (1 << cs) - 1;
+  const int bx = (int)(j & cmask), by = (int)((j >> cs) & cmask), bz = (int)(j >> (2 * cs));
+  const int64_t cells = (int64_t)1 << (3 * res_shift);
+  const uint32_t* lv = bits + ((l * cells) >> 5);
+  uint32_t any = 0u;
+  for (int z = 0; z < 8; ++z)
+    for (int y = 0; y < 8; ++y) {
+      const int64_t c = ((int64_t)(8 * bx)) |
+                        ((((int64_t)(8 * by + y)) | ((int64_t)(8 * bz + z) << res_shift))
+                         << res_shift);
+      any |= (lv[c >> 5] >> (c & 31)) & 0xffu;
+    }
+  if (!any) return;
+  uint32_t* plain = coarse + 2 * l * half_words;
+  uint32_t* block = plain + half_words;
+  atomicOr(&plain[j >> 5], 1u << (j & 31));
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const int x = bx - dx, y = by - dy, z = bz - dz;
+        if (x < 0 || y < 0 || z < 0) continue;
+        const int64_t k = x | ((y | ((int64_t)z << cs)) << cs);
+        atomicOr(&block[k >> 5], 1u << (k & 31));
+      }
+}
+
 }  // namespace
 }  // namespace txs
+
+extern "C" int64_t txs_grid_coarse_words(int32_t res) {
+  if (res < 8 || res > 1024 || (res & (res - 1)) != 0) return 0;
+  const int64_t b = (int64_t)(res / 8) * (res / 8) * (res / 8);
+  return 2 * ((b + 31) / 32);
+}
+
+extern "C" txs_status txs_grid_coarsen(const txs_grid* grid, uint32_t* coarse, void* stream) {
+  using namespace txs;
+  clear_error();
+  TXS_REQUIRE(grid && grid->bits && coarse, "txs_grid_coarsen: null pointer");
+  const int res = grid->res;
+  TXS_REQUIRE(res >= 8 && res <= 1024 && (res & (res - 1)) == 0,
+              "txs_grid_coarsen: res must be a power of two in [8,1024], got %d", res);
+  TXS_REQUIRE(grid->n_levels >= 1 && grid->n_levels <= 8, "txs_grid_coarsen: bad n_levels");
+  const int64_t words = txs_grid_coarse_words(res) * grid->n_levels;
+  hipLaunchKernelGGL(clear_words_kernel, dim3(grid_1d(words, 256)), dim3(256), 0,
+                     as_stream(stream), words, coarse);
+  const int shift = __builtin_ctz((unsigned)res);
+  const int64_t bricks = ((int64_t)1 << (3 * (shift - kBrickShift))) * grid->n_levels;
+  hipLaunchKernelGGL(coarsen_kernel, dim3(grid_1d(bricks, 256)), dim3(256), 0,
+                     as_stream(stream), grid->bits, shift, grid->n_levels,
+                     txs_grid_coarse_words(res) / 2, coarse);
+  return launch_status("txs_grid_coarsen");
+}
 
 extern "C" txs_status txs_grid_points(const txs_grid* grid, const float* u, float* points,
                                       void* stream) {

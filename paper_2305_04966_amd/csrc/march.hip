@@ -1,12 +1,27 @@
 // Occupancy-grid ray marching (spatial-skipping estimator, Section 3.1 and
 // Table 1 second row; cascaded levels for unbounded scenes, Section 3.2).
 //
-// One wave marches one ray: its 64 lanes test 64 consecutive lattice points
-// at a time with the binary32 recipe of txs.h (contraction disabled in this
-// file), a ballot collects the occupied ones and a lane-rank (mbcnt) packs
-// them, so the fill pass writes each ray's samples as contiguous, coalesced
-// runs.  Every lattice point is tested, so the emitted samples are the dense
-// definition exactly.
+// One wave marches one ray: its 64 lanes test 64 lattice points at a time
+// with the binary32 recipe of txs.h (contraction disabled in this file), a
+// ballot collects the occupied ones and a lane-rank (mbcnt) packs them, so the
+// fill pass writes each ray's samples as contiguous, coalesced runs.
+//
+// Empty-space skipping.  Given the grid's brick occupancy (8^3-cell bricks,
+// staged in LDS per block), a segment is first walked in runs of kChunk
+// lattice points, one run per lane: the cell coordinates of a run's points
+// lie between those of its two end points (the recipe's u is monotone in the
+// midpoint m up to its rounding, which a per-axis margin covers), so a run
+// whose bounding bricks are all empty holds no occupied point.  The points of
+// the remaining runs are then tested one by one, four runs per 64 lanes, in k
+// order (or, when most runs of the window remain, the window's points in
+// order without the run list).  Skipped points are exactly points that are
+// not occupied, so the emitted samples are those of testing every lattice
+// point.  Without brick occupancy (or over contracted space, where the path
+// bends in cell space) every point is tested.
+//
+// A block of four waves marches 64 consecutive rays (16 per wave) after
+// copying the brick occupancy of every level into LDS (1 KiB for one 128^3
+// level).
 #pragma clang fp contract(off)
 
 #include <cmath>
@@ -20,10 +35,20 @@ constexpr int kMaxLevels = 8;
 constexpr int32_t kLatticeLimit = 1 << 24;  // k stays exact in binary32
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
+// rays per block: waves live for several rays, so that the launch of waves
+// (a fixed cost per wave) does not bound the march of short rays
+constexpr int kRaysPerBlock = 64;
+constexpr int kChunk = 16;                  // lattice points per run of the skipping pass
+constexpr int kDenseRuns = 48;              // more maybe-occupied runs of 63: test the window in order
+constexpr int kBrickShift = 3;              // bricks of 8^3 cells
+constexpr int kCoarseLdsWords = 4096;       // brick occupancy staged per block (16 KiB)
+constexpr int kListLen = kWave + 16;        // run list per wave, sentinel-padded
+constexpr int kSentinelRun = 1 << 21;       // a run beyond every segment's last point
 
 struct MarchArgs {
   const uint32_t* bits;
   int32_t res;
+  int32_t res_shift;  // log2(res)
   int32_t n_levels;
   int32_t level_words;
   float center[3];
@@ -31,6 +56,10 @@ struct MarchArgs {
   float near_plane, far_plane, dt0;
   int32_t max_per_ray;
   float inv_scale;  // contracted lookup: 1 / contract_scale
+  // brick occupancy (skipping kernels only)
+  const uint32_t* coarse;
+  int32_t cshift;       // log2(bricks per axis)
+  int32_t coarse_half;  // words of one of a level's two arrays
 };
 
 // Level-l box and grid scale, evaluated exactly as the recipe defines them.
@@ -87,7 +116,7 @@ struct Lattice {
   LevelBox box;
   const uint32_t* bits;
   float a, b, dt, resf;
-  int res;
+  int res, res_shift;
   float center[3], inv_scale;  // contracted lookup
 };
 
@@ -100,6 +129,7 @@ __device__ __forceinline__ Lattice lattice(const MarchArgs& g, float a, float b,
   p.b = b;
   p.dt = g.dt0 * (float)(1 << l);
   p.res = g.res;
+  p.res_shift = g.res_shift;
   p.resf = (float)g.res;
 #pragma unroll
   for (int c = 0; c < 3; ++c) p.center[c] = g.center[c];
@@ -146,21 +176,45 @@ __device__ __forceinline__ bool probe(const Lattice& p, const float o[3], const 
       for (int c = 0; c < 3; ++c) x[c] = o[c] + m * d[c];
       idx = contracted_cell(p, x);
     } else {
-      int cell[3];
+      uint32_t cell[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float x = o[c] + m * d[c];
         const float u = (x - p.box.bmin[c]) * p.box.scale[c];
-        // clamp of the floor to [0, res - 1] as one median-of-three (u is
-        // never NaN here, so it equals min(max(floor(u), 0), res - 1))
-        cell[c] = (int)__builtin_amdgcn_fmed3f(floorf(u), 0.0f, p.resf - 1.0f);
+        // clamp(floor(u), 0, res - 1) as the truncation of the clamped u: for
+        // a u that is not NaN both give floor(u) inside [0, res - 1] and the
+        // bound outside it (one median-of-three and one conversion)
+        cell[c] = (uint32_t)__builtin_amdgcn_fmed3f(u, 0.0f, p.resf - 1.0f);
       }
-      idx = cell[0] + p.res * (cell[1] + p.res * cell[2]);
+      idx = (int32_t)(cell[0] | ((cell[1] | (cell[2] << p.res_shift)) << p.res_shift));
     }
-    word = p.bits[idx >> 5];
+    word = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(p.bits) +
+                                              (((uint32_t)idx >> 3) & ~3u));
     sh = idx & 31;
   }
   return valid;
+}
+
+// Grid word of the lattice point with (float)k + 1/2 = kh on a cascade level
+// (the recipe of probe()); bit = the cell's bit position in the word.  The
+// clamp keeps the address inside the level's grid for any k, so the load
+// needs no branch; the caller decides whether the point belongs to the
+// segment.  The word's byte offset fits 32 bits: a scalar base and a 32-bit
+// lane offset.
+__device__ __forceinline__ uint32_t cell_word(const Lattice& p, const float o[3],
+                                              const float d[3], float kh, uint32_t& bit) {
+  const float m = p.a + kh * p.dt;
+  uint32_t cell[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float x = o[c] + m * d[c];
+    const float u = (x - p.box.bmin[c]) * p.box.scale[c];
+    cell[c] = (uint32_t)__builtin_amdgcn_fmed3f(u, 0.0f, p.resf - 1.0f);
+  }
+  const uint32_t idx = cell[0] | ((cell[1] | (cell[2] << p.res_shift)) << p.res_shift);
+  bit = idx & 31u;
+  return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(p.bits) +
+                                            ((idx >> 3) & ~3u));
 }
 
 // One segment [a, b) on level l.  Each step tests kGroups groups of 64
@@ -176,19 +230,38 @@ __device__ __forceinline__ int32_t march_segment(const MarchArgs& g, const float
                                                  int32_t n, int32_t cap, Emit& em) {
   const Lattice p = lattice<kContract>(g, a, b, l);
   const int ln = lane();
+  const float lane_h = (float)ln + 0.5f;
+  // kLatticeLimit is a multiple of 64 kGroups, so every k of a step is below it
+  static_assert(kLatticeLimit % (kWave * kGroups) == 0, "lattice limit");
   for (int32_t k0 = 0; k0 < kLatticeLimit; k0 += kWave * kGroups) {
     bool valid[kGroups], occ[kGroups];
     uint32_t word[kGroups];
     int32_t sh[kGroups];
 #pragma unroll
-    for (int q = 0; q < kGroups; ++q)
-      valid[q] = probe<kContract>(p, o, d, k0 + kWave * q + ln, word[q], sh[q]);
+    for (int q = 0; q < kGroups; ++q) {
+      if (kContract) {
+        valid[q] = probe<kContract>(p, o, d, k0 + kWave * q + ln, word[q], sh[q]);
+      } else {
+        // (float)k + 1/2 as a scalar plus a lane constant: exact below 2^24
+        const float kh = (float)(k0 + kWave * q) + lane_h;
+        uint32_t bt;
+        word[q] = cell_word(p, o, d, kh, bt);
+        sh[q] = (int32_t)bt;
+        valid[q] = p.a + kh * p.dt < p.b;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < kGroups; ++q) occ[q] = valid[q] && ((word[q] >> sh[q]) & 1u);
+    // every group's ballot before any early exit: the loads of all groups
+    // then stay in flight together (a convergent ballot is not sunk into a
+    // branch)
+    uint64_t masks[kGroups];
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) masks[q] = __ballot(occ[q]);
 #pragma unroll
     for (int q = 0; q < kGroups; ++q) {
       const int32_t k = k0 + kWave * q + ln;
-      const uint64_t mask = __ballot(occ[q]);
+      const uint64_t mask = masks[q];
       if (kMode == kSpan && mask != 0) {
         // the fill pass's binary32 t0 at the lowest occupied k
         const int32_t kf = k0 + kWave * q + (int32_t)__builtin_ctzll(mask);
@@ -226,6 +299,157 @@ __device__ __forceinline__ int32_t last_lattice_point(float a, float b, float dt
   return k;
 }
 
+// Brick occupancy of one level as staged in LDS: the plain array, then the
+// 2x2x2-block array.
+struct Bricks {
+  const uint32_t* plain;
+  const uint32_t* block;
+  int cshift;
+};
+
+// One segment [a, b) on level l with empty-space skipping (see the top of the
+// file).  Pass 1: lane j < 63 bounds run c0 + j (lattice points
+// [kChunk (c0 + j), kChunk (c0 + j + 1))) by the recipe's u at its first
+// point and at the next run's first point (lane j + 1's); lane 63 only
+// supplies that bound.  Every u of the run lies within 2 delta of the
+// interval between the two, delta the rounding bound of one evaluation of the
+// recipe, so the clamped floors of the widened interval bound the run's
+// cells.  The run may hold an occupied point only if the brick of those
+// bounds (one brick) or the 2x2x2 block starting at the lower brick (when the
+// bounds span at most two bricks per axis) is occupied; wider bounds count as
+// occupied.  Pass 2 tests the points of the maybe-occupied runs, four runs
+// per 64 lanes, in k order, exactly as the dense march does; a window where
+// more than kDenseRuns of its 63 runs remain is tested point by point in
+// order instead.
+template <int kMode>
+__device__ __forceinline__ int32_t march_segment_skip(const MarchArgs& g, const Bricks& br,
+                                                      int* list, const float o[3],
+                                                      const float d[3], float a, float b, int l,
+                                                      int32_t n, int32_t cap, Emit& em) {
+  const Lattice p = lattice<false>(g, a, b, l);
+  const int32_t kmax = last_lattice_point(a, b, p.dt);
+  if (kmax < 0) return n;
+  const int ln = lane();
+  // rounding bound of u = ((o + m d) - bmin) scale per axis (each of the four
+  // operations rounds once): |u - exact| <= scale u_r (4|m d| + 3|o| + 2|bmin|)
+  // (1 + 1e-6) with u_r = 2^-24; 2^-20 (scale (2 m_max|d| + 2|o| + 2|bmin|) +
+  // res) exceeds it at least fourfold for any m of this segment's runs
+  const float m_max = fmaxf(fabsf(a), fabsf(b) + (float)(kChunk + 2) * p.dt);
+  float marg[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    marg[c] = 2.0f * 0x1p-20f *
+              (p.box.scale[c] * (2.0f * m_max * fabsf(d[c]) + 2.0f * fabsf(o[c]) +
+                                 2.0f * fabsf(p.box.bmin[c])) + p.resf);
+  const int sh = br.cshift;
+  const int32_t n_runs = kmax / kChunk + 1;
+  for (int32_t c0 = 0; c0 < n_runs; c0 += kWave - 1) {
+    const int32_t ks = kChunk * (c0 + ln);
+    const float ms = a + ((float)ks + 0.5f) * p.dt;
+    float u[3], un[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = ((o[c] + ms * d[c]) - p.box.bmin[c]) * p.box.scale[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) un[c] = dpp<kWaveShl1>(u[c], u[c]);  // lane + 1's u
+    bool maybe = false;
+    if (ln < kWave - 1 && c0 + ln < n_runs) {
+      int lo[3], hi[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float u0 = fminf(u[c], un[c]) - marg[c], u1 = fmaxf(u[c], un[c]) + marg[c];
+        lo[c] = (int)__builtin_amdgcn_fmed3f(u0, 0.0f, p.resf - 1.0f) >> kBrickShift;
+        hi[c] = (int)__builtin_amdgcn_fmed3f(u1, 0.0f, p.resf - 1.0f) >> kBrickShift;
+      }
+      const int j = lo[0] | ((lo[1] | (lo[2] << sh)) << sh);
+      const int w0 = hi[0] - lo[0], w1 = hi[1] - lo[1], w2 = hi[2] - lo[2];
+      if ((w0 | w1 | w2) == 0) maybe = (br.plain[j >> 5] >> (j & 31)) & 1u;
+      else if (w0 <= 1 && w1 <= 1 && w2 <= 1) maybe = (br.block[j >> 5] >> (j & 31)) & 1u;
+      else maybe = true;
+    }
+    const uint64_t runs = __ballot(maybe);
+    if (runs == 0) continue;
+    const int nr = __popcll(runs);
+    // one step: two groups of 64 points, kq[q] the lane's point of group q
+    // (valid when inside the segment and below k_end); their grid-word loads
+    // stay in flight together.  Returns true when the ray is done.
+    auto step = [&](const int32_t (&kq)[kGroups], int32_t k_end) -> bool {
+      bool valid[kGroups];
+      uint32_t word[kGroups], bit[kGroups];
+#pragma unroll
+      for (int q = 0; q < kGroups; ++q) {
+        valid[q] = kq[q] <= kmax && kq[q] < k_end;
+        word[q] = cell_word(p, o, d, (float)kq[q] + 0.5f, bit[q]);
+      }
+      bool occs[kGroups];
+      uint64_t masks[kGroups];
+#pragma unroll
+      for (int q = 0; q < kGroups; ++q) {
+        occs[q] = valid[q] && ((word[q] >> bit[q]) & 1u);
+        masks[q] = __ballot(occs[q]);  // all ballots first: loads stay in flight together
+      }
+#pragma unroll
+      for (int q = 0; q < kGroups; ++q) {
+        const uint64_t mask = masks[q];
+        if (kMode == kSpan && mask != 0) {
+          const int32_t kf = readlane(kq[q], (int)__builtin_ctzll(mask));
+          em.lo = a + (float)kf * p.dt;
+          n += __popcll(mask);
+          return true;
+        }
+        if (kMode == kFill && occs[q]) {
+          const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+          const int64_t pos = em.base + n + rank;
+          if ((cap == 0 || n + rank < cap) && n + rank < em.count && pos < em.capacity) {
+            const float kf = (float)kq[q];
+            em.t0[pos] = a + kf * p.dt;
+            em.t1[pos] = fminf(a + (kf + 1.0f) * p.dt, b);
+            if (em.ray_id) em.ray_id[pos] = em.ray;
+          }
+        }
+        n += __popcll(mask);
+        if (cap > 0 && n >= cap) {
+          n = cap;
+          return true;
+        }
+      }
+      return false;
+    };
+    if (nr > kDenseRuns) {
+      // most runs of the window may hold samples: its points in order, as
+      // the dense march does (no list)
+      const int32_t k_end = kChunk * min(c0 + kWave - 1, n_runs);
+      for (int32_t k0 = kChunk * c0; k0 < k_end; k0 += kWave * kGroups) {
+        int32_t kq[kGroups];
+#pragma unroll
+        for (int q = 0; q < kGroups; ++q) kq[q] = k0 + kWave * q + ln;
+        if (step(kq, k_end)) return n;
+      }
+      continue;
+    }
+    // the maybe-occupied runs in k order at list[0, nr), every other lane's
+    // sentinel after them (entries kWave.. hold the sentinel already), so the
+    // steps read the list without a branch
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(runs >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)runs, 0u));
+    list[maybe ? rank : nr + ln - rank] = maybe ? c0 + ln : kSentinelRun;
+    wave_sync();
+    constexpr int kRunsPerGroup = kWave / kChunk;
+    for (int i0 = 0; i0 < nr; i0 += kGroups * kRunsPerGroup) {
+      int32_t kq[kGroups];
+#pragma unroll
+      for (int q = 0; q < kGroups; ++q)
+        kq[q] = kChunk * list[i0 + kRunsPerGroup * q + ln / kChunk] + (ln % kChunk);
+      if (step(kq, kLatticeLimit)) {
+        wave_sync();
+        return n;
+      }
+    }
+    wave_sync();  // the list is rewritten by the next run window
+  }
+  return n;
+}
+
 // Highest occupied lattice point of segment [a, b) on level l, scanning k
 // downwards from the last point kGroups groups of 64 at a time; on success
 // em.hi = the fill pass's binary32 t1 of that sample.
@@ -257,8 +481,9 @@ __device__ __forceinline__ bool span_back(const MarchArgs& g, const float o[3], 
   return false;
 }
 
-template <int kMode, bool kContract>
-__device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const float o[3], const float d[3],
+template <int kMode, bool kContract, bool kSkip>
+__device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const uint32_t* coarse_lds,
+                                             int* list, const float o[3], const float d[3],
                                              Emit& em) {
   float inv[3];
 #pragma unroll
@@ -297,6 +522,14 @@ __device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const float o[3
     }
     return true;
   };
+  auto forward = [&](int l, float a, float b, int32_t n, int32_t cap) {
+    if (kSkip) {
+      const Bricks br{coarse_lds + 2 * l * g.coarse_half,
+                      coarse_lds + (2 * l + 1) * g.coarse_half, g.cshift};
+      return march_segment_skip<kMode>(g, br, list, o, d, a, b, l, n, cap, em);
+    }
+    return march_segment<kMode, kContract>(g, o, d, a, b, l, n, cap, em);
+  };
 
   const int32_t cap = g.max_per_ray;
   int32_t n = 0;
@@ -306,8 +539,7 @@ __device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const float o[3
     // the first occupied point going forward, then the last one going back
     int s_first = -1;
     for (int s = 0; s < 2 * L - 1 && s_first < 0; ++s)
-      if (segment(s, l, a, b) && march_segment<kSpan, kContract>(g, o, d, a, b, l, 0, 0, em) > 0)
-        s_first = s;
+      if (segment(s, l, a, b) && forward(l, a, b, 0, 0) > 0) s_first = s;
     if (s_first < 0) return 0;
     for (int s = 2 * L - 2; s >= s_first; --s)
       if (segment(s, l, a, b) && span_back<kContract>(g, o, d, a, b, l, em)) break;
@@ -315,41 +547,74 @@ __device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const float o[3
   }
   for (int s = 0; s < 2 * L - 1; ++s) {
     if (!segment(s, l, a, b)) continue;
-    n = march_segment<kMode, kContract>(g, o, d, a, b, l, n, cap, em);
+    n = forward(l, a, b, n, cap);
     if (cap > 0 && n >= cap) break;
   }
   return n;
 }
 
-template <int kMode, bool kContract>
+// Dynamic LDS of a march block: the brick occupancy of every level (skipping
+// kernels), then one 64-entry run list per wave.
+template <int kMode, bool kContract, bool kSkip>
 __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float* __restrict__ ro,
                                                        const float* __restrict__ rd,
                                                        int32_t n_rays, int32_t* counts,
                                                        const int32_t* __restrict__ info,
                                                        int64_t capacity, float* t0, float* t1,
                                                        int32_t* ray_id, float* span) {
-  // one ray per wave; the ray index is wave-uniform
-  const int32_t r = __builtin_amdgcn_readfirstlane(
-      (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
-  if (r >= n_rays) return;
-  float o[3], d[3];
+  extern __shared__ uint32_t lds[];
+  const int coarse_words = kSkip ? 2 * g.n_levels * g.coarse_half : 0;
+  if (kSkip) {
+    for (int i = threadIdx.x; i < coarse_words; i += kBlock) lds[i] = g.coarse[i];
+    __syncthreads();
+  }
+  const int w = threadIdx.x / kWave;
+  int* list = reinterpret_cast<int*>(lds + coarse_words) + kListLen * w;
+  if (kSkip && lane() < kListLen - kWave) list[kWave + lane()] = kSentinelRun;
+  // a block marches kRaysPerBlock consecutive rays, its waves taking every
+  // kWavesPerBlock-th of them (neighbouring rays cost alike, so the waves
+  // finish together); the next ray's origin and direction load while the
+  // current one marches.  Ray indices are wave-uniform.
+  const int64_t base = (int64_t)blockIdx.x * kRaysPerBlock;
+  const int64_t end = min(base + kRaysPerBlock, (int64_t)n_rays);
+  int64_t r64 = base + w;
+  float on[3] = {0.0f, 0.0f, 0.0f}, dn[3] = {0.0f, 0.0f, 0.0f};
+  if (r64 < end) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    o[c] = ro[3 * (int64_t)r + c];
-    d[c] = rd[3 * (int64_t)r + c];
+    for (int c = 0; c < 3; ++c) {
+      on[c] = ro[3 * r64 + c];
+      dn[c] = rd[3 * r64 + c];
+    }
   }
-  Emit em{t0, t1, ray_id, 0, 0, capacity, r, 0.0f, 0.0f};
-  if (kMode == kFill) {
-    const int2 row = reinterpret_cast<const int2*>(info)[r];
-    em.base = row.x;
-    em.count = (row.x < 0 || row.y < 0) ? 0 : row.y;  // malformed row: nothing written
-  }
-  const int32_t n = march_ray<kMode, kContract>(g, o, d, em);
-  if (kMode == kCount && lane() == 0) counts[r] = n;
-  if (kMode == kSpan && lane() == 0) {
-    span[2 * (int64_t)r] = em.lo;
-    span[2 * (int64_t)r + 1] = em.hi;
-    counts[r] = n > 0 ? 1 : 0;
+  for (; r64 < end; r64 += kWavesPerBlock) {
+    const int32_t r = __builtin_amdgcn_readfirstlane((int32_t)r64);
+    float o[3], d[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      o[c] = on[c];
+      d[c] = dn[c];
+    }
+    const int64_t rn = r64 + kWavesPerBlock;
+    if (rn < end) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        on[c] = ro[3 * rn + c];
+        dn[c] = rd[3 * rn + c];
+      }
+    }
+    Emit em{t0, t1, ray_id, 0, 0, capacity, r, 0.0f, 0.0f};
+    if (kMode == kFill) {
+      const int2 row = reinterpret_cast<const int2*>(info)[r];
+      em.base = row.x;
+      em.count = (row.x < 0 || row.y < 0) ? 0 : row.y;  // malformed row: nothing written
+    }
+    const int32_t n = march_ray<kMode, kContract, kSkip>(g, lds, list, o, d, em);
+    if (kMode == kCount && lane() == 0) counts[r] = n;
+    if (kMode == kSpan && lane() == 0) {
+      span[2 * (int64_t)r] = em.lo;
+      span[2 * (int64_t)r + 1] = em.hi;
+      counts[r] = n > 0 ? 1 : 0;
+    }
   }
 }
 
@@ -373,6 +638,7 @@ txs_status make_args(const txs_grid* grid, const txs_march_params* p, MarchArgs&
   TXS_REQUIRE(p->max_per_ray >= 0, "txs_march: max_per_ray must be >= 0");
   g.bits = grid->bits;
   g.res = res;
+  g.res_shift = __builtin_ctz((unsigned)res);
   g.n_levels = grid->n_levels;
   g.level_words = (int32_t)(((int64_t)res * res * res + 31) / 32);
   for (int c = 0; c < 3; ++c) g.center[c] = grid->center[c];
@@ -382,11 +648,40 @@ txs_status make_args(const txs_grid* grid, const txs_march_params* p, MarchArgs&
   g.dt0 = p->dt0;
   g.max_per_ray = p->max_per_ray;
   g.inv_scale = 0.0f;
+  // brick occupancy: used when given, res >= 8 and small enough for LDS
+  g.coarse = nullptr;
+  g.cshift = 0;
+  g.coarse_half = 0;
+  const int64_t cw = txs_grid_coarse_words(res);
+  if (grid->coarse && cw > 0 && cw * grid->n_levels <= kCoarseLdsWords) {
+    g.coarse = grid->coarse;
+    g.cshift = g.res_shift - kBrickShift;
+    g.coarse_half = (int32_t)(cw / 2);
+  }
   return TXS_OK;
 }
 
 unsigned march_blocks(int32_t n_rays) {
-  return grid_1d(((int64_t)n_rays + kWavesPerBlock - 1) / kWavesPerBlock, 1);
+  return grid_1d(((int64_t)n_rays + kRaysPerBlock - 1) / kRaysPerBlock, 1);
+}
+
+// Launches one march kernel (skipping when the grid carries brick occupancy).
+template <int kMode, bool kContract>
+txs_status launch_march(const MarchArgs& g, void* stream, const float* ro, const float* rd,
+                        int32_t n_rays, int32_t* counts, const int32_t* info, int64_t capacity,
+                        float* t0, float* t1, int32_t* ray_id, float* span, const char* who) {
+  const bool skip = !kContract && g.coarse != nullptr;
+  const size_t lds = sizeof(uint32_t) * ((skip ? 2 * g.n_levels * g.coarse_half : 0) +
+                                         kWavesPerBlock * kListLen);
+  if (skip)
+    hipLaunchKernelGGL((march_kernel<kMode, kContract, !kContract>), dim3(march_blocks(n_rays)),
+                       dim3(kBlock), lds, as_stream(stream), g, ro, rd, n_rays, counts, info,
+                       capacity, t0, t1, ray_id, span);
+  else
+    hipLaunchKernelGGL((march_kernel<kMode, kContract, false>), dim3(march_blocks(n_rays)),
+                       dim3(kBlock), lds, as_stream(stream), g, ro, rd, n_rays, counts, info,
+                       capacity, t0, t1, ray_id, span);
+  return launch_status(who);
 }
 
 }  // namespace
@@ -402,10 +697,8 @@ extern "C" txs_status txs_march_count(const txs_grid* grid, const txs_march_para
   TXS_REQUIRE(n_rays >= 0, "txs_march_count: n_rays < 0");
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && counts, "txs_march_count: null array");
-  hipLaunchKernelGGL((march_kernel<kCount, false>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
-                     as_stream(stream), g, rays_o, rays_d, n_rays, counts, nullptr, 0, nullptr,
-                     nullptr, nullptr, nullptr);
-  return launch_status("txs_march_count");
+  return launch_march<kCount, false>(g, stream, rays_o, rays_d, n_rays, counts, nullptr, 0,
+                                     nullptr, nullptr, nullptr, nullptr, "txs_march_count");
 }
 
 extern "C" txs_status txs_march_fill(const txs_grid* grid, const txs_march_params* params,
@@ -420,10 +713,8 @@ extern "C" txs_status txs_march_fill(const txs_grid* grid, const txs_march_param
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && packed_info, "txs_march_fill: null array");
   TXS_REQUIRE(capacity == 0 || (t0 && t1), "txs_march_fill: null output");
-  hipLaunchKernelGGL((march_kernel<kFill, false>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
-                     as_stream(stream), g, rays_o, rays_d, n_rays, nullptr, packed_info, capacity,
-                     t0, t1, ray_id, nullptr);
-  return launch_status("txs_march_fill");
+  return launch_march<kFill, false>(g, stream, rays_o, rays_d, n_rays, nullptr, packed_info,
+                                    capacity, t0, t1, ray_id, nullptr, "txs_march_fill");
 }
 
 extern "C" txs_status txs_march_span(const txs_grid* grid, const txs_march_params* params,
@@ -437,10 +728,8 @@ extern "C" txs_status txs_march_span(const txs_grid* grid, const txs_march_param
   TXS_REQUIRE(n_rays >= 0, "txs_march_span: n_rays < 0");
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && span && hit, "txs_march_span: null array");
-  hipLaunchKernelGGL((march_kernel<kSpan, false>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
-                     as_stream(stream), g, rays_o, rays_d, n_rays, hit, nullptr, 0, nullptr,
-                     nullptr, nullptr, span);
-  return launch_status("txs_march_span");
+  return launch_march<kSpan, false>(g, stream, rays_o, rays_d, n_rays, hit, nullptr, 0, nullptr,
+                                    nullptr, nullptr, span, "txs_march_span");
 }
 
 extern "C" txs_status txs_march_count_contracted(const txs_grid* grid,
@@ -458,10 +747,9 @@ extern "C" txs_status txs_march_count_contracted(const txs_grid* grid,
   TXS_REQUIRE(n_rays >= 0, "txs_march_count_contracted: n_rays < 0");
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && counts, "txs_march_count_contracted: null array");
-  hipLaunchKernelGGL((march_kernel<kCount, true>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
-                     as_stream(stream), g, rays_o, rays_d, n_rays, counts, nullptr, 0, nullptr,
-                     nullptr, nullptr, nullptr);
-  return launch_status("txs_march_count_contracted");
+  return launch_march<kCount, true>(g, stream, rays_o, rays_d, n_rays, counts, nullptr, 0,
+                                    nullptr, nullptr, nullptr, nullptr,
+                                    "txs_march_count_contracted");
 }
 
 extern "C" txs_status txs_march_fill_contracted(const txs_grid* grid,
@@ -482,8 +770,7 @@ extern "C" txs_status txs_march_fill_contracted(const txs_grid* grid,
   if (n_rays == 0) return TXS_OK;
   TXS_REQUIRE(rays_o && rays_d && packed_info, "txs_march_fill_contracted: null array");
   TXS_REQUIRE(capacity == 0 || (t0 && t1), "txs_march_fill_contracted: null output");
-  hipLaunchKernelGGL((march_kernel<kFill, true>), dim3(march_blocks(n_rays)), dim3(kBlock), 0,
-                     as_stream(stream), g, rays_o, rays_d, n_rays, nullptr, packed_info, capacity,
-                     t0, t1, ray_id, nullptr);
-  return launch_status("txs_march_fill_contracted");
+  return launch_march<kFill, true>(g, stream, rays_o, rays_d, n_rays, nullptr, packed_info,
+                                   capacity, t0, t1, ray_id, nullptr,
+                                   "txs_march_fill_contracted");
 }

@@ -105,8 +105,11 @@ __device__ __forceinline__ void ray_invert(const RsArgs& a, int64_t r, const flo
   for (int k = ln; k <= a.n_out; k += kLanes) {
     const float uk = a.u ? a.u[r * (a.n_out + 1) + k] : (float)k / (float)a.n_out;
     const float up = uk * Fn;
-    // largest i in [0, n_bins] with F[i] <= up (F[0] = 0 <= up)
-    int lo = 0, hi = a.n_bins;
+    // largest i in [0, n_bins] with F[i] <= up (F[0] = 0 <= up).  u' = F_n
+    // (u = 1) is i = n_bins: F is non-decreasing, but its binary32 lane scan
+    // may put a bin of zero mass an ulp above F_n, which the search would
+    // otherwise stop at
+    int lo = up >= Fn ? a.n_bins : 0, hi = a.n_bins;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (F[mid] <= up) lo = mid;

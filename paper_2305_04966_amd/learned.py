@@ -90,6 +90,17 @@ class ProposalEstimator:
         """Proposal density at the bin midpoints -> float32 [N, n_bins]."""
         return ops.prop_mlp_fwd(self.spec, rays_o, rays_d, edges)
 
+    def density_at(self, points):
+        """Proposal density at arbitrary points [n, 3] -> float32 [n]: each point
+        is a one-bin row whose midpoint is t = 0 (so x = o exactly).  This is
+        the density an occupancy grid can cache when the network stands for a
+        field with learnable parameters (the grid update of Section 3.1)."""
+        n = points.shape[0]
+        d = torch.zeros_like(points)
+        d[:, 0] = 1.0
+        e = torch.zeros((n, 2), dtype=torch.float32, device=points.device)
+        return ops.prop_mlp_fwd(self.spec, points.contiguous(), d, e).view(-1)
+
     def sample(self, rays_o, rays_d, edges, n_out, u=None):
         """Inverse-CDF intervals from the proposal transmittance -> edges [N, n_out+1]."""
         sig = self.density(rays_o, rays_d, edges)

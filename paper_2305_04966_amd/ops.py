@@ -51,19 +51,44 @@ def _opt(t, name, dtype, shape=None):
 
 @dataclass
 class GridSpec:
-    """Occupancy grid: bits (uint32-in-int32 tensor), res, levels, box."""
+    """Occupancy grid: bits (uint32-in-int32 tensor), res, levels, box.
+
+    With skip=True (and res >= 8) the grid carries its brick occupancy
+    (`coarse`, built by txs_grid_coarsen when the spec is made), which the
+    march uses to skip empty space.  After changing `bits` in place, call
+    refresh() so that the brick occupancy describes the new bits."""
     bits: torch.Tensor
     res: int
     n_levels: int = 1
     center: tuple = (0.0, 0.0, 0.0)
     half_extent0: float = 1.5
+    skip: bool = True
+    coarse: torch.Tensor = None
+
+    def __post_init__(self):
+        if self.skip and self.coarse is None:
+            w = int(load().txs_grid_coarse_words(self.res))
+            if w > 0 and self.bits.numel() * 32 >= self.n_levels * self.res ** 3:
+                self.coarse = torch.empty(w * self.n_levels, dtype=torch.int32,
+                                          device=self.bits.device)
+                self.refresh()
+
+    def refresh(self):
+        """Rebuilds the brick occupancy from the current bits (no-op without it)."""
+        if self.coarse is not None:
+            g = self.struct()
+            check(load().txs_grid_coarsen(C.byref(g), _ptr(self.coarse), _stream()),
+                  "txs_grid_coarsen")
+        return self
 
     def struct_contracted(self) -> Grid:
         """The descriptor of a grid over contracted space (one res^3 level of bits)."""
         _need(self.bits, "grid.bits", torch.int32)
         if self.bits.numel() * 32 < self.res ** 3:
             raise ValueError("grid.bits holds fewer than res^3 bits")
-        return self._fill(Grid())
+        g = self._fill(Grid())
+        g.coarse = None
+        return g
 
     def struct(self) -> Grid:
         _need(self.bits, "grid.bits", torch.int32)
@@ -77,6 +102,7 @@ class GridSpec:
         g.n_levels = self.n_levels
         g.center = (C.c_float * 3)(*self.center)
         g.half_extent0 = self.half_extent0
+        g.coarse = None if self.coarse is None else self.coarse.data_ptr()
         return g
 
 
@@ -521,6 +547,19 @@ def stream_probe(t0, t1, sigma, rgb, out_a, out_b):
     check(load().txs_stream_probe(n, _ptr(t0), _ptr(t1), _ptr(sigma), _ptr(rgb), _ptr(out_a),
                                   _ptr(out_b), _stream()), "txs_stream_probe")
 
+
+def read_probe(t0, t1, sigma, rgb, out=None):
+    """Measurement support: the forward render's reads with trivial arithmetic."""
+    n = t0.shape[0]
+    for name, t in (("t0", t0), ("t1", t1), ("sigma", sigma)):
+        _need(t, name, torch.float32, (n,))
+    _need(rgb, "rgb", torch.float32, (n, 3))
+    size = int(load().txs_read_probe_out_size())
+    out = out if out is not None else torch.empty(size, dtype=torch.float32, device=t0.device)
+    _need(out, "out", torch.float32, (size,))
+    check(load().txs_read_probe(n, _ptr(t0), _ptr(t1), _ptr(sigma), _ptr(rgb), _ptr(out),
+                                _stream()), "txs_read_probe")
+    return out
 
 
 def march_span(grid: GridSpec, rays_o, rays_d, *, near=0.0, far=float("inf"), dt0):

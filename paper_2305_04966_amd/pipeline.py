@@ -180,6 +180,7 @@ class OccupancyGrid:
         sigma = density_fn(self.points(u))
         n = self.density.shape[0]
         ops.grid_ema(self.density, sigma, gamma, tau, self.grid.bits[:n // 32])
+        self.grid.refresh()  # the brick occupancy follows the new bits
 
     def update_every_n_steps(self, step, density_fn: Callable, n=16, gamma=0.95, tau=0.01,
                              u=None):

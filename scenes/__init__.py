@@ -219,6 +219,15 @@ def rig_rays(n_cams: int = 8, width: int = 512, height: int = 256, fov_deg: floa
     return np.concatenate(os), np.concatenate(ds)
 
 
+def rig_camera(index: int, width: int = 512, height: int = 256, fov_deg: float = 60.0,
+               radius: float = 3.0, seed: int = SEED_RAYS):
+    """Camera `index` of the seeded rig's eye sequence.  The eyes are drawn in
+    order from one generator, so cameras 0..n-1 are those of rig_rays(n) and
+    cameras n, n+1, ... are further views of the same rig (held-out views)."""
+    eye = random_eyes(index + 1, radius, seed)[index]
+    return look_at_camera(eye, width, height, fov_deg, fov_axis="x")
+
+
 # ----------------------------------------------------------------------------
 # other seeded inputs
 # ----------------------------------------------------------------------------

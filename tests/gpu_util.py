@@ -78,3 +78,24 @@ def bwd_condition(packed_info, t0, t1, sigma, v):
     tot = np.concatenate([[0.0], ca])[ends][seg]
     suffix = tot - ca
     return delta * (T_next * np.abs(v) + np.maximum(suffix, 0.0))
+
+
+def resample_tol(edges, vals, mode, out_ref, bins_ref):
+    """Inverse-CDF conditioning: a CDF error eps moves t by eps/(F_{i+1}-F_i) of the bin."""
+    e = edges.astype(np.float64)
+    v = vals.astype(np.float64)
+    if mode == 0:
+        F = -np.expm1(-np.cumsum(v * np.diff(e, axis=1), axis=1))
+    else:
+        F = np.cumsum(v, axis=1)
+    F = np.concatenate([np.zeros((F.shape[0], 1)), F], 1)
+    Fn = F[:, -1:]
+    uni = Fn[:, 0] <= 1e-12
+    F[uni] = np.linspace(0, 1, F.shape[1])
+    Fn = F[:, -1:]
+    i = np.minimum(bins_ref, e.shape[1] - 2)
+    dF = np.take_along_axis(F, i + 1, 1) - np.take_along_axis(F, i, 1)
+    width = np.take_along_axis(e, i + 1, 1) - np.take_along_axis(e, i, 1)
+    span = e[:, -1:] - e[:, :1]
+    return (1e-5 * np.abs(out_ref) + 1e-6 * span
+            + width * np.minimum(1.0, 4e-6 * Fn / np.maximum(dF, 1e-300)))

@@ -43,7 +43,7 @@ def test_binding_covers_the_header():
 def test_version_and_error_without_gpu(lib):
     lib.txs_abi_version.restype = C.c_int32
     lib.txs_last_error.restype = C.c_char_p
-    assert lib.txs_abi_version() == 1
+    assert lib.txs_abi_version() == 2
     # argument validation happens on the host before any launch
     lib.txs_resample.restype = C.c_int32
     st = lib.txs_resample(C.c_int32(4), C.c_int32(0), None, None, C.c_int32(0), C.c_int32(8),
@@ -52,6 +52,24 @@ def test_version_and_error_without_gpu(lib):
     assert b"n_bins" in lib.txs_last_error()
     lib.txs_scan_workspace_size.restype = C.c_size_t
     assert lib.txs_scan_workspace_size(C.c_int32(1 << 20)) >= 8 * 256
+
+
+def test_brick_occupancy_sizes(lib):
+    """Two arrays of ceil((res/8)^3 / 32) words per level; no bricks below res 8;
+    the coarsening refuses such grids on the host."""
+    lib.txs_grid_coarse_words.restype = C.c_int64
+    lib.txs_grid_coarse_words.argtypes = [C.c_int32]
+    assert lib.txs_grid_coarse_words(4) == 0
+    assert lib.txs_grid_coarse_words(8) == 2
+    assert lib.txs_grid_coarse_words(64) == 2 * 16
+    assert lib.txs_grid_coarse_words(128) == 2 * 128
+    assert lib.txs_grid_coarse_words(1024) == 2 * 128 ** 3 // 32
+    assert lib.txs_grid_coarse_words(100) == 0
+    from paper_2305_04966_amd._lib import Grid
+    g = Grid()
+    g.bits, g.res, g.n_levels, g.half_extent0 = 1024, 4, 1, 1.5
+    lib.txs_grid_coarsen.restype = C.c_int32
+    assert lib.txs_grid_coarsen(C.byref(g), C.c_void_p(4096), None) == -1
 
 
 def test_counts_past_int32_return_eoverflow(lib):

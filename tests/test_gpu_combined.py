@@ -20,7 +20,7 @@ import torch
 import oracle
 import scenes
 from gpu_util import dev, grid_spec, host
-from test_gpu_parity import resample_tol
+from gpu_util import resample_tol
 
 pytestmark = pytest.mark.gpu
 

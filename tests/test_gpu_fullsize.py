@@ -23,7 +23,7 @@ import oracle
 import scenes
 from gpu_util import assert_close, bwd_condition, dev, host
 from test_gpu_learned import assert_bf16_close, assert_grad_close, bf16_ulp  # noqa: F401
-from test_gpu_parity import resample_tol
+from gpu_util import resample_tol
 
 pytestmark = pytest.mark.gpu
 

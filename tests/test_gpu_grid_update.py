@@ -65,6 +65,110 @@ def test_estimator_update_then_march(gpu_lib):
     band = np.abs(sref - tau) <= 3e-4 * sref + 1e-6 * w.fld.peak  # binary32 field
     assert np.array_equal(occ[~band], (sref > tau)[~band])
     assert occ.any() and not occ.all()
+    # the march reads the bits the update wrote; the oracle marches its own
+    # bits, and every ray that never tests a band cell must agree bit for bit
     p = gpu_lib.march(grid, dev(w.rays_o), dev(w.rays_d), dt0=w.dt0)
-    ref = oracle.march(w.rays_o, w.rays_d, host(bits).view(np.uint32), res, dt0=w.dt0)
-    assert np.array_equal(host(p.packed_info), ref["packed_info"])
+    ref = oracle.march(w.rays_o, w.rays_d, scenes.pack_bits(sref > tau), res, dt0=w.dt0)
+    clear = _rays_clear_of(band, w, res, 1)
+    assert clear.mean() > 0.9
+    info = host(p.packed_info)
+    assert np.array_equal(info[clear, 1], ref["packed_info"][clear, 1])
+    if clear.all():
+        assert np.array_equal(info, ref["packed_info"])
+        assert np.array_equal(host(p.t0), ref["t0"])
+
+
+def _rays_clear_of(cells, w, res, n_levels):
+    """Rays whose dense march over a grid holding only `cells` finds no sample:
+    those rays never test one of these cells, so a decision there cannot
+    change their samples."""
+    m = oracle.march(w.rays_o, w.rays_d, scenes.pack_bits(cells), res, n_levels=n_levels,
+                     half_extent0=w.half_extent0, dt0=w.dt0)
+    return m["counts"] == 0
+
+
+def test_grid_update_on_learnable_field(gpu_lib):
+    """The grid estimator's update (Section 3.1, "Spatial Skipping"; Table 1,
+    update column; Algorithm 1's update_every_n_steps) on a field with
+    learnable parameters: the proposal network stands for the field and is
+    trained along the oracle's binary64 Adam trajectory (as in test_gpu_train);
+    every 8th step the grid caches its density at the cell centres (EMA,
+    gamma 0.95) through txs_prop_mlp_fwd, and the oracle does the same with its
+    bf16-emulated network at its binary64 cell centres.  The GPU density is
+    within 16 bf16 ulps (12.5%) of the emulated one at every point and within
+    2 ulps at 99.9% of them, so the cached density is within 12.5% too: outside
+    the band tau/1.13 <= D <= tau/0.87 the bits must agree, and outside a 2%
+    band at 99.9% of the cells.  The march is bit-exact on the oracle's bits;
+    on the GPU's own bits every ray's samples must contain those of the
+    oracle's bits without the band cells and lie among those with them."""
+    from paper_2305_04966_amd.learned import ProposalEstimator, cosine_lr
+    from paper_2305_04966_amd.pipeline import OccupancyGrid
+    from test_gpu_train import oracle_edges, oracle_step, oracle_targets
+
+    w = scenes.unbounded(32, 16, n_cams=2, res=64)
+    H, nb, steps, every, gamma = 64, 32, 24, 8, 0.95
+    res, L = 32, 4
+    edges = oracle_edges(w, nb)
+    tgt = oracle_targets(w)
+    pts = oracle.grid_points(res, n_levels=L, half_extent0=w.half_extent0)
+
+    # the oracle's trajectory and its grid cache
+    p = scenes.mlp_init(H).astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    traj = {}
+    D_ref = np.zeros(pts.shape[0])
+    for step in range(1, steps + 1):
+        p32 = p.astype(np.float32)
+        if step % every == 0:
+            traj[step] = p32
+            sig = oracle.mlp_fwd(pts, p32, H, scale=1.5, contract=True, emulate_bf16=True)
+            D_ref, _ = oracle.grid_ema(D_ref, sig.astype(np.float32), np.float32(gamma), 0.0)
+        _, g = oracle_step(w, edges, tgt, p32, H)
+        p, m, v = oracle.adam(p32, m, v, g, lr=cosine_lr(step, steps), step=step)
+    tau = float(np.float32(np.quantile(D_ref, 0.6)))
+    occ_ref = D_ref > tau
+    assert 0.2 < occ_ref.mean() < 0.8
+
+    # the GPU: the same parameters at the update steps, its own kernels
+    bits = torch.zeros(L * res ** 3 // 32, dtype=torch.int32, device="cuda")
+    grid = gpu_lib.GridSpec(bits, res, L, (0.0, 0.0, 0.0), w.half_extent0)
+    est_grid = OccupancyGrid(grid)
+    est = ProposalEstimator(dev(scenes.mlp_init(H)), H, scale=1.5, contract=True)
+    for step in range(1, steps + 1):
+        if step in traj:
+            est.params.copy_(torch.from_numpy(traj[step]))
+            est.spec.repack()
+        est_grid.update_every_n_steps(step, est.density_at, n=every, gamma=gamma, tau=tau)
+    torch.cuda.synchronize()
+    D = host(est_grid.density).astype(np.float64)
+    assert np.all(np.abs(D - D_ref) <= 0.125 * D_ref + 1e-30)
+    occ = scenes.unpack_bits(host(bits).view(np.uint32), L * res ** 3)
+    band = (D_ref >= tau / 1.13) & (D_ref <= tau / 0.87)
+    assert np.array_equal(occ[~band], occ_ref[~band])
+    narrow = (D_ref >= tau / 1.02) & (D_ref <= tau / 0.98)
+    assert np.mean(occ[~narrow] == occ_ref[~narrow]) >= 0.999
+
+    # march: bit-exact on the oracle's bits
+    march = lambda b: oracle.march(w.rays_o, w.rays_d, scenes.pack_bits(b), res, n_levels=L,
+                                   half_extent0=w.half_extent0, dt0=w.dt0)
+    ref = march(occ_ref)
+    assert ref["total"] > 10 * w.n_rays
+    o, d = dev(w.rays_o), dev(w.rays_d)
+    pg = gpu_lib.march(gpu_lib.GridSpec(dev(scenes.pack_bits(occ_ref)), res, L, (0.0, 0.0, 0.0),
+                                        w.half_extent0), o, d, dt0=w.dt0)
+    assert np.array_equal(host(pg.packed_info), ref["packed_info"])
+    assert np.array_equal(host(pg.t0), ref["t0"]) and np.array_equal(host(pg.t1), ref["t1"])
+    # on the bits the update wrote: between the march without and with the band
+    lo, hi = march(occ_ref & ~band), march(occ_ref | band)
+    p_own = gpu_lib.march(grid, o, d, dt0=w.dt0)
+    info, t0, t1 = host(p_own.packed_info), host(p_own.t0), host(p_own.t1)
+    for r in range(w.n_rays):
+        a, c = info[r]
+        got = set(zip(t0[a:a + c].tolist(), t1[a:a + c].tolist()))
+        rows = []
+        for mm in (lo, hi):
+            b, e = mm["packed_info"][r]
+            rows.append(set(zip(mm["t0"][b:b + e].tolist(), mm["t1"][b:b + e].tolist())))
+        assert len(got) == c and rows[0] <= got <= rows[1], r
+        assert np.all(np.diff(t0[a:a + c]) > 0)

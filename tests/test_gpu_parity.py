@@ -16,7 +16,8 @@ import torch
 
 import oracle
 import scenes
-from gpu_util import assert_close, bwd_condition, dev, grid_spec, host, segment_ids
+from gpu_util import (assert_close, bwd_condition, dev, grid_spec, host, resample_tol,
+                      segment_ids)
 
 pytestmark = pytest.mark.gpu
 
@@ -97,6 +98,28 @@ def test_march_cascade_bit_exact(gpu_lib):
     ref = oracle_march(w)
     assert ref["total"] > 0
     assert_march_equal(gpu_march(gpu_lib, w), ref)
+
+
+def test_march_cascade_full_size_sampled_rays(gpu_lib):
+    # the unbounded workload at full size (4 x 128^3 cascade, 8 cameras of
+    # 512x256 = 2^20 rays, distance-doubling steps) in the benchmark's launch;
+    # every 37th ray checked by the oracle: counts, t0, t1 bit for bit
+    w = scenes.unbounded()
+    assert w.n_rays == 1 << 20 and w.n_levels == 4 and w.res == 128
+    p = gpu_march(gpu_lib, w)
+    idx = np.arange(0, w.n_rays, 37)
+    ref = oracle_march(w, rays=(w.rays_o[idx], w.rays_d[idx]))
+    info = host(p.packed_info)
+    assert np.array_equal(info[idx, 1], ref["counts"])
+    t0, t1 = host(p.t0), host(p.t1)
+    sel = np.concatenate([np.arange(info[r, 0], info[r, 0] + info[r, 1]) for r in idx])
+    assert np.array_equal(t0[sel], ref["t0"]) and np.array_equal(t1[sel], ref["t1"])
+    assert np.array_equal(host(p.ray_id)[sel], idx[ref["ray_id"]].astype(np.int32))
+    counts = info[:, 1].astype(np.int64)
+    assert np.array_equal(info[:, 0], np.concatenate([[0], np.cumsum(counts)[:-1]]))
+    assert p.n_samples == counts.sum()
+    # ragged rows: the longest holds over 1.5 times the median count
+    assert counts.max() > 1.5 * np.median(counts[counts > 0])
 
 
 @pytest.mark.parametrize("kw", [dict(max_per_ray=11), dict(near=2.5, far=3.4),
@@ -446,27 +469,6 @@ def test_render_empty(gpu_lib):
 # ----------------------------------------------------------------------------
 # resample / uniform bins / field
 # ----------------------------------------------------------------------------
-def resample_tol(edges, vals, mode, out_ref, bins_ref):
-    """Inverse-CDF conditioning: a CDF error eps moves t by eps/(F_{i+1}-F_i) of the bin."""
-    e = edges.astype(np.float64)
-    v = vals.astype(np.float64)
-    if mode == 0:
-        F = -np.expm1(-np.cumsum(v * np.diff(e, axis=1), axis=1))
-    else:
-        F = np.cumsum(v, axis=1)
-    F = np.concatenate([np.zeros((F.shape[0], 1)), F], 1)
-    Fn = F[:, -1:]
-    uni = Fn[:, 0] <= 1e-12
-    F[uni] = np.linspace(0, 1, F.shape[1])
-    Fn = F[:, -1:]
-    i = np.minimum(bins_ref, e.shape[1] - 2)
-    dF = np.take_along_axis(F, i + 1, 1) - np.take_along_axis(F, i, 1)
-    width = np.take_along_axis(e, i + 1, 1) - np.take_along_axis(e, i, 1)
-    span = e[:, -1:] - e[:, :1]
-    return (1e-5 * np.abs(out_ref) + 1e-6 * span
-            + width * np.minimum(1.0, 4e-6 * Fn / np.maximum(dF, 1e-300)))
-
-
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("use_u", [False, True])
 def test_resample(gpu_lib, mode, use_u):
@@ -647,3 +649,22 @@ def test_stream_probe_outputs(gpu_lib, n):
     gpu_lib.stream_probe(dev(t0), dev(t1), dev(s), dev(rgb), oa, ob)
     assert np.array_equal(host(oa), (t0 + t1) + s)
     assert np.array_equal(host(ob), rgb + rgb)
+
+
+@pytest.mark.parametrize("n", [1, 511, 512 * 16384 + 777])
+def test_read_probe_covers_every_sample(gpu_lib, n):
+    # measurement support: with every input 1.0 each sample adds 6 (t0, t1,
+    # sigma and three colours) to exactly one lane's sum, so the sums total 6n
+    # (exact in binary32 per lane) and the forward's reads cover each sample once
+    one = torch.ones(n, dtype=torch.float32, device="cuda")
+    rgb = torch.ones((n, 3), dtype=torch.float32, device="cuda")
+    out = gpu_lib.read_probe(one, one, one, rgb)
+    sums = host(out)
+    assert sums.shape == (int(gpu_lib.load().txs_read_probe_out_size()),)
+    # the probe's ranges: ceil(n / 16384) samples rounded up to whole windows
+    # of 512 per wave, one lane sum per lane of each wave that has a range
+    per_wave = (-(-n // 16384) + 511) // 512 * 512
+    used = -(-n // per_wave)
+    s = sums[:used * 64]
+    assert np.all(s == np.round(s))
+    assert s.astype(np.int64).sum() == 6 * n

@@ -25,7 +25,7 @@ import pytest
 
 import oracle
 import scenes
-from gpu_util import dev, host
+from gpu_util import assert_close, dev, host, resample_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -101,3 +101,71 @@ def test_pdf_estimator_matches_oracle_chain(gpu_lib, union):
     assert np.quantile(err[out], 0.99) <= 2e-4, np.quantile(err[out], 0.99)
     assert err[out].max() <= 2e-3, err[out].max()
     assert err.mean() <= 2e-5, err.mean()
+
+
+@pytest.mark.parametrize("union", [True, False])
+def test_pdf_estimator_steps_on_oracle_densities(gpu_lib, union):
+    """The estimator's own steps held to the 1e-5 bar on identical inputs: the
+    oracle's coarse edges and float32 coarse densities feed the GPU inverse
+    CDF (edges within the resample bar, only quantiles the oracle flags as
+    within 1e-5 of a CDF knot excused); the sorted merge of the coarse edges
+    with those fine edges (sorting moves no value by more than the largest
+    input difference, so the merged rows keep the fine edges' bound); and the
+    render on the oracle's merged intervals and float32 field values within
+    1e-5.  The field itself is checked in its own test."""
+    w = scenes.tiny()
+    nc, nf = 64, 32
+    o, d = w.rays_o, w.rays_d
+    n = o.shape[0]
+    fp = w.fld.packed_params()
+    tn, tf = oracle.clip(o, d, np.full(3, -1.5, np.float32), np.full(3, 1.5, np.float32))
+    hit = tn < tf
+    span = np.stack([np.where(hit, tn, 0.0), np.where(hit, tf, 0.0)], 1)
+    edges = oracle.span_bins(span, nc).astype(np.float32)
+    sc, _ = oracle.field_at_samples(o, d, edges[:, :-1].reshape(-1), edges[:, 1:].reshape(-1),
+                                    np.repeat(np.arange(n), nc), fp)
+    sc32 = sc.astype(np.float32).reshape(n, nc)
+    assert (sc32.sum(1) > 0).mean() > 0.3  # most rays cross the blobs
+    # inverse CDF
+    fine = host(gpu_lib.resample(dev(edges), dev(sc32), nf, mode=gpu_lib.TXS_PDF_SIGMA))
+    ref, bins, _ = oracle.resample(edges, sc32, nf, oracle.MODE_SIGMA)
+    tol = resample_tol(edges, sc32, 0, ref, bins)
+    # an interior quantile within 1e-5 F_n of a non-zero interior knot may take
+    # the neighbouring bin (the two sides sum the same binary32 inputs in
+    # different orders); runs of empty bins have exactly zero mass on both
+    # sides, so the first edge is never excused
+    P = np.cumsum(sc32.astype(np.float64) * np.diff(edges.astype(np.float64), axis=1), 1)
+    F = -np.expm1(-P)
+    Fn = F[:, -1:]
+    up = (np.arange(nf + 1) / nf)[None, :] * Fn
+    knots = np.where(F[:, :-1] > 0, F[:, :-1], -1.0)
+    near = (np.abs(up[:, :, None] - knots[:, None, :]) <= 1e-5 * Fn[:, :, None]).any(axis=2)
+    near[:, 0] = near[:, -1] = False
+    err = np.abs(fine - ref)
+    bad = (err > tol) & ~near
+    assert not bad.any(), (bad.sum(), np.argwhere(bad)[:5])
+    assert near.mean() < 0.01, near.mean()
+    band = near.any(axis=1)
+    # merge (exact on its own inputs: test_merge_edges): within the fine edges'
+    # bound of the oracle's merge of its own rows
+    ref32 = ref.astype(np.float32)
+    if union:
+        m_gpu = host(gpu_lib.merge_edges(dev(edges), dev(fine)))
+        m_ref = oracle.merge_edges(edges, ref32)
+        ok = ~band
+        assert np.all(np.abs(m_gpu - m_ref)[ok].max(1) <= tol[ok].max(1)
+                      + np.spacing(np.abs(m_ref[ok]).max(1)))
+    else:
+        m_ref = ref32
+    # render on the oracle's intervals and field values
+    m = m_ref.shape[1] - 1
+    t0, t1 = m_ref[:, :-1].reshape(-1), m_ref[:, 1:].reshape(-1)
+    s, c = oracle.field_at_samples(o, d, t0, t1, np.repeat(np.arange(n), m), fp)
+    s32, c32 = s.astype(np.float32), c.astype(np.float32)
+    out = gpu_lib.render_fwd(None, dev(t0), dev(t1), dev(s32), dev(c32), n_rays=n,
+                             fixed_count=m)
+    info = np.stack([np.arange(n) * m, np.full(n, m)], 1).astype(np.int32)
+    r = oracle.render_fwd(info, t0, t1, s32, c32)
+    assert_close(host(out[0]), r["rgb"], name="rgb")
+    assert_close(host(out[1]), r["opacity"], name="opacity")
+    assert_close(host(out[2]), r["depth"], name="depth")

@@ -921,3 +921,55 @@ def test_contracted_cell_points_map_back_into_their_cells():
         back = contract64(p - np.array([0.25, -0.125, 0.375]), scale)
         assert np.allclose(back[inside], zc[inside], rtol=0, atol=1e-9)
         assert np.all(np.linalg.norm(p[~inside], axis=1) > 1e3)
+
+
+def test_grid_bricks_hand_cases():
+    """Brick occupancy (the coarse level the march skips empty space with),
+    hand-derived on a 16^3 grid of 2^3 bricks: one cell at the far corner of
+    brick (0,0,0), then one cell at the near corner of brick (1,0,0).  A plain
+    bit marks the brick holding the cell; a block bit marks every brick whose
+    2x2x2 block (itself and its +x, +y, +z neighbours) holds it."""
+    res = 16
+    idx = lambda x, y, z: x + res * (y + res * z)
+    bidx = lambda x, y, z: x + 2 * (y + 2 * z)
+    occ = np.zeros(res ** 3, bool)
+    occ[idx(7, 7, 7)] = True
+    b = oracle.grid_bricks(scenes.pack_bits(occ), res)
+    assert b.shape == (1, 2, 8)
+    assert np.flatnonzero(b[0, 0]).tolist() == [bidx(0, 0, 0)]
+    assert np.flatnonzero(b[0, 1]).tolist() == [bidx(0, 0, 0)]
+    occ[:] = False
+    occ[idx(8, 0, 0)] = True
+    b = oracle.grid_bricks(scenes.pack_bits(occ), res)
+    assert np.flatnonzero(b[0, 0]).tolist() == [bidx(1, 0, 0)]
+    assert sorted(np.flatnonzero(b[0, 1]).tolist()) == [bidx(0, 0, 0), bidx(1, 0, 0)]
+    # a cell of brick (1,1,1) is in the block of all eight bricks; levels are
+    # independent; an empty grid has no bit
+    occ[:] = False
+    occ[idx(15, 9, 12)] = True
+    two = np.concatenate([np.zeros(res ** 3, bool), occ])
+    b = oracle.grid_bricks(scenes.pack_bits(two), res, n_levels=2)
+    assert not b[0].any()
+    assert np.flatnonzero(b[1, 0]).tolist() == [bidx(1, 1, 1)]
+    assert b[1, 1].all()
+
+
+def test_grid_bricks_against_brute_force():
+    """Each brick bit equals the OR of the cell bits it covers, cell by cell."""
+    res = 32
+    occ = scenes.unpack_bits(scenes.random_bits(res, 0.002, 11), res ** 3)
+    b = oracle.grid_bricks(scenes.pack_bits(occ), res)
+    nb = res // 8
+    for j in range(nb ** 3):
+        bx, by, bz = j % nb, (j // nb) % nb, j // (nb * nb)
+        plain = any(occ[x + res * (y + res * z)]
+                    for z in range(8 * bz, 8 * bz + 8) for y in range(8 * by, 8 * by + 8)
+                    for x in range(8 * bx, 8 * bx + 8))
+        assert b[0, 0, j] == plain
+    for j in range(nb ** 3):
+        bx, by, bz = j % nb, (j // nb) % nb, j // (nb * nb)
+        blk = any(b[0, 0, x + nb * (y + nb * z)]
+                  for z in range(bz, min(bz + 2, nb)) for y in range(by, min(by + 2, nb))
+                  for x in range(bx, min(bx + 2, nb)))
+        assert b[0, 1, j] == blk
+    assert 0 < b[0, 0].sum() < nb ** 3
