@@ -62,13 +62,15 @@ int32_t txs_abi_version(void);
  * `coarse` (nullable) is the brick occupancy that lets the march skip empty
  * space (the point of the spatial-skipping estimator, Section 3.1): bricks of
  * 8^3 cells, cb = res/8 per axis, brick (bx, by, bz) holding the cells
- * [8bx, 8bx+8) x [8by, 8by+8) x [8bz, 8bz+8).  Per level two arrays of
- * txs_grid_coarse_words(res) / 2 words each, brick index j = bx + cb (by +
- * cb bz), bit (j & 31) of word j >> 5: first "some cell of the brick is
- * occupied", then "some cell of the 2x2x2 bricks (bx..bx+1, by..by+1,
- * bz..bz+1) is occupied".  txs_grid_coarsen writes it from `bits`; it must
- * describe the current bits (rebuild it after every change of bits), or the
- * march may skip occupied cells.  NULL: every lattice point is tested.       */
+ * [8bx, 8bx+8) x [8by, 8by+8) x [8bz, 8bz+8).  Per level
+ * txs_grid_coarse_words(res) words: two bit arrays of h = ceil(cb^3 / 32)
+ * words each, brick index j = bx + cb (by + cb bz), bit (j & 31) of word
+ * j >> 5 -- first "some cell of the brick is occupied", then "some cell of
+ * the 2x2x2 bricks (bx..bx+1, by..by+1, bz..bz+1) is occupied" -- then one
+ * word holding the number of occupied bricks.  txs_grid_coarsen writes it
+ * from `bits`; it must describe the current bits (rebuild it after every
+ * change of bits), or the march may skip occupied cells.  NULL: every
+ * lattice point is tested.                                                   */
 typedef struct {
   const uint32_t* bits; /* device, n_levels * res^3 / 32 words */
   int32_t res;          /* cells per axis: a power of two in [2, 1024] */
@@ -79,8 +81,8 @@ typedef struct {
 } txs_grid;
 
 /*
- * Words of brick occupancy per level (both arrays) for a grid of res cells
- * per axis: 2 * ceil((res/8)^3 / 32), or 0 for res < 8 (no bricks).
+ * Words of brick occupancy per level for a grid of res cells per axis:
+ * 2 * ceil((res/8)^3 / 32) + 1, or 0 for res < 8 (no bricks).
  */
 int64_t txs_grid_coarse_words(int32_t res);
 
@@ -111,13 +113,15 @@ typedef struct {
  * function of the inputs that any binary32 evaluation of the same recipe at
  * every lattice point reproduces bit for bit.
  *
- * Empty-space skipping: with grid->coarse set (res >= 8 and at most 4096
- * words of brick occupancy over all levels, so that a block holds it in LDS;
- * otherwise it is ignored), runs of 16 lattice points are first bounded in
- * cell space from their end points (with a margin that covers every
- * rounding of the recipe) and skipped when every brick the bound touches is
- * empty; the points of the other runs are tested one by one.  The emitted
- * samples are those of testing every point.
+ * Empty-space skipping: with grid->coarse set (res >= 8 and at most 1088
+ * words of brick occupancy over all levels, so that a wave holds it in LDS:
+ * up to four 128^3 levels; otherwise it is ignored), on segments of more than
+ * 256 lattice points of levels with at most 5/16 of their bricks occupied,
+ * runs of 16 lattice points are first bounded in cell space from their end
+ * points (with a margin that covers every rounding of the recipe) and
+ * skipped when every brick the bound touches is empty; the points of the
+ * other runs are tested one by one.  Other segments test every point.  The
+ * emitted samples are those of testing every point either way.
  *
  * txs_march_count writes counts[n_rays] (int32).
  * rays_o, rays_d: float [n_rays, 3]; rays_d need not be normalised (the

@@ -73,8 +73,9 @@ __global__ __launch_bounds__(256) void grid_ema_kernel(int64_t n, float* __restr
 }
 
 // Brick occupancy of the grid (the march's empty-space skipping): bricks of
-// 8^3 cells, per level a plain array (some cell of the brick occupied) and a
-// block array (some cell of the 2x2x2 bricks starting at the brick occupied).
+// 8^3 cells, per level a plain array (some cell of the brick occupied), a
+// block array (some cell of the 2x2x2 bricks starting at the brick occupied)
+// and the number of occupied bricks.
 constexpr int kBrickShift = 3;
 
 __global__ __launch_bounds__(256) void clear_words_kernel(int64_t n, uint32_t* __restrict__ w) {
@@ -109,9 +110,10 @@ __global__ __launch_bounds__(256) void coarsen_kernel(const uint32_t* __restrict
       any |= (lv[c >> 5] >> (c & 31)) & 0xffu;
     }
   if (!any) return;
-  uint32_t* plain = coarse + 2 * l * half_words;
+  uint32_t* plain = coarse + l * (2 * half_words + 1);
   uint32_t* block = plain + half_words;
   atomicOr(&plain[j >> 5], 1u << (j & 31));
+  atomicAdd(&block[half_words], 1u);  // the level's count of occupied bricks
   for (int dz = 0; dz < 2; ++dz)
     for (int dy = 0; dy < 2; ++dy)
       for (int dx = 0; dx < 2; ++dx) {
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(256) void coarsen_kernel(const uint32_t* __restrict
 extern "C" int64_t txs_grid_coarse_words(int32_t res) {
   if (res < 8 || res > 1024 || (res & (res - 1)) != 0) return 0;
   const int64_t b = (int64_t)(res / 8) * (res / 8) * (res / 8);
-  return 2 * ((b + 31) / 32);
+  return 2 * ((b + 31) / 32) + 1;
 }
 
 extern "C" txs_status txs_grid_coarsen(const txs_grid* grid, uint32_t* coarse, void* stream) {
@@ -146,7 +148,7 @@ extern "C" txs_status txs_grid_coarsen(const txs_grid* grid, uint32_t* coarse, v
   const int64_t bricks = ((int64_t)1 << (3 * (shift - kBrickShift))) * grid->n_levels;
   hipLaunchKernelGGL(coarsen_kernel, dim3(grid_1d(bricks, 256)), dim3(256), 0,
                      as_stream(stream), grid->bits, shift, grid->n_levels,
-                     txs_grid_coarse_words(res) / 2, coarse);
+                     (txs_grid_coarse_words(res) - 1) / 2, coarse);
   return launch_status("txs_grid_coarsen");
 }
 

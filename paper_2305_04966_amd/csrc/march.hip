@@ -19,9 +19,11 @@
 // point.  Without brick occupancy (or over contracted space, where the path
 // bends in cell space) every point is tested.
 //
-// A block of four waves marches 64 consecutive rays (16 per wave) after
-// copying the brick occupancy of every level into LDS (1 KiB for one 128^3
-// level).
+// A block of four waves marches 64 consecutive rays (16 per wave); a wave
+// copies a level's brick occupancy into its LDS the first time it skips on
+// that level (1 KiB for a 128^3 level).  Skipping is chosen per segment: on
+// levels with at most 5/16 of their bricks occupied, for segments of more
+// than a few hundred lattice points.
 #pragma clang fp contract(off)
 
 #include <cmath>
@@ -41,7 +43,9 @@ constexpr int kRaysPerBlock = 64;
 constexpr int kChunk = 16;                  // lattice points per run of the skipping pass
 constexpr int kDenseRuns = 48;              // more maybe-occupied runs of 63: test the window in order
 constexpr int kBrickShift = 3;              // bricks of 8^3 cells
-constexpr int kCoarseLdsWords = 4096;       // brick occupancy staged per block (16 KiB)
+// brick occupancy a wave may hold in LDS (four 128^3 levels: 1028 words);
+// with the run list, 8 blocks of 4 waves fit a CU's LDS
+constexpr int kCoarseLdsWords = 1088;
 constexpr int kListLen = kWave + 16;        // run list per wave, sentinel-padded
 constexpr int kSentinelRun = 1 << 21;       // a run beyond every segment's last point
 
@@ -202,8 +206,9 @@ __device__ __forceinline__ bool probe(const Lattice& p, const float o[3], const 
 // segment.  The word's byte offset fits 32 bits: a scalar base and a 32-bit
 // lane offset.
 __device__ __forceinline__ uint32_t cell_word(const Lattice& p, const float o[3],
-                                              const float d[3], float kh, uint32_t& bit) {
-  const float m = p.a + kh * p.dt;
+                                              const float d[3], float kh, uint32_t& bit,
+                                              float& m) {
+  m = p.a + kh * p.dt;
   uint32_t cell[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -245,9 +250,10 @@ __device__ __forceinline__ int32_t march_segment(const MarchArgs& g, const float
         // (float)k + 1/2 as a scalar plus a lane constant: exact below 2^24
         const float kh = (float)(k0 + kWave * q) + lane_h;
         uint32_t bt;
-        word[q] = cell_word(p, o, d, kh, bt);
+        float m;
+        word[q] = cell_word(p, o, d, kh, bt, m);
         sh[q] = (int32_t)bt;
-        valid[q] = p.a + kh * p.dt < p.b;
+        valid[q] = m < p.b;
       }
     }
 #pragma unroll
@@ -307,6 +313,16 @@ struct Bricks {
   int cshift;
 };
 
+// Skipping pays where the bricks are mostly empty; on a level with more than
+// 5/16 of its bricks occupied the points are tested one by one (measured on
+// MI355X, one 128^3 level, 2^20 camera rays: 44% occupied, skipping 5% slower
+// than testing every point; 19% occupied, 13% faster)...
+constexpr uint32_t kSkipNum = 5, kSkipDen = 16;
+// ... and on segments long enough for the run pass to pay (a few hundred
+// lattice points; the unbounded rig's short middle-level segments march
+// faster point by point)
+constexpr int kSkipMinPoints = 256;
+
 // One segment [a, b) on level l with empty-space skipping (see the top of the
 // file).  Pass 1: lane j < 63 bounds run c0 + j (lattice points
 // [kChunk (c0 + j), kChunk (c0 + j + 1))) by the recipe's u at its first
@@ -327,32 +343,91 @@ __device__ __forceinline__ int32_t march_segment_skip(const MarchArgs& g, const 
                                                       const float d[3], float a, float b, int l,
                                                       int32_t n, int32_t cap, Emit& em) {
   const Lattice p = lattice<false>(g, a, b, l);
-  const int32_t kmax = last_lattice_point(a, b, p.dt);
-  if (kmax < 0) return n;
   const int ln = lane();
-  // rounding bound of u = ((o + m d) - bmin) scale per axis (each of the four
-  // operations rounds once): |u - exact| <= scale u_r (4|m d| + 3|o| + 2|bmin|)
-  // (1 + 1e-6) with u_r = 2^-24; 2^-20 (scale (2 m_max|d| + 2|o| + 2|bmin|) +
-  // res) exceeds it at least fourfold for any m of this segment's runs
+  // The bounds need not follow the recipe, only enclose it.  With U(m) =
+  // (o + m d - bmin) scale in exact arithmetic on the binary32 inputs and
+  // u_r = 2^-24: the recipe's u at a point is within u_r scale (4|m d| + 3|o|
+  // + 2|bmin|) 1.01 of U(m_k) (four roundings); the bound's u~ = fma(B, m, A)
+  // with A = fl(fl(o - bmin) scale), B = fl(d scale), at the recipe's m of a
+  // run's first point, is within u_r scale (3.02|m d| + 3.02(|o| + |bmin|))
+  // of U(m).  U is monotone in m and m_k is non-decreasing in k, so every
+  // point of a run lies within the sum of the two of the interval between
+  // its first point's and the next run's u~.  marg = 2^-19 (scale (2 m_max|d|
+  // + 2|o| + 2|bmin|) + res) exceeds that sum at least fivefold for any m of
+  // this segment's runs.
   const float m_max = fmaxf(fabsf(a), fabsf(b) + (float)(kChunk + 2) * p.dt);
-  float marg[3];
+  float marg[3], A[3], B[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < 3; ++c) {
     marg[c] = 2.0f * 0x1p-20f *
               (p.box.scale[c] * (2.0f * m_max * fabsf(d[c]) + 2.0f * fabsf(o[c]) +
                                  2.0f * fabsf(p.box.bmin[c])) + p.resf);
+    A[c] = (o[c] - p.box.bmin[c]) * p.box.scale[c];
+    B[c] = d[c] * p.box.scale[c];
+  }
   const int sh = br.cshift;
-  const int32_t n_runs = kmax / kChunk + 1;
-  for (int32_t c0 = 0; c0 < n_runs; c0 += kWave - 1) {
+  constexpr uint64_t kRunLanes = ~0ull >> 1;  // lanes 0..62 own runs, lane 63 bounds
+  // one step: two groups of 64 points, kq[q] the lane's point of group q
+  // (valid when a point of the segment, below 2^24 and below k_end); their
+  // grid-word loads stay in flight together.  Returns true when the ray is
+  // done.
+  auto step = [&](const int32_t (&kq)[kGroups], int32_t k_end) -> bool {
+    bool valid[kGroups];
+    uint32_t word[kGroups], bit[kGroups];
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) {
+      float m;
+      word[q] = cell_word(p, o, d, (float)kq[q] + 0.5f, bit[q], m);
+      valid[q] = kq[q] < k_end && m < b;
+    }
+    bool occs[kGroups];
+    uint64_t masks[kGroups];
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) {
+      occs[q] = valid[q] && ((word[q] >> bit[q]) & 1u);
+      masks[q] = __ballot(occs[q]);  // all ballots first: loads stay in flight together
+    }
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) {
+      const uint64_t mask = masks[q];
+      if (kMode == kSpan && mask != 0) {
+        const int32_t kf = readlane(kq[q], (int)__builtin_ctzll(mask));
+        em.lo = a + (float)kf * p.dt;
+        n += __popcll(mask);
+        return true;
+      }
+      if (kMode == kFill && occs[q]) {
+        const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        const int64_t pos = em.base + n + rank;
+        if ((cap == 0 || n + rank < cap) && n + rank < em.count && pos < em.capacity) {
+          const float kf = (float)kq[q];
+          em.t0[pos] = a + kf * p.dt;
+          em.t1[pos] = fminf(a + (kf + 1.0f) * p.dt, b);
+          if (em.ray_id) em.ray_id[pos] = em.ray;
+        }
+      }
+      n += __popcll(mask);
+      if (cap > 0 && n >= cap) {
+        n = cap;
+        return true;
+      }
+    }
+    return false;
+  };
+  for (int32_t c0 = 0; c0 < kLatticeLimit / kChunk; c0 += kWave - 1) {
     const int32_t ks = kChunk * (c0 + ln);
-    const float ms = a + ((float)ks + 0.5f) * p.dt;
+    // the recipe's midpoint of the run's first point: the run holds points of
+    // the segment iff it lies before b (midpoints grow with k)
+    const float m0 = a + ((float)ks + 0.5f) * p.dt;
+    const bool live = ks < kLatticeLimit && m0 < b;
     float u[3], un[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = ((o[c] + ms * d[c]) - p.box.bmin[c]) * p.box.scale[c];
+    for (int c = 0; c < 3; ++c) u[c] = __builtin_fmaf(B[c], m0, A[c]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) un[c] = dpp<kWaveShl1>(u[c], u[c]);  // lane + 1's u
     bool maybe = false;
-    if (ln < kWave - 1 && c0 + ln < n_runs) {
+    if (ln < kWave - 1 && live) {
       int lo[3], hi[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -366,86 +441,44 @@ __device__ __forceinline__ int32_t march_segment_skip(const MarchArgs& g, const 
       else if (w0 <= 1 && w1 <= 1 && w2 <= 1) maybe = (br.block[j >> 5] >> (j & 31)) & 1u;
       else maybe = true;
     }
+    const bool last_window = (__ballot(live) & kRunLanes) != kRunLanes;
     const uint64_t runs = __ballot(maybe);
-    if (runs == 0) continue;
     const int nr = __popcll(runs);
-    // one step: two groups of 64 points, kq[q] the lane's point of group q
-    // (valid when inside the segment and below k_end); their grid-word loads
-    // stay in flight together.  Returns true when the ray is done.
-    auto step = [&](const int32_t (&kq)[kGroups], int32_t k_end) -> bool {
-      bool valid[kGroups];
-      uint32_t word[kGroups], bit[kGroups];
-#pragma unroll
-      for (int q = 0; q < kGroups; ++q) {
-        valid[q] = kq[q] <= kmax && kq[q] < k_end;
-        word[q] = cell_word(p, o, d, (float)kq[q] + 0.5f, bit[q]);
-      }
-      bool occs[kGroups];
-      uint64_t masks[kGroups];
-#pragma unroll
-      for (int q = 0; q < kGroups; ++q) {
-        occs[q] = valid[q] && ((word[q] >> bit[q]) & 1u);
-        masks[q] = __ballot(occs[q]);  // all ballots first: loads stay in flight together
-      }
-#pragma unroll
-      for (int q = 0; q < kGroups; ++q) {
-        const uint64_t mask = masks[q];
-        if (kMode == kSpan && mask != 0) {
-          const int32_t kf = readlane(kq[q], (int)__builtin_ctzll(mask));
-          em.lo = a + (float)kf * p.dt;
-          n += __popcll(mask);
-          return true;
-        }
-        if (kMode == kFill && occs[q]) {
-          const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
-              (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-          const int64_t pos = em.base + n + rank;
-          if ((cap == 0 || n + rank < cap) && n + rank < em.count && pos < em.capacity) {
-            const float kf = (float)kq[q];
-            em.t0[pos] = a + kf * p.dt;
-            em.t1[pos] = fminf(a + (kf + 1.0f) * p.dt, b);
-            if (em.ray_id) em.ray_id[pos] = em.ray;
-          }
-        }
-        n += __popcll(mask);
-        if (cap > 0 && n >= cap) {
-          n = cap;
-          return true;
-        }
-      }
-      return false;
-    };
     if (nr > kDenseRuns) {
       // most runs of the window may hold samples: its points in order, as
       // the dense march does (no list)
-      const int32_t k_end = kChunk * min(c0 + kWave - 1, n_runs);
+      const int32_t k_end = kChunk * (c0 + kWave - 1);
       for (int32_t k0 = kChunk * c0; k0 < k_end; k0 += kWave * kGroups) {
         int32_t kq[kGroups];
 #pragma unroll
         for (int q = 0; q < kGroups; ++q) kq[q] = k0 + kWave * q + ln;
         if (step(kq, k_end)) return n;
+        if (__ballot(kq[kGroups - 1] < k_end && a + ((float)kq[kGroups - 1] + 0.5f) * p.dt < b) !=
+            ~0ull)
+          break;  // the segment ended in this step
       }
-      continue;
-    }
-    // the maybe-occupied runs in k order at list[0, nr), every other lane's
-    // sentinel after them (entries kWave.. hold the sentinel already), so the
-    // steps read the list without a branch
-    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(runs >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)runs, 0u));
-    list[maybe ? rank : nr + ln - rank] = maybe ? c0 + ln : kSentinelRun;
-    wave_sync();
-    constexpr int kRunsPerGroup = kWave / kChunk;
-    for (int i0 = 0; i0 < nr; i0 += kGroups * kRunsPerGroup) {
-      int32_t kq[kGroups];
+    } else if (nr > 0) {
+      // the maybe-occupied runs in k order at list[0, nr), every other lane's
+      // sentinel after them (entries kWave.. hold the sentinel already), so
+      // the steps read the list without a branch
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(runs >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)runs, 0u));
+      list[maybe ? rank : nr + ln - rank] = maybe ? c0 + ln : kSentinelRun;
+      wave_sync();
+      constexpr int kRunsPerGroup = kWave / kChunk;
+      for (int i0 = 0; i0 < nr; i0 += kGroups * kRunsPerGroup) {
+        int32_t kq[kGroups];
 #pragma unroll
-      for (int q = 0; q < kGroups; ++q)
-        kq[q] = kChunk * list[i0 + kRunsPerGroup * q + ln / kChunk] + (ln % kChunk);
-      if (step(kq, kLatticeLimit)) {
-        wave_sync();
-        return n;
+        for (int q = 0; q < kGroups; ++q)
+          kq[q] = kChunk * list[i0 + kRunsPerGroup * q + ln / kChunk] + (ln % kChunk);
+        if (step(kq, kLatticeLimit)) {
+          wave_sync();
+          return n;
+        }
       }
+      wave_sync();  // the list is rewritten by the next run window
     }
-    wave_sync();  // the list is rewritten by the next run window
+    if (last_window) break;
   }
   return n;
 }
@@ -482,9 +515,9 @@ __device__ __forceinline__ bool span_back(const MarchArgs& g, const float o[3], 
 }
 
 template <int kMode, bool kContract, bool kSkip>
-__device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const uint32_t* coarse_lds,
-                                             int* list, const float o[3], const float d[3],
-                                             Emit& em) {
+__device__ __forceinline__ int32_t march_ray(const MarchArgs& g, uint32_t* coarse_lds,
+                                             uint32_t& staged, int* list, const float o[3],
+                                             const float d[3], Emit& em) {
   float inv[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) inv[c] = 1.0f / d[c];
@@ -524,9 +557,20 @@ __device__ __forceinline__ int32_t march_ray(const MarchArgs& g, const uint32_t*
   };
   auto forward = [&](int l, float a, float b, int32_t n, int32_t cap) {
     if (kSkip) {
-      const Bricks br{coarse_lds + 2 * l * g.coarse_half,
-                      coarse_lds + (2 * l + 1) * g.coarse_half, g.cshift};
-      return march_segment_skip<kMode>(g, br, list, o, d, a, b, l, n, cap, em);
+      const int lw = 2 * g.coarse_half + 1;
+      const uint32_t occupied = g.coarse[l * lw + 2 * g.coarse_half];  // scalar load
+      if (kSkipDen * occupied <= kSkipNum * (1u << (3 * g.cshift)) &&
+          b - a > (float)kSkipMinPoints * (g.dt0 * (float)(1 << l))) {
+        uint32_t* lv = coarse_lds + l * lw;
+        if (!((staged >> l) & 1u)) {
+          // first skip on this level: this wave copies its bricks into LDS
+          for (int i = lane(); i < 2 * g.coarse_half; i += kWave) lv[i] = g.coarse[l * lw + i];
+          wave_sync();
+          staged |= 1u << l;
+        }
+        const Bricks br{lv, lv + g.coarse_half, g.cshift};
+        return march_segment_skip<kMode>(g, br, list, o, d, a, b, l, n, cap, em);
+      }
     }
     return march_segment<kMode, kContract>(g, o, d, a, b, l, n, cap, em);
   };
@@ -563,14 +607,14 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float*
                                                        int64_t capacity, float* t0, float* t1,
                                                        int32_t* ray_id, float* span) {
   extern __shared__ uint32_t lds[];
-  const int coarse_words = kSkip ? 2 * g.n_levels * g.coarse_half : 0;
-  if (kSkip) {
-    for (int i = threadIdx.x; i < coarse_words; i += kBlock) lds[i] = g.coarse[i];
-    __syncthreads();
-  }
+  // per wave: the brick occupancy of every level (copied on the first skip
+  // on that level) and the run list
+  const int coarse_words = kSkip ? g.n_levels * (2 * g.coarse_half + 1) : 0;
   const int w = threadIdx.x / kWave;
-  int* list = reinterpret_cast<int*>(lds + coarse_words) + kListLen * w;
+  uint32_t* coarse_lds = lds + (coarse_words + kListLen) * w;
+  int* list = reinterpret_cast<int*>(coarse_lds + coarse_words);
   if (kSkip && lane() < kListLen - kWave) list[kWave + lane()] = kSentinelRun;
+  uint32_t staged = 0u;  // levels whose bricks this wave holds (wave-uniform)
   // a block marches kRaysPerBlock consecutive rays, its waves taking every
   // kWavesPerBlock-th of them (neighbouring rays cost alike, so the waves
   // finish together); the next ray's origin and direction load while the
@@ -608,7 +652,7 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float*
       em.base = row.x;
       em.count = (row.x < 0 || row.y < 0) ? 0 : row.y;  // malformed row: nothing written
     }
-    const int32_t n = march_ray<kMode, kContract, kSkip>(g, lds, list, o, d, em);
+    const int32_t n = march_ray<kMode, kContract, kSkip>(g, coarse_lds, staged, list, o, d, em);
     if (kMode == kCount && lane() == 0) counts[r] = n;
     if (kMode == kSpan && lane() == 0) {
       span[2 * (int64_t)r] = em.lo;
@@ -656,7 +700,7 @@ txs_status make_args(const txs_grid* grid, const txs_march_params* p, MarchArgs&
   if (grid->coarse && cw > 0 && cw * grid->n_levels <= kCoarseLdsWords) {
     g.coarse = grid->coarse;
     g.cshift = g.res_shift - kBrickShift;
-    g.coarse_half = (int32_t)(cw / 2);
+    g.coarse_half = (int32_t)((cw - 1) / 2);
   }
   return TXS_OK;
 }
@@ -671,8 +715,8 @@ txs_status launch_march(const MarchArgs& g, void* stream, const float* ro, const
                         int32_t n_rays, int32_t* counts, const int32_t* info, int64_t capacity,
                         float* t0, float* t1, int32_t* ray_id, float* span, const char* who) {
   const bool skip = !kContract && g.coarse != nullptr;
-  const size_t lds = sizeof(uint32_t) * ((skip ? 2 * g.n_levels * g.coarse_half : 0) +
-                                         kWavesPerBlock * kListLen);
+  const size_t lds = sizeof(uint32_t) * kWavesPerBlock *
+                     ((skip ? g.n_levels * (2 * g.coarse_half + 1) : 0) + kListLen);
   if (skip)
     hipLaunchKernelGGL((march_kernel<kMode, kContract, !kContract>), dim3(march_blocks(n_rays)),
                        dim3(kBlock), lds, as_stream(stream), g, ro, rd, n_rays, counts, info,

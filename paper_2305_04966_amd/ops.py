@@ -53,20 +53,23 @@ def _opt(t, name, dtype, shape=None):
 class GridSpec:
     """Occupancy grid: bits (uint32-in-int32 tensor), res, levels, box.
 
-    With skip=True (and res >= 8) the grid carries its brick occupancy
-    (`coarse`, built by txs_grid_coarsen when the spec is made), which the
-    march uses to skip empty space.  After changing `bits` in place, call
-    refresh() so that the brick occupancy describes the new bits."""
+    Unless skip is False (and for res >= 8) the grid keeps its brick
+    occupancy (`coarse`, built by txs_grid_coarsen when the spec is made) for
+    the march's empty-space skipping: with skip="auto" the descriptor passes
+    it when every level is sparse (see refresh), with skip=True always (the
+    library still skips only where its per-level and per-segment rules
+    allow).  After changing `bits` in place, call refresh() so that the brick
+    occupancy describes the new bits."""
     bits: torch.Tensor
     res: int
     n_levels: int = 1
     center: tuple = (0.0, 0.0, 0.0)
     half_extent0: float = 1.5
-    skip: bool = True
+    skip: object = "auto"
     coarse: torch.Tensor = None
 
     def __post_init__(self):
-        if self.skip and self.coarse is None:
+        if self.skip is not False and self.coarse is None:
             w = int(load().txs_grid_coarse_words(self.res))
             if w > 0 and self.bits.numel() * 32 >= self.n_levels * self.res ** 3:
                 self.coarse = torch.empty(w * self.n_levels, dtype=torch.int32,
@@ -74,11 +77,27 @@ class GridSpec:
                 self.refresh()
 
     def refresh(self):
-        """Rebuilds the brick occupancy from the current bits (no-op without it)."""
+        """Rebuilds the brick occupancy from the current bits (no-op without it).
+
+        The march skips only on levels with at most 5/16 of their bricks
+        occupied, and skipping pays only on sparse grids (measured on MI355X:
+        one 128^3 level with 19% of its bricks occupied, the count pass 10%
+        faster; a 4-level cascade with two of its levels that sparse, 18%
+        slower, the dense levels paying for the skipping kernel); so the
+        descriptor carries the brick occupancy only when every level is that
+        sparse (one small device-to-host read of the per-level counts, once
+        per grid update)."""
+        self._skip_levels = False
         if self.coarse is not None:
-            g = self.struct()
+            g = self._fill(Grid())
+            g.coarse = None
             check(load().txs_grid_coarsen(C.byref(g), _ptr(self.coarse), _stream()),
                   "txs_grid_coarsen")
+            per_level = self.coarse.numel() // self.n_levels
+            counts = self.coarse.view(self.n_levels, per_level)[:, -1].cpu()
+            bricks = (self.res // 8) ** 3
+            self._skip_levels = (self.skip is True or
+                                 bool((16 * counts.to(torch.int64) <= 5 * bricks).all()))
         return self
 
     def struct_contracted(self) -> Grid:
@@ -102,7 +121,8 @@ class GridSpec:
         g.n_levels = self.n_levels
         g.center = (C.c_float * 3)(*self.center)
         g.half_extent0 = self.half_extent0
-        g.coarse = None if self.coarse is None else self.coarse.data_ptr()
+        use = self.coarse is not None and getattr(self, "_skip_levels", False)
+        g.coarse = self.coarse.data_ptr() if use else None
         return g
 
 

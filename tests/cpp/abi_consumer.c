@@ -17,7 +17,7 @@ int main(void) {
   if (st != TXS_EINVAL) return 4;
   if (txs_scan_workspace_size(1 << 20) == 0) return 5;
   /* brick occupancy sizes; a zero-initialised grid descriptor has none */
-  if (txs_grid_coarse_words(128) != 256 || txs_grid_coarse_words(4) != 0) return 6;
+  if (txs_grid_coarse_words(128) != 257 || txs_grid_coarse_words(4) != 0) return 6;
   {
     txs_grid g;
     memset(&g, 0, sizeof g);

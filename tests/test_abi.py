@@ -55,15 +55,16 @@ def test_version_and_error_without_gpu(lib):
 
 
 def test_brick_occupancy_sizes(lib):
-    """Two arrays of ceil((res/8)^3 / 32) words per level; no bricks below res 8;
+    """Two arrays of ceil((res/8)^3 / 32) words and a count word per level; no
+    bricks below res 8;
     the coarsening refuses such grids on the host."""
     lib.txs_grid_coarse_words.restype = C.c_int64
     lib.txs_grid_coarse_words.argtypes = [C.c_int32]
     assert lib.txs_grid_coarse_words(4) == 0
-    assert lib.txs_grid_coarse_words(8) == 2
-    assert lib.txs_grid_coarse_words(64) == 2 * 16
-    assert lib.txs_grid_coarse_words(128) == 2 * 128
-    assert lib.txs_grid_coarse_words(1024) == 2 * 128 ** 3 // 32
+    assert lib.txs_grid_coarse_words(8) == 2 + 1
+    assert lib.txs_grid_coarse_words(64) == 2 * 16 + 1
+    assert lib.txs_grid_coarse_words(128) == 2 * 128 + 1
+    assert lib.txs_grid_coarse_words(1024) == 2 * 128 ** 3 // 32 + 1
     assert lib.txs_grid_coarse_words(100) == 0
     from paper_2305_04966_amd._lib import Grid
     g = Grid()

@@ -65,15 +65,19 @@ def test_grid_coarsen(gpu_lib, res, L, p):
     ref = oracle.grid_bricks(bits, res, n_levels=L)
     nb3 = (res // 8) ** 3
     half = max(1, (nb3 + 31) // 32)
-    got = got.reshape(L, 2, half)
+    got = got.reshape(L, 2 * half + 1)
     for l in range(L):
         for a in range(2):
-            bitsl = scenes.unpack_bits(got[l, a], 32 * half)[:nb3]
+            bitsl = scenes.unpack_bits(got[l, a * half:(a + 1) * half], 32 * half)[:nb3]
             assert np.array_equal(bitsl, ref[l, a]), (l, a)
+        assert got[l, 2 * half] == ref[l, 0].sum()  # occupied bricks of the level
 
 
 def march_both(gpu_lib, w, **kw):
-    g = grid_spec(gpu_lib, w.bits, w.res, w.n_levels, w.half_extent0)
+    # skip=True: the descriptor always carries the brick occupancy, so the
+    # library's own per-level and per-segment rules choose where to skip
+    g = gpu_lib.GridSpec(dev(np.asarray(w.bits, np.uint32)), w.res, w.n_levels, (0.0, 0.0, 0.0),
+                         w.half_extent0, skip=True)
     o, d = dev(w.rays_o), dev(w.rays_d)
     p = gpu_lib.march(g, o, d, dt0=w.dt0, **kw)
     ref = oracle.march(w.rays_o, w.rays_d, w.bits, w.res, n_levels=w.n_levels,
@@ -88,11 +92,14 @@ def assert_same(p, ref):
     assert np.array_equal(host(p.ray_id), ref["ray_id"])
 
 
-@pytest.mark.parametrize("res,n_cells,dt", [(32, 60, 0.0123), (32, 60, 0.003), (64, 400, 0.005),
-                                            (64, 400, 0.05), (16, 8, 0.0021)])
-def test_march_sparse_grid_brick_faces(gpu_lib, res, n_cells, dt):
+@pytest.mark.parametrize("res,n_cells,dt,skips", [(32, 20, 0.0123, True), (32, 20, 0.003, True),
+                                                  (64, 120, 0.005, True), (64, 120, 0.011, True),
+                                                  (16, 3, 0.0021, True), (32, 60, 0.0123, False)])
+def test_march_sparse_grid_brick_faces(gpu_lib, res, n_cells, dt, skips):
     occ = face_cells(res, n_cells, res + n_cells)
     assert occ.mean() <= 0.05
+    # the march skips on levels with at most 5/16 of their bricks occupied
+    assert (oracle.grid_bricks(scenes.pack_bits(occ), res)[0, 0].mean() <= 5 / 16) == skips
     o, d = brick_rays(res, 3000, res)
     w = scenes.Workload("sparse", scenes.blob_field(8), scenes.pack_bits(occ), res, 1, 1.5,
                         o, d, dt)
@@ -109,7 +116,10 @@ def test_march_sparse_cascade_and_cap(gpu_lib):
     """A 4-level cascade of sparse face-cell grids (distance-doubling steps) and
     a per-ray cap, against the oracle."""
     res, L = 32, 4
-    occ = np.concatenate([face_cells(res, 80, 90 + l) for l in range(L)])
+    # level 0 dense enough to test every point, the others skipping
+    occ = np.concatenate([face_cells(res, 80 if l == 0 else 20, 90 + l) for l in range(L)])
+    frac = oracle.grid_bricks(scenes.pack_bits(occ), res, n_levels=L)[:, 0].mean(axis=1)
+    assert frac[0] > 5 / 16 and np.all(frac[1:] <= 5 / 16)
     g0 = scenes.rng(91)
     eyes = 3.0 * g0.standard_normal((3000, 3))
     tgt = g0.uniform(-1.0, 1.0, (3000, 3))
@@ -118,8 +128,10 @@ def test_march_sparse_cascade_and_cap(gpu_lib):
     o2, d2 = brick_rays(res, 2000, 92, h=1.5 * 2 ** (L - 1))
     o = np.concatenate([eyes, o2]).astype(np.float32)
     d = np.concatenate([d, d2]).astype(np.float32)
+    # steps small enough that segments of every level run past the 256 lattice
+    # points from which the march skips
     w = scenes.Workload("sparse4", scenes.blob_field(8), scenes.pack_bits(occ), res, L, 1.5,
-                        o, d, 0.004)
+                        o, d, 0.001)
     _, p, ref = march_both(gpu_lib, w)
     assert ref["total"] > 500
     assert_same(p, ref)
@@ -128,22 +140,29 @@ def test_march_sparse_cascade_and_cap(gpu_lib):
 
 
 def test_skip_equals_dense_at_full_size(gpu_lib):
-    """The benchmark workload (2^20 rays, 128^3 grid) and the unbounded one
-    (4 x 128^3 cascade): the march with brick occupancy gives the same packed
-    samples as the march that tests every lattice point."""
-    for w in (scenes.image(), scenes.unbounded()):
+    """The benchmark workload (2^20 rays, 128^3 grid; its bricks are dense
+    enough that every point is tested), the same camera on an 8-blob field (19%
+    of the bricks occupied: skipping) and the unbounded workload (4 x 128^3
+    cascade, two of its levels sparse): the march with brick occupancy gives
+    the same packed samples as the march that tests every lattice point."""
+    f8 = scenes.blob_field(8)
+    o8, d8 = scenes.pinhole_rays()
+    sparse = scenes.Workload("sparse", f8, scenes.occupancy_bits(f8, 128), 128, 1, 1.5, o8, d8,
+                             scenes.IMAGE_STEP)
+    for w in (scenes.image(), sparse, scenes.unbounded()):
         o, d = dev(w.rays_o), dev(w.rays_d)
         outs = []
-        for skip in (True, False):
+        for skip in (True, "auto", False):
             g = gpu_lib.GridSpec(dev(w.bits.view(np.int32)), w.res, w.n_levels, (0.0, 0.0, 0.0),
                                  w.half_extent0, skip=skip)
-            assert (g.coarse is not None) == skip
+            assert (g.coarse is not None) == (skip is not False)
             p = gpu_lib.march(g, o, d, dt0=w.dt0)
             outs.append([host(t) for t in (p.packed_info, p.t0, p.t1, p.ray_id)])
             del p
             torch.cuda.empty_cache()
-        for a, b in zip(*outs):
-            assert np.array_equal(a, b)
+        for other in outs[1:]:
+            for a, b in zip(outs[0], other):
+                assert np.array_equal(a, b)
 
 
 def test_large_grid_marches_without_bricks(gpu_lib):
@@ -166,15 +185,16 @@ def test_grid_update_refreshes_bricks(gpu_lib):
     from paper_2305_04966_amd.pipeline import OccupancyGrid
     res = 32
     bits = torch.zeros(res ** 3 // 32, dtype=torch.int32, device="cuda")
-    grid = gpu_lib.GridSpec(bits, res)
+    grid = gpu_lib.GridSpec(bits, res, skip=True)
     assert grid.coarse is not None and int(grid.coarse.abs().sum()) == 0
     est = OccupancyGrid(grid)
-    occ = face_cells(res, 50, 96)
+    occ = face_cells(res, 15, 96)  # sparse enough for the march to skip
+    assert oracle.grid_bricks(scenes.pack_bits(occ), res)[0, 0].mean() <= 5 / 16
     sig = dev(np.where(occ, 1.0, 0.0).astype(np.float32))
     est.update(lambda pts: sig, gamma=0.0, tau=0.5)
     assert np.array_equal(scenes.unpack_bits(host(bits).view(np.uint32), res ** 3), occ)
     o, d = brick_rays(res, 1000, 97)
-    p = gpu_lib.march(grid, dev(o), dev(d), dt0=0.01)
-    ref = oracle.march(o, d, scenes.pack_bits(occ), res, dt0=0.01)
+    p = gpu_lib.march(grid, dev(o), dev(d), dt0=0.004)
+    ref = oracle.march(o, d, scenes.pack_bits(occ), res, dt0=0.004)
     assert ref["total"] > 50
     assert_same(p, ref)
