@@ -36,7 +36,8 @@ struct ParamOffsets {
 // Packed operand tiles (bf16), each tile = 64 lanes x 8 values:
 //   A1[m][s]  layer 1 (W1; b1 in the constant-1 slots), m < H/16, s < 2
 //   A2[m][s]  layer 2 (W2), s < H/32
-//   A2t[m][s] layer 2 transposed (W2^T, for the adjoint), s < H/32
+//   A2t[T][s] W2^T for the adjoint, B operand: K = layer-2 units in the order
+//             of K-step s, N = layer-1 units in the order of point-major tile T
 //   w3 (H values, unit order)
 struct PackOffsets {
   int64_t A1, A2, A2t, w3, total;  // in bf16 elements
@@ -58,6 +59,18 @@ __host__ __device__ inline int feature_of(int g, int q) {
 // previous layer's fragments: input unit 16 (2s + i/4) + 4g + i%4.
 __host__ __device__ inline int unit_of(int s, int g, int i) {
   return 16 * (2 * s + i / 4) + 4 * g + (i % 4);
+}
+
+// Unit in column n of point-major tile T: the transpose of K-step T/2 of a
+// unit-major fragment, half T%2 of its K range.
+__host__ __device__ inline int pm_unit(int T, int n) {
+  return unit_of(T / 2, 2 * (T % 2) + n / 8, n % 8);
+}
+
+// Canonical feature (or -1) in column n of point-major feature tile F:
+// F = 0: axes 0,1 slots 0..7; F = 1: axes 0,1 slots 8..15; F = 2: axis 2.
+__host__ __device__ inline int pm_feature(int F, int n) {
+  return F == 2 ? feature_of(2, n) : feature_of(n / 8, 8 * F + n % 8);
 }
 
 __global__ void pack_kernel(const float* __restrict__ p, int H, __bf16* __restrict__ out) {
@@ -84,10 +97,10 @@ __global__ void pack_kernel(const float* __restrict__ p, int H, __bf16* __restri
     const int64_t t = (e - ko.A2) / 512, r = (e - ko.A2) % 512;
     const int m = (int)(t / (H / 32)), s = (int)(t % (H / 32)), l = (int)(r / 8), i = (int)(r % 8);
     v = p[po.W2 + (int64_t)(16 * m + l % 16) * H + unit_of(s, l / 16, i)];
-  } else if (e < ko.w3) {  // A2t[m][s][lane][i] = W2[out = permuted K][in = row]
+  } else if (e < ko.w3) {  // A2t[T][s][lane][i] = W2[out = K order of s][in = pm_unit(T, n)]
     const int64_t t = (e - ko.A2t) / 512, r = (e - ko.A2t) % 512;
-    const int m = (int)(t / (H / 32)), s = (int)(t % (H / 32)), l = (int)(r / 8), i = (int)(r % 8);
-    v = p[po.W2 + (int64_t)unit_of(s, l / 16, i) * H + (16 * m + l % 16)];
+    const int T = (int)(t / (H / 32)), s = (int)(t % (H / 32)), l = (int)(r / 8), i = (int)(r % 8);
+    v = p[po.W2 + (int64_t)unit_of(s, l / 16, i) * H + pm_unit(T, l % 16)];
   } else {  // w3 in unit order
     v = p[po.w3 + (e - ko.w3)];
   }
@@ -349,20 +362,27 @@ __attribute__((amdgpu_waves_per_eu(kThreads == 512 ? 4 : 1))) void mlp_fwd_kerne
 // points: gamma, h1, h2, the weights, and the adjoints d2 = dL/da2 and
 // d1 = dL/da1 are bf16 (matrix-core operands); every sum is fp32.
 //
-// A block of 4 waves takes 64 points at a time, 16 per wave.  Phase A: each
-// wave recomputes its tile's forward in the transposed orientation (rows =
-// units, columns = points), forms dz, d2 = [a2 > 0] dz w3 and
-// d1 = [a1 > 0] W2^T d2 (W2^T from the A2t tiles, whose K order matches the
-// fragments of d2), and stores bf16 gamma, h1, d2, d1 into LDS as
-// [unit][point] rows.  Phase B: the weight gradients contract over points, so
-// each operand lane needs 8 consecutive points of one unit -- one 16-byte LDS
-// read from those rows; wave w owns rows [RO w, RO w + RO) of the 16-unit row
-// tiles of dW2 and dW1 and accumulates them over every batch in registers.
-// Per-block partial gradients go to a workspace; a second kernel sums the
-// blocks in a fixed order (deterministic, no float atomics).
-constexpr int kBwdBlocks = 256;  // one block per CU (LDS-limited)
-constexpr int kBwdBatch = 64;    // points per block iteration
-constexpr int kRowStride = kBwdBatch + 8;  // bf16 elements per staged row (144 B)
+// Two orientations of a 16x16 tile.  Unit-major: a lane holds 8 units of one
+// point (the layout the forward layers consume as K).  Point-major: a lane
+// holds 8 points of one unit -- 4 from each of two 16-point tiles -- which is
+// the operand layout of the weight gradients, whose K runs over points.  An
+// MFMA's A and B operands share one lane layout, so a unit-major fragment fed
+// as A against a 0/1 selector B comes out of the accumulator point-major,
+// exactly (one nonzero product per output); this transposes h1, d2 and gamma
+// on the matrix cores.  d1 is produced point-major directly, with d2 as the A
+// operand and W2^T tiles as B (their N order matching the transposed h1).
+//
+// Each wave takes 32 points (one chunk) per iteration and keeps its own fp32
+// dW2 tiles for the whole launch (H^2/64 values per lane: the accumulation
+// registers).  dW1 is shared out instead: each wave writes its chunk's d1 and
+// gamma fragments to an LDS slot, and wave w accumulates dW1's row tiles
+// [w H/64, (w+1) H/64) over the four slots, in slot order, one iteration
+// later.  At the end the block's waves add their dW2 tiles in LDS in a fixed
+// order and the block writes one partial; a second kernel sums the blocks in
+// index order (deterministic, no float atomics).
+constexpr int kBwdWaves = 4;  // waves per block
+
+__host__ __device__ inline int bwd_blocks(int H) { return H == 64 ? 512 : 256; }
 
 struct BwdArgs {
   const __bf16* packed;
@@ -379,238 +399,447 @@ struct BwdArgs {
   float* partial;  // [gridDim.x][param count]
 };
 
-__device__ __forceinline__ float bf16_round(float v) { return (float)(__bf16)v; }
+__device__ __forceinline__ bf16x8 pack_pair(const f32x4& x, const f32x4& y) {
+  const float v[8] = {x[0], x[1], x[2], x[3], y[0], y[1], y[2], y[3]};
+  return pack8(v);
+}
+
+// x where the matching value of m (a relu output, never negative) is
+// positive, else +0; both eight bf16 wide.  Per 16-bit half: min(m, 1) is 1
+// or 0 and multiplies x's bits.
+__device__ __forceinline__ bf16x8 mask_positive(bf16x8 x, bf16x8 m) {
+  typedef unsigned uint4v __attribute__((ext_vector_type(4)));
+  const uint4v xv = __builtin_bit_cast(uint4v, x), mv = __builtin_bit_cast(uint4v, m);
+  uint4v r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    unsigned one;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(one) : "v"(mv[q]), "s"(0x00010001u));
+    asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(r[q]) : "v"(xv[q]), "v"(one));
+  }
+  return __builtin_bit_cast(bf16x8, r);
+}
+
+// acc[q] += a b[q] (q < N) with acc held in the accumulation registers.  The
+// compiler places an MFMA's accumulator in one register file for the whole
+// kernel; written out here, dW2's N^2/4 x 64 values sit in AGPRs while the
+// other products keep their results in VGPRs for the VALU work that follows.
+// Being opaque to the hazard checks, the block pads itself: 4 wait states for
+// VALU writes of a and b before it, 8 for its own operand reads after it.
+template <int N>
+__device__ __forceinline__ void mfma_agpr_row(f32x4 (&acc)[N], const bf16x8& a,
+                                              const bf16x8 (&b)[N]);
+template <>
+__device__ __forceinline__ void mfma_agpr_row<8>(f32x4 (&acc)[8], const bf16x8& a,
+                                                 const bf16x8 (&b)[8]) {
+  asm volatile(
+      "s_nop 3\n\t"
+      "v_mfma_f32_16x16x32_bf16 %0, %8, %9, %0\n\t"
+      "v_mfma_f32_16x16x32_bf16 %1, %8, %10, %1\n\t"
+      "v_mfma_f32_16x16x32_bf16 %2, %8, %11, %2\n\t"
+      "v_mfma_f32_16x16x32_bf16 %3, %8, %12, %3\n\t"
+      "v_mfma_f32_16x16x32_bf16 %4, %8, %13, %4\n\t"
+      "v_mfma_f32_16x16x32_bf16 %5, %8, %14, %5\n\t"
+      "v_mfma_f32_16x16x32_bf16 %6, %8, %15, %6\n\t"
+      "v_mfma_f32_16x16x32_bf16 %7, %8, %16, %7\n\t"
+      "s_nop 7"
+      : "+a"(acc[0]), "+a"(acc[1]), "+a"(acc[2]), "+a"(acc[3]), "+a"(acc[4]), "+a"(acc[5]),
+        "+a"(acc[6]), "+a"(acc[7])
+      : "v"(a), "v"(b[0]), "v"(b[1]), "v"(b[2]), "v"(b[3]), "v"(b[4]), "v"(b[5]), "v"(b[6]),
+        "v"(b[7]));
+}
+template <>
+__device__ __forceinline__ void mfma_agpr_row<4>(f32x4 (&acc)[4], const bf16x8& a,
+                                                 const bf16x8 (&b)[4]) {
+  asm volatile(
+      "s_nop 3\n\t"
+      "v_mfma_f32_16x16x32_bf16 %0, %4, %5, %0\n\t"
+      "v_mfma_f32_16x16x32_bf16 %1, %4, %6, %1\n\t"
+      "v_mfma_f32_16x16x32_bf16 %2, %4, %7, %2\n\t"
+      "v_mfma_f32_16x16x32_bf16 %3, %4, %8, %3\n\t"
+      "s_nop 7"
+      : "+a"(acc[0]), "+a"(acc[1]), "+a"(acc[2]), "+a"(acc[3])
+      : "v"(a), "v"(b[0]), "v"(b[1]), "v"(b[2]), "v"(b[3]));
+}
+
+__device__ __forceinline__ f32x4 mfma(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 template <int H>
-__global__ __launch_bounds__(256) void mlp_bwd_kernel(BwdArgs a) {
-  constexpr int MT = H / 16, KS = H / 32, RO = MT / 4, RS = kRowStride;
+__global__ __launch_bounds__(kBwdWaves * kWave)
+__attribute__((amdgpu_waves_per_eu(H == 64 ? 2 : 1, H == 64 ? 2 : 1)))
+void mlp_bwd_kernel(BwdArgs a) {
+  constexpr int MT = H / 16, KS = H / 32;
   const PackOffsets ko(H);
   const ParamOffsets po(H);
-  __shared__ bf16x8 sA1[MT * 2 * 64];
-  __shared__ bf16x8 sA2[MT * KS * 64];
-  __shared__ bf16x8 sA2t[MT * KS * 64];
-  __shared__ float sb1[H], sb2[H], sw3[H];
-  __shared__ __attribute__((aligned(16))) __bf16 sH1[H * RS];
-  __shared__ __attribute__((aligned(16))) __bf16 sD2[H * RS];
-  __shared__ __attribute__((aligned(16))) __bf16 sD1[H * RS];
-  __shared__ __attribute__((aligned(16))) __bf16 sG[48 * RS];
-  __shared__ float sRed[4][H + 1];
+  // operand tiles and the d1 / gamma exchange slots, then (after the loop)
+  // the block's reduction buffer
+  constexpr int kTiles = MT * 2 + 2 * MT * KS + KS + 4;
+  constexpr int kSlot = MT + 3;  // fragments per wave: d1 row tiles, gamma tiles
+  constexpr int RT = MT / kBwdWaves;  // dW1 row tiles owned by each wave
+  constexpr int kBytes = (kTiles + kBwdWaves * kSlot) * 64 * 16 + 2 * H * 4;
+  static_assert(kBwdWaves * 16 * H * 4 <= kTiles * 64 * 16, "reduction buffer");
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  bf16x8* sA1 = reinterpret_cast<bf16x8*>(smem);  // layer 1, A operand
+  bf16x8* sA2 = sA1 + MT * 2 * 64;                 // layer 2, A operand
+  bf16x8* sA2t = sA2 + MT * KS * 64;               // W2^T, B operand of d1
+  bf16x8* sA3 = sA2t + MT * KS * 64;               // w3 in row 0
+  bf16x8* sSel = sA3 + KS * 64;                    // 0/1 selectors
+  float* sb2 = reinterpret_cast<float*>(sSel + 4 * 64);
+  float* sw3 = sb2 + H;  // w3 at unit_of(s, g, j), as [s][g][j]
+  bf16x8* sX = reinterpret_cast<bf16x8*>(sw3 + H);  // [wave][kSlot][64]
   {
     const bf16x8* src = reinterpret_cast<const bf16x8*>(a.packed);
     for (int i = threadIdx.x; i < MT * 2 * 64; i += blockDim.x) sA1[i] = src[i];
     const bf16x8* src2 = reinterpret_cast<const bf16x8*>(a.packed + ko.A2);
-    for (int i = threadIdx.x; i < MT * KS * 64; i += blockDim.x) sA2[i] = src2[i];
-    const bf16x8* src3 = reinterpret_cast<const bf16x8*>(a.packed + ko.A2t);
-    for (int i = threadIdx.x; i < MT * KS * 64; i += blockDim.x) sA2t[i] = src3[i];
+    for (int i = threadIdx.x; i < 2 * MT * KS * 64; i += blockDim.x) sA2[i] = src2[i];
+    for (int i = threadIdx.x; i < KS * 64; i += blockDim.x) {
+      const int s3 = i / 64, l = i % 64;
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        v[e] = (l % 16 == 0) ? a.packed[ko.w3 + unit_of(s3, l / 16, e)] : (__bf16)0.0f;
+      sA3[i] = v;
+    }
+    // selector k of lane (n, g), element j: B[8g + j][n] = 1 where
+    //   k = 0: 8g + j == n        (K rows 0..15)
+    //   k = 1: 8g + j == 16 + n   (K rows 16..31)
+    //   k = 2: n < 8 and 8g + j == 16 + n
+    //   k = 3: n >= 8 and 8g + j == 8 + n
+    for (int i = threadIdx.x; i < 4 * 64; i += blockDim.x) {
+      const int k = i / 64, l = i % 64, n = l % 16, gg = l / 16;
+      const int row = k == 0 ? n : k == 1 ? 16 + n : k == 2 ? (n < 8 ? 16 + n : -1)
+                                                            : (n >= 8 ? 8 + n : -1);
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (__bf16)(8 * gg + e == row ? 1.0f : 0.0f);
+      sSel[i] = v;
+    }
+    const bf16x8 zero8 = {};
+    for (int i = threadIdx.x; i < kBwdWaves * kSlot * 64; i += blockDim.x) sX[i] = zero8;
     for (int i = threadIdx.x; i < H; i += blockDim.x) {
-      sb1[i] = a.params[po.b1 + i];
       sb2[i] = a.params[po.b2 + i];
-      sw3[i] = (float)a.packed[ko.w3 + i];
+      const int s = i / 32, gg = (i / 8) % 4, j = i % 8;
+      sw3[i] = (float)a.packed[ko.w3 + unit_of(s, gg, j)];
     }
     __syncthreads();
   }
   const float b3 = a.params[po.b3];
   const int ln = lane(), g = ln >> 4, col = ln & 15, w = threadIdx.x / kWave;
   const int64_t n_points = (int64_t)a.n_rays * a.n_bins;
-  const int64_t n_batches = (n_points + kBwdBatch - 1) / kBwdBatch;
+  const int64_t n_chunks = (n_points + 31) / 32;
+  // chunk groups of kBwdWaves chunks: block b takes groups b, b + gridDim.x,
+  // ...; wave w takes chunk kBwdWaves group + w (past the end: no valid points,
+  // so the wave still meets the block's barriers and adds zeros)
+  const int64_t n_groups = (n_chunks + kBwdWaves - 1) / kBwdWaves;
 
-  f32x4 acc2[RO][MT], acc1[RO][3];
-#pragma unroll
-  for (int r = 0; r < RO; ++r) {
-#pragma unroll
-    for (int m = 0; m < MT; ++m) acc2[r][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int m = 0; m < 3; ++m) acc1[r][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  }
-  float db2p[RO];
-#pragma unroll
-  for (int r = 0; r < RO; ++r) db2p[r] = 0.0f;
-  float acc3[MT][4];
+  f32x4 acc2[MT][MT], acc1[RT][3];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc3[m][i] = 0.0f;
-  float acc_b3 = 0.0f;
-
-  const int pc = 16 * w + col;  // column of this lane's point in the staged rows
-  // inputs of the current batch, fetched one batch ahead (before phase B)
-  PointIn in{};
-  float dsig = 0.0f;
-  {
-    const int64_t p = (int64_t)blockIdx.x * kBwdBatch + pc;
-    if (p < n_points) {
-      in = load_point(a, p);
-      dsig = a.d_sigma[p];
-    }
-  }
-  for (int64_t batch = blockIdx.x; batch < n_batches; batch += gridDim.x) {
-    // ---------------- phase A: this wave's 16 points
-    const int64_t p = batch * kBwdBatch + pc;
-    const bool valid = p < n_points;
-    bf16x8 B1[2];
-    {
-      float y[3] = {0.0f, 0.0f, 0.0f};
-      if (valid) encode_loaded(a, in, y);
-      const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
-      features(xa, g, B1[0], B1[1]);
-      if (g < 3) {
+    for (int q = 0; q < MT; ++q) acc2[m][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int q = 0; q < 16; ++q) sG[(16 * g + q) * RS + pc] = B1[q / 8][q % 8];
-      }
+  for (int m = 0; m < RT; ++m)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc1[m][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // dW1 += d1 gamma^T for this wave's row tiles, over every wave's points of
+  // the last group (slots in wave order: a fixed summation order)
+  const auto consume = [&]() {
+    bf16x8 q[2][3 + RT];  // one source wave's fragments, the next one's in flight
+    const auto load = [&](int v, bf16x8 (&d)[3 + RT]) {
+      const bf16x8* slot = sX + v * kSlot * 64;
+#pragma unroll
+      for (int F = 0; F < 3; ++F) d[F] = slot[(MT + F) * 64 + ln];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) d[3 + r] = slot[(RT * w + r) * 64 + ln];
+    };
+    load(0, q[0]);
+#pragma unroll
+    for (int v = 0; v < kBwdWaves; ++v) {
+      if (v + 1 < kBwdWaves) load(v + 1, q[(v + 1) % 2]);
+      const bf16x8(&d)[3 + RT] = q[v % 2];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int F = 0; F < 3; ++F) acc1[r][F] = mfma(d[3 + r], d[F], acc1[r][F]);
     }
-    bf16x8 B2[KS];
+  };
+  // dw3 and db2 partials of unit pm_unit(m, col), over this lane's points
+  float acc3[MT], db2p[MT], db3p = 0.0f;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc3[m] = db2p[m] = 0.0f;
+
+  // Per chunk: the raw inputs and features, then the phases below.  The
+  // previous group's dW1 products run beside the d2 arithmetic.  Out-of-range
+  // points load the last point (clamped, so no branch splits the scheduling
+  // regions) and are zeroed through ds.  Weight tiles are read two steps ahead
+  // of their products (the wq, w1q, wtq rings): LDS latency is then covered by
+  // the products in between, which with one wave per SIMD nothing else covers.
+  const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  bf16x8* slot_w = sX + w * kSlot * 64;
+  PointIn in[2];
+  float dsig[2];
+  const auto fetch = [&](int64_t chunk) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int64_t p = min(chunk * 32 + 16 * t + col, n_points - 1);
+      in[t] = load_point(a, p);
+      dsig[t] = a.d_sigma[p];
+    }
+  };
+  bf16x8 B1[2][2];
+  float ds[2];
+  const auto encode_chunk = [&](int64_t chunk) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const bool valid = chunk * 32 + 16 * t + col < n_points;
+      float y[3];
+      encode_loaded(a, in[t], y);
+      const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
+      features(valid ? xa : 0.0f, g, B1[t][0], B1[t][1]);
+      ds[t] = valid ? dsig[t] : 0.0f;
+    }
+  };
+
+  // the four 0/1 selectors stay in registers for the whole loop
+  const bf16x8 sel[4] = {sSel[ln], sSel[64 + ln], sSel[128 + ln], sSel[192 + ln]};
+  for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    const int64_t c = grp * kBwdWaves + w;
+    // The operand tiles never change, so their LDS reads are loop-invariant:
+    // hoisted, they would pin ~5H registers for the whole loop.  An offset of
+    // zero the compiler cannot see through keeps each read next to its use.
+    int opaque;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(opaque));
+    const int li = ln + opaque;
+    fetch(c);
+    encode_chunk(c);
+    // gamma point-major, and layer 1 unit-major (K-step s of layer 2 = row
+    // tiles 2s and 2s+1)
+    bf16x8 G[3];
+    {
+      const bf16x8 e0 = sel[0], e2 = sel[2], e3 = sel[3];
+      f32x4 c0[2], c1[2], c2[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        c0[t] = mfma(B1[t][0], e0, zero);
+        c1[t] = mfma(B1[t][1], e0, zero);
+        c2[t] = mfma(B1[t][1], e3, mfma(B1[t][0], e2, zero));
+      }
+      G[0] = pack_pair(c0[0], c0[1]);
+      G[1] = pack_pair(c1[0], c1[1]);
+      G[2] = pack_pair(c2[0], c2[1]);
+    }
+    bf16x8 B2[2][KS];
+    bf16x8 w1q[4];
+    w1q[0] = sA1[li];
+    w1q[1] = sA1[64 + li];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      f32x4 hh[2];
+      f32x4 hh[2][2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int m = 2 * s + h;
-        const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};  // b1 arrives through K
-        f32x4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA1[(m * 2 + 0) * 64 + ln], B1[0], zero,
-                                                           0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA1[(m * 2 + 1) * 64 + ln], B1[1], c, 0, 0, 0);
-        hh[h] = c;
+        if (m + 1 < MT) {
+          w1q[(2 * m + 2) % 4] = sA1[(2 * m + 2) * 64 + li];
+          w1q[(2 * m + 3) % 4] = sA1[(2 * m + 3) * 64 + li];
+        }
+        const bf16x8 w0 = w1q[(2 * m) % 4], w1 = w1q[(2 * m + 1) % 4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) hh[t][h] = mfma(w1, B1[t][1], mfma(w0, B1[t][0], zero));
       }
-      const float v[8] = {hh[0][0], hh[0][1], hh[0][2], hh[0][3],
-                          hh[1][0], hh[1][1], hh[1][2], hh[1][3]};
-      B2[s] = pack8_relu(v);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sH1[(16 * (2 * s + j / 4) + 4 * g + j % 4) * RS + pc] = B2[s][j];
+      for (int t = 0; t < 2; ++t) {
+        const float v[8] = {hh[t][0][0], hh[t][0][1], hh[t][0][2], hh[t][0][3],
+                            hh[t][1][0], hh[t][1][1], hh[t][1][2], hh[t][1][3]};
+        B2[t][s] = pack8_relu(v);
+      }
     }
-    // layer 2, all row tiles kept for the masks
-    f32x4 a2[MT];
-    float z = 0.0f;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      f32x4 c = {sb2[16 * m + 4 * g], sb2[16 * m + 4 * g + 1], sb2[16 * m + 4 * g + 2],
-                 sb2[16 * m + 4 * g + 3]};
-#pragma unroll
-      for (int s = 0; s < KS; ++s)
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA2[(m * KS + s) * 64 + ln], B2[s], c, 0, 0, 0);
-      a2[m] = c;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) z = fmaf(bf16_round(fmaxf(c[i], 0.0f)), sw3[16 * m + 4 * g + i], z);
-    }
-    z += __shfl_xor(z, 16, kWave);
-    z += __shfl_xor(z, 32, kWave);
-    const float dz = valid ? dsig / (1.0f + expf(-(z + b3))) : 0.0f;
-    if (g == 0) acc_b3 += dz;
-    bf16x8 D2B[KS];
+    // layer 2, unit-major, as bf16 h2
+    bf16x8 H2[2][KS];
+    bf16x8 wq[3];
+    wq[0] = sA2[li];
+    wq[1] = sA2[64 + li];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      float v[8];
+      f32x4 cc[2][2];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int m = 2 * s + j / 4, i = j % 4, u = 16 * m + 4 * g + i;
-        const float h2 = bf16_round(fmaxf(a2[m][i], 0.0f));
-        acc3[m][i] = fmaf(dz, h2, acc3[m][i]);
-        v[j] = a2[m][i] > 0.0f ? dz * sw3[u] : 0.0f;
+      for (int h = 0; h < 2; ++h) {
+        const int m = 2 * s + h;
+        const f32x4 bias = *reinterpret_cast<const f32x4*>(&sb2[16 * m + 4 * g + opaque]);
+        cc[0][h] = bias;
+        cc[1][h] = bias;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+          const int idx = m * KS + k;
+          if (idx + 2 < MT * KS) wq[(idx + 2) % 3] = sA2[(idx + 2) * 64 + li];
+          const bf16x8 wv = wq[idx % 3];
+#pragma unroll
+          for (int t = 0; t < 2; ++t) cc[t][h] = mfma(wv, B2[t][k], cc[t][h]);
+        }
       }
-      D2B[s] = pack8(v);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sD2[(16 * (2 * s + j / 4) + 4 * g + j % 4) * RS + pc] = D2B[s][j];
+      for (int t = 0; t < 2; ++t) {
+        const float v[8] = {cc[t][0][0], cc[t][0][1], cc[t][0][2], cc[t][0][3],
+                            cc[t][1][0], cc[t][1][1], cc[t][1][2], cc[t][1][3]};
+        H2[t][s] = pack8_relu(v);
+      }
     }
-    // d1 = [a1 > 0] W2^T d2, K over layer-2 units in the fragments' order
+    // z = w3 . h2 + b3 on the matrix cores (row 0 of the product), then dz;
+    // beside it, h1 point-major
+    float dz[2];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < 2; ++t) {
+      f32x4 zt = zero;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) zt = mfma(sA3[s * 64 + li], H2[t][s], zt);
+      const float z = __shfl(zt[0], col, kWave);
+      dz[t] = ds[t] / (1.0f + expf(-(z + b3)));
+    }
+    if (g == 0) db3p += dz[0] + dz[1];
+    bf16x8 H1p[MT];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        const bf16x8 e = sel[hf];
+        H1p[2 * s + hf] = pack_pair(mfma(B2[0][s], e, zero), mfma(B2[1][s], e, zero));
+      }
+    // d2 = [a2 > 0] dz w3 (unit-major, bf16); dw3 += h2 dz with h2
+    // point-major (unit col, points 4g + r) and dz of those points; beside
+    // them, dW1 from the previous group's slots
+    bf16x8 D2[2][KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const f32x4 wlo = *reinterpret_cast<const f32x4*>(&sw3[(4 * s + g) * 8 + opaque]);
+      const f32x4 whi = *reinterpret_cast<const f32x4*>(&sw3[(4 * s + g) * 8 + 4 + opaque]);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const float v[8] = {dz[t] * wlo[0], dz[t] * wlo[1], dz[t] * wlo[2], dz[t] * wlo[3],
+                            dz[t] * whi[0], dz[t] * whi[1], dz[t] * whi[2], dz[t] * whi[3]};
+        D2[t][s] = mask_positive(pack8(v), H2[t][s]);
+      }
+    }
+    {
+      float dzp[2][4];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dzp[t][r] = __shfl(dz[t], 4 * g + r, kWave);
 #pragma unroll
       for (int s = 0; s < KS; ++s)
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sA2t[(m * KS + s) * 64 + ln], D2B[s], c, 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const bool on = (float)B2[m / 2][4 * (m % 2) + i] > 0.0f;
-        sD1[(16 * m + 4 * g + i) * RS + pc] = (__bf16)(on ? c[i] : 0.0f);
-      }
+        for (int hf = 0; hf < 2; ++hf) {
+          const bf16x8 e = sel[hf];
+          const f32x4 x = mfma(H2[0][s], e, zero), y = mfma(H2[1][s], e, zero);
+          float v = acc3[2 * s + hf];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v = fmaf(x[r], dzp[0][r], fmaf(y[r], dzp[1][r], v));
+          acc3[2 * s + hf] = v;
+        }
     }
-    __syncthreads();
-    {
-      const int64_t pn = (batch + gridDim.x) * kBwdBatch + pc;
-      if (pn < n_points) {
-        in = load_point(a, pn);
-        dsig = a.d_sigma[pn];
+    consume();  // the first group's slots hold zeros
+    // d1 = [a1 > 0] W2^T d2, point-major, into this wave's slot with gamma
+    __syncthreads();  // every wave has consumed the slots of the last group
+#pragma unroll
+    for (int F = 0; F < 3; ++F) slot_w[(MT + F) * 64 + ln] = G[F];
+    bf16x8 wtq[3];
+    wtq[0] = sA2t[li];
+    wtq[1] = sA2t[64 + li];
+#pragma unroll
+    for (int T = 0; T < MT; ++T) {
+      f32x4 cc[2] = {zero, zero};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int idx = T * KS + s;
+        if (idx + 2 < MT * KS) wtq[(idx + 2) % 3] = sA2t[(idx + 2) * 64 + li];
+        const bf16x8 wt = wtq[idx % 3];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) cc[t] = mfma(D2[t][s], wt, cc[t]);
       }
+      slot_w[T * 64 + ln] = mask_positive(pack_pair(cc[0], cc[1]), H1p[T]);
     }
-    // ---------------- phase B: contract over the batch's 64 points
+    // d2 point-major; db2 += its column sums; dW2 += d2 h1^T; beside them,
+    // the next chunk's features
 #pragma unroll
-    for (int ks = 0; ks < kBwdBatch / 32; ++ks) {
-      const int kp = 32 * ks + 8 * g;
-      bf16x8 AD2[RO], AD1[RO];
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
-      for (int r = 0; r < RO; ++r) {
-        const int row = 16 * (RO * w + r) + col;
-        AD2[r] = *reinterpret_cast<const bf16x8*>(&sD2[row * RS + kp]);
-        AD1[r] = *reinterpret_cast<const bf16x8*>(&sD1[row * RS + kp]);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) db2p[r] += (float)AD2[r][j];
+      for (int hf = 0; hf < 2; ++hf) {
+        const bf16x8 e = sel[hf];
+        const f32x4 x = mfma(D2[0][s], e, zero), y = mfma(D2[1][s], e, zero);
+        const int To = 2 * s + hf;
+        db2p[To] += ((x[0] + x[1]) + (x[2] + x[3])) + ((y[0] + y[1]) + (y[2] + y[3]));
+        const bf16x8 d2p = pack_pair(x, y);
+        mfma_agpr_row<MT>(acc2[To], d2p, H1p);
       }
-#pragma unroll
-      for (int mf = 0; mf < MT; ++mf) {
-        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sH1[(16 * mf + col) * RS + kp]);
-#pragma unroll
-        for (int r = 0; r < RO; ++r)
-          acc2[r][mf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AD2[r], bh, acc2[r][mf], 0, 0, 0);
-      }
-#pragma unroll
-      for (int gf = 0; gf < 3; ++gf) {
-        const bf16x8 bg = *reinterpret_cast<const bf16x8*>(&sG[(16 * gf + col) * RS + kp]);
-#pragma unroll
-        for (int r = 0; r < RO; ++r)
-          acc1[r][gf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AD1[r], bg, acc1[r][gf], 0, 0, 0);
-      }
-    }
-    __syncthreads();
+    __syncthreads();  // this group's slots are complete
   }
+  if (n_groups > blockIdx.x) consume();
 
-  // ---------------- per-block partial gradients
-  const int64_t P = po.total;
-  float* out = a.partial + (int64_t)blockIdx.x * P;
+  // the last accumulation MFMAs' results before any read of them
+  asm volatile("s_nop 15\n\ts_nop 15" ::: "memory");
+  // ---------------- the block's partial: waves added in LDS in index order
+  float* red = reinterpret_cast<float*>(smem);
+  float* out = a.partial + (int64_t)blockIdx.x * po.total;
+  // db2, dw3: sums over the lane groups
 #pragma unroll
-  for (int r = 0; r < RO; ++r) {
+  for (int m = 0; m < MT; ++m) {
+    db2p[m] += __shfl_xor(db2p[m], 16, kWave);
+    db2p[m] += __shfl_xor(db2p[m], 32, kWave);
+    acc3[m] += __shfl_xor(acc3[m], 16, kWave);
+    acc3[m] += __shfl_xor(acc3[m], 32, kWave);
+  }
+  db3p += __shfl_xor(db3p, 1, kWave);
+  db3p += __shfl_xor(db3p, 2, kWave);
+  db3p += __shfl_xor(db3p, 4, kWave);
+  db3p += __shfl_xor(db3p, 8, kWave);
+  __syncthreads();  // every wave is past its last read of the operand tiles
+  // One 16-unit row tile at a time: each wave stores its values for the tile
+  // into a region of its own (row n = 4g + r of the accumulator, so only
+  // stores), then the block sums the regions in wave order and writes the
+  // tile's rows.  Rows of point-major tile T: pm_unit(T, n).
+  constexpr int kSlab = 16 * H;  // floats per wave region
+  float* mine = red + w * kSlab;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int o = 16 * (RO * w + r) + 4 * g + i;
+  for (int To = 0; To < MT; ++To) {
 #pragma unroll
-      for (int mf = 0; mf < MT; ++mf) out[po.W2 + (int64_t)o * H + 16 * mf + col] = acc2[r][mf][i];
+    for (int Ti = 0; Ti < MT; ++Ti)
 #pragma unroll
-      for (int gf = 0; gf < 3; ++gf) {
-        const int f = feature_of(gf, col);
-        if (f >= 0) out[po.W1 + (int64_t)o * kNF + f] = acc1[r][gf][i];
+      for (int r = 0; r < 4; ++r) mine[(4 * g + r) * H + pm_unit(Ti, col)] = acc2[To][Ti][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < kSlab; e += blockDim.x) {
+      const float v = ((red[e] + red[kSlab + e]) + red[2 * kSlab + e]) + red[3 * kSlab + e];
+      out[po.W2 + (int64_t)pm_unit(To, e / H) * H + e % H] = v;
+    }
+    __syncthreads();
+  }
+  // dW1 and db1: this wave's row tiles, each owned by one wave of the block
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int F = 0; F < 3; ++F) {
+      const int f = pm_feature(F, col);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = pm_unit(RT * w + r, 4 * g + q);
+        if (f >= 0) out[po.W1 + o * kNF + f] = acc1[r][F][q];
+        // column 5 of tile 1 is slot 13 of axis 0, the constant 1 that
+        // carries b1: its dW1 column is db1
+        if (F == 1 && col == 5) out[po.b1 + o] = acc1[r][F][q];
       }
-      // feature slot 13 of lane group 0 is the constant 1 that carries b1, so
-      // its column of dW1 is db1 = sum over points of d1
-      if (col == 13) out[po.b1 + o] = acc1[r][0][i];
     }
-    float s2 = db2p[r];
-    s2 += __shfl_xor(s2, 16, kWave);
-    s2 += __shfl_xor(s2, 32, kWave);
-    if (g == 0) out[po.b2 + 16 * (RO * w + r) + col] = s2;
-  }
-  // dw3, db3: sum over the 16 point columns, then over the 4 waves in order
+  // b2, w3, b3 as one vector [b2 | w3 | b3] per wave
+  if (g == 0) {
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float v = acc3[m][i];
-      v += __shfl_xor(v, 1, kWave);
-      v += __shfl_xor(v, 2, kWave);
-      v += __shfl_xor(v, 4, kWave);
-      v += __shfl_xor(v, 8, kWave);
-      if (col == 0) sRed[w][16 * m + 4 * g + i] = v;
+    for (int m = 0; m < MT; ++m) {
+      mine[pm_unit(m, col)] = db2p[m];
+      mine[H + pm_unit(m, col)] = acc3[m];
     }
-  {
-    float v = acc_b3;
-    v += __shfl_xor(v, 1, kWave);
-    v += __shfl_xor(v, 2, kWave);
-    v += __shfl_xor(v, 4, kWave);
-    v += __shfl_xor(v, 8, kWave);
-    if (ln == 0) sRed[w][H] = v;
   }
+  if (ln == 0) mine[2 * H] = db3p;
   __syncthreads();
-  for (int u = threadIdx.x; u <= H; u += blockDim.x) {
-    const float v = ((sRed[0][u] + sRed[1][u]) + sRed[2][u]) + sRed[3][u];
-    out[u < H ? po.w3 + u : po.b3] = v;
-  }
+  for (int e = threadIdx.x; e < 2 * H + 1; e += blockDim.x)
+    out[po.b2 + e] = ((red[e] + red[kSlab + e]) + red[2 * kSlab + e]) + red[3 * kSlab + e];
 }
 
 // grad[i] = sum over blocks of partial[b][i], blocks in index order
@@ -690,7 +919,7 @@ extern "C" txs_status txs_prop_mlp_fwd(const txs_mlp* mlp, const float* rays_o,
 
 extern "C" size_t txs_mlp_bwd_workspace_size(int32_t hidden) {
   if (hidden != 64 && hidden != 128) return 0;
-  return (size_t)txs::kBwdBlocks * (size_t)txs::ParamOffsets(hidden).total * sizeof(float);
+  return (size_t)txs::bwd_blocks(hidden) * (size_t)txs::ParamOffsets(hidden).total * sizeof(float);
 }
 
 extern "C" txs_status txs_prop_mlp_bwd(const txs_mlp* mlp, const float* rays_o,
@@ -705,8 +934,9 @@ extern "C" txs_status txs_prop_mlp_bwd(const txs_mlp* mlp, const float* rays_o,
   const int H = mlp->hidden;
   const int64_t P = ParamOffsets(H).total;
   const int64_t n_points = (int64_t)n_rays * n_bins;
-  const int64_t n_batches = (n_points + kBwdBatch - 1) / kBwdBatch;
-  const int blocks = (int)std::min<int64_t>(n_batches, kBwdBlocks);
+  const int64_t n_chunks = (n_points + 31) / 32;  // 32 points per wave iteration
+  const int blocks =
+      (int)std::min<int64_t>((n_chunks + kBwdWaves - 1) / kBwdWaves, bwd_blocks(H));
   if (blocks > 0) {
     TXS_REQUIRE(rays_o && rays_d && edges && d_sigma, "txs_prop_mlp_bwd: null array");
     TXS_REQUIRE(workspace, "txs_prop_mlp_bwd: null workspace");
@@ -717,9 +947,11 @@ extern "C" txs_status txs_prop_mlp_bwd(const txs_mlp* mlp, const float* rays_o,
               mlp->contract, rays_o, rays_d, n_rays, n_bins, FastDiv((uint32_t)n_bins),
               n_points < ((int64_t)1 << 32), edges, d_sigma, static_cast<float*>(workspace)};
     if (H == 64)
-      hipLaunchKernelGGL(mlp_bwd_kernel<64>, dim3(blocks), dim3(256), 0, as_stream(stream), a);
+      hipLaunchKernelGGL(mlp_bwd_kernel<64>, dim3(blocks), dim3(kBwdWaves * kWave), 0,
+                         as_stream(stream), a);
     else
-      hipLaunchKernelGGL(mlp_bwd_kernel<128>, dim3(blocks), dim3(256), 0, as_stream(stream), a);
+      hipLaunchKernelGGL(mlp_bwd_kernel<128>, dim3(blocks), dim3(kBwdWaves * kWave), 0,
+                         as_stream(stream), a);
     if (txs_status s = launch_status("txs_prop_mlp_bwd")) return s;
   }
   hipLaunchKernelGGL(sum_partials_kernel, dim3(grid_1d(P, 256)), dim3(256), 0, as_stream(stream),

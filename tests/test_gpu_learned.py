@@ -127,6 +127,10 @@ def assert_grad_close(got, ref, mag, name):
     (64, 300, 64, False),    # 300 batches: some blocks take two
     (128, 400, 48, False),
     (128, 300, 40, True),
+    # more 32-point chunks than waves (1024 at hidden 128, 2048 at hidden 64):
+    # each wave carries its gradient tiles over several chunks; ragged tail
+    (128, 5000, 17, False),
+    (64, 6000, 13, True),
 ])
 def test_mlp_bwd_matches_emulated_oracle(gpu_lib, H, n_rays, n_bins, contract):
     params, o, d, edges, ds = mlp_case(gpu_lib, H, n_rays, n_bins, contract, seed=11 + H)
