@@ -49,7 +49,9 @@ __host__ __device__ inline size_t loss_lds_bytes(int nb) {
 // targets overlapping a bin form a contiguous run: the lane of bin j finds its
 // run by a binary search over the staged ranges and sums it in target order.
 // Rays with more than kChunk targets are staged in chunks, each bin carrying
-// its partial sum across them (same order).
+// its partial sum across them (same order).  kBinsPerLane = ceil(nb / 64)
+// rounded up to 1, 4 or 16: the bins' partial sums a lane carries.
+template <int kBinsPerLane>
 __global__ __launch_bounds__(kWave* kLossWaves) void hist_loss_kernel(
     const int32_t* __restrict__ info, const float* __restrict__ t0, const float* __restrict__ t1,
     const float* __restrict__ w, int32_t n_rays, int64_t n_targets, int32_t nb,
@@ -70,16 +72,28 @@ __global__ __launch_bounds__(kWave* kLossWaves) void hist_loss_kernel(
   wave_sync();
   int64_t st = info[2 * r], ct = info[2 * r + 1];
   if (st < 0 || ct < 0 || st + ct > n_targets) ct = 0;  // malformed row: no targets
-  constexpr int kBinsPerLane = kMaxBins / kWave;
   float gacc[kBinsPerLane];
 #pragma unroll
   for (int q = 0; q < kBinsPerLane; ++q) gacc[q] = 0.0f;
   float acc = 0.0f;
   for (int64_t c0 = 0; c0 < ct || c0 == 0; c0 += kChunk) {
     const int n = (int)min<int64_t>(kChunk, ct - c0);
+    // each lane's next target loads while its current one is processed
+    float na = 0.0f, nb_ = 0.0f, nw = 0.0f;
+    if (ln < n) {
+      const int64_t i = st + c0 + ln;
+      na = t0[i];
+      nb_ = t1[i];
+      nw = w[i];
+    }
     for (int k = ln; k < n; k += kWave) {
-      const int64_t i = st + c0 + k;
-      const float a = t0[i], b = t1[i], wi = w[i];
+      const float a = na, b = nb_, wi = nw;
+      if (k + kWave < n) {
+        const int64_t i = st + c0 + k + kWave;
+        na = t0[i];
+        nb_ = t1[i];
+        nw = w[i];
+      }
       int jlo, jhi;
       bin_range(e, nb, a, b, jlo, jhi);
       float bound = 0.0f;
@@ -174,7 +188,10 @@ extern "C" txs_status txs_hist_loss(const int32_t* packed_info, int32_t n_rays, 
   TXS_REQUIRE(n_targets == 0 || (t0 && t1 && w), "txs_hist_loss: null target array");
   const int64_t blocks = ((int64_t)n_rays + kLossWaves - 1) / kLossWaves;
   const size_t lds = kLossWaves * loss_lds_bytes(n_bins);
-  hipLaunchKernelGGL(hist_loss_kernel, dim3((unsigned)blocks), dim3(kWave * kLossWaves), lds,
+  const auto kern = n_bins <= kWave       ? hist_loss_kernel<1>
+                    : n_bins <= 4 * kWave ? hist_loss_kernel<4>
+                                          : hist_loss_kernel<kMaxBins / kWave>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kWave * kLossWaves), lds,
                      as_stream(stream), packed_info, t0, t1, w, n_rays, n_targets, n_bins, edges,
                      prop_w, eps, 1.0f / (float)n_rays, loss, d_prop);
   return launch_status("txs_hist_loss");

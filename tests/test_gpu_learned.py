@@ -168,10 +168,10 @@ def test_mlp_bwd_deterministic_and_empty(gpu_lib):
 # ----------------------------------------------------------------------------
 # histogram loss, weights-only render, Adam
 # ----------------------------------------------------------------------------
-def target_histograms(n_rays, seed):
+def target_histograms(n_rays, seed, max_count=40, min_count=0):
     """Sorted disjoint target intervals with weights (a stand-in grid render)."""
     g = scenes.rng(seed)
-    counts = g.integers(0, 40, n_rays).astype(np.int32)
+    counts = g.integers(min_count, max_count, n_rays).astype(np.int32)
     info, S = oracle.exclusive_scan(counts)
     t0 = np.zeros(S, np.float32)
     t1 = np.zeros(S, np.float32)
@@ -197,6 +197,23 @@ def test_hist_loss(gpu_lib, nb):
     np.testing.assert_allclose(host(loss), rl, rtol=2e-5, atol=1e-7)
     np.testing.assert_allclose(host(d), rd, rtol=2e-5, atol=1e-9)
     assert (rl > 0).mean() > 0.3
+
+
+@pytest.mark.parametrize("nb", [16, 64, 200])
+def test_hist_loss_long_rays(gpu_lib, nb):
+    # rays of 400-1400 targets: the kernel stages 512 targets per pass and
+    # carries each bin's partial sum across the passes
+    n = 120
+    info, t0, t1, w = target_histograms(n, 60 + nb, max_count=1400, min_count=400)
+    g = scenes.rng(61)
+    edges = (1.5 + np.concatenate([np.zeros((n, 1)), np.cumsum(g.uniform(0, 1, (n, nb)), 1)],
+                                  1) * (3.0 / nb)).astype(np.float32)
+    pw = (g.exponential(1.0, (n, nb)) / nb * g.choice([0.2, 1.0], (n, 1))).astype(np.float32)
+    loss, d = gpu_lib.hist_loss(dev(info), dev(t0), dev(t1), dev(w), dev(edges), dev(pw))
+    rl, rd = oracle.hist_loss(info, t0, t1, w, edges, pw)
+    assert info[:, 1].max() > 1024
+    np.testing.assert_allclose(host(loss), rl, rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(host(d), rd, rtol=2e-5, atol=1e-9)
 
 
 def test_hist_loss_rejects_more_bins_than_its_limit(gpu_lib):
