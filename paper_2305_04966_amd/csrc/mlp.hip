@@ -842,14 +842,22 @@ void mlp_bwd_kernel(BwdArgs a) {
     out[po.b2 + e] = ((red[e] + red[kSlab + e]) + red[2 * kSlab + e]) + red[3 * kSlab + e];
 }
 
-// grad[i] = sum over blocks of partial[b][i], blocks in index order
-__global__ void sum_partials_kernel(const float* __restrict__ partial, int n_blocks, int64_t P,
-                                    float* __restrict__ grad) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
+// grad[i] = sum over blocks of partial[b][i] in binary64, in a fixed order:
+// a block takes 64 parameters; its thread (g, i) sums blocks b = g (mod 4) in
+// increasing order, and the four sums are added in g order.
+constexpr int kSumLanes = 64, kSumGroups = 4;
+__global__ __launch_bounds__(kSumLanes* kSumGroups) void sum_partials_kernel(
+    const float* __restrict__ partial, int n_blocks, int64_t P, float* __restrict__ grad) {
+  __shared__ double part[kSumGroups][kSumLanes];
+  const int li = threadIdx.x % kSumLanes, g = threadIdx.x / kSumLanes;
+  const int64_t i = (int64_t)blockIdx.x * kSumLanes + li;
   double s = 0.0;
-  for (int b = 0; b < n_blocks; ++b) s += (double)partial[(int64_t)b * P + i];
-  grad[i] = (float)s;
+  if (i < P)
+    for (int b = g; b < n_blocks; b += kSumGroups) s += (double)partial[(int64_t)b * P + i];
+  part[g][li] = s;
+  __syncthreads();
+  if (g == 0 && i < P)
+    grad[i] = (float)(((part[0][li] + part[1][li]) + part[2][li]) + part[3][li]);
 }
 
 txs_status check_mlp(const txs_mlp* m) {
@@ -954,7 +962,8 @@ extern "C" txs_status txs_prop_mlp_bwd(const txs_mlp* mlp, const float* rays_o,
                          as_stream(stream), a);
     if (txs_status s = launch_status("txs_prop_mlp_bwd")) return s;
   }
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(grid_1d(P, 256)), dim3(256), 0, as_stream(stream),
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((P + kSumLanes - 1) / kSumLanes)),
+                     dim3(kSumLanes * kSumGroups), 0, as_stream(stream),
                      static_cast<const float*>(workspace), blocks, P, grad);
   return launch_status("txs_prop_mlp_bwd");
 }

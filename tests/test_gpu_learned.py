@@ -123,6 +123,7 @@ def assert_grad_close(got, ref, mag, name):
 
 
 @pytest.mark.parametrize("H,n_rays,n_bins,contract", [
+    (128, 1, 1, False),      # a single point: one wave of one block has work
     (64, 3, 13, False),      # one partial batch
     (64, 300, 64, False),    # 300 batches: some blocks take two
     (128, 400, 48, False),
