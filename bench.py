@@ -75,9 +75,6 @@ def parse():
     ap.add_argument("--proposal-config", type=int, default=1,
                     help="time one proposal round at its own configuration (2^18 rays, hidden "
                          "64, 128 bins -> 32) (0 = skip)")
-    ap.add_argument("--march-masks", choices=("auto", "on", "off"), default="auto",
-                    help="the count pass records each lattice group's occupancy for the fill "
-                         "to replay (auto: on cascades of more than one level)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run a plain device copy of this many MiB (counter "
                          "calibration for profiler byte counts)")
@@ -137,17 +134,12 @@ def gpu_bench(args, w):
     N = w.n_rays
     tl = Timeline(torch)
     stats = {}
-    # the count pass records each lattice group's occupancy for the fill
-    use_masks = {"on": True, "off": False}.get(args.march_masks, txs.MarchMasks.pays(grid))
-    masks = (txs.MarchMasks(N, txs.MarchMasks.groups_for(grid, w.dt0), o.device)
-             if use_masks else None)
 
     def step():
-        counts = tl.run("march_count", txs.march_count, grid, o, d, dt0=w.dt0, masks=masks)
+        counts = tl.run("march_count", txs.march_count, grid, o, d, dt0=w.dt0)
         info, total = tl.run("exclusive_scan", txs.exclusive_scan, counts)
         sm = int(total.item())
-        t0, t1, rid = tl.run("march_fill", txs.march_fill, grid, o, d, info, sm, dt0=w.dt0,
-                             masks=masks)
+        t0, t1, rid = tl.run("march_fill", txs.march_fill, grid, o, d, info, sm, dt0=w.dt0)
         sig_ng, _ = tl.run("field_density", txs.blob_field, params, nb, o, d, t0, t1, rid,
                            want_rgb=False)
         kept = tl.run("transmittance_prefix", txs.transmittance_prefix, info, t0, t1, sig_ng,

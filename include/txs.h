@@ -178,40 +178,6 @@ txs_status txs_march_fill(const txs_grid* grid, const txs_march_params* params,
                           int32_t* ray_id, void* stream);
 
 /*
- * The same march with the count pass's tests kept for the fill (Section 3.1
- * "Spatial Skipping"; the fill of Section 4.2 "Sample as Interval").  A
- * wave marches one ray in groups of 64 consecutive lattice points; the count
- * records, per ray, the occupancy of every group it walks as one 64-bit mask
- * (bit i: lattice point 64 g + i of the segment is occupied and inside it),
- * and the fill replays the masks instead of testing the points again.  It
- * still evaluates each point's midpoint against the segment's end, so it
- * walks the same groups and emits, bit for bit, the samples of
- * txs_march_fill.
- *
- * masks: device uint64 [txs_march_mask_words(n_rays, groups_per_ray)],
- * caller-owned: per ray a row of groups_per_ray + 1 words, word 0 the number
- * of groups the count walked, words 1.. their masks.  A ray that walks more
- * than groups_per_ray groups (or that the skipping kernels march, when the
- * grid carries brick occupancy) is marked not replayable and the fill tests
- * its points as txs_march_fill does.  Single-level grids walk at most
- * 2 (ceil(chord / (128 dt0)) + 1) groups per segment, chord the cube's
- * longest chord; a cascade has 2 n_levels - 1 segments.
- * groups_per_ray in [0, 16384] (EINVAL otherwise); 0 records nothing.
- * txs_march_fill_masked must see the masks of txs_march_count_masked with the
- * same grid, params and rays (and groups_per_ray).
- */
-int64_t txs_march_mask_words(int32_t n_rays, int32_t groups_per_ray);
-txs_status txs_march_count_masked(const txs_grid* grid, const txs_march_params* params,
-                                  const float* rays_o, const float* rays_d, int32_t n_rays,
-                                  int32_t* counts, uint64_t* masks, int32_t groups_per_ray,
-                                  void* stream);
-txs_status txs_march_fill_masked(const txs_grid* grid, const txs_march_params* params,
-                                 const float* rays_o, const float* rays_d, int32_t n_rays,
-                                 const int32_t* packed_info, int64_t capacity, float* t0,
-                                 float* t1, int32_t* ray_id, const uint64_t* masks,
-                                 int32_t groups_per_ray, void* stream);
-
-/*
  * Grid estimator over contracted space (a variant for unbounded scenes, next
  * to the cascade of nested cubes; Section 3.2, "Handling Unbounded Scenes",
  * leaves the parameterisation of far space to the works it cites, of which

@@ -7,7 +7,7 @@ Importing it does not touch the GPU; `load()` raises if the library is absent.
 from ._lib import (TXS_EHIP, TXS_EINVAL, TXS_ECAPACITY, TXS_EOVERFLOW, TXS_OK,
                    TXS_PDF_SIGMA, TXS_PDF_SIGMA_EXP, TXS_PDF_WEIGHTS, LIB_PATH, TxsError,
                    exported_symbols, load)
-from .ops import (GridSpec, MarchMasks, MlpSpec, adam_step, blob_field, compact_rows, disparity_bins,
+from .ops import (GridSpec, MlpSpec, adam_step, blob_field, compact_rows, disparity_bins,
                   edges_to_intervals,
                   exclusive_scan, exclusive_scan_noalloc, exclusive_scan_noalloc_max_rays,
                   expand_rows, gather_prefix, grid_ema, grid_points,

@@ -51,9 +51,6 @@ SIGNATURES = {
     "txs_exclusive_scan_noalloc_max_rays": (I32, []),
     "txs_exclusive_scan_noalloc": (I32, [P, I32, P, P, P]),
     "txs_march_fill": (I32, [GP, MP, P, P, I32, P, I64, P, P, P, P]),
-    "txs_march_mask_words": (I64, [I32, I32]),
-    "txs_march_count_masked": (I32, [GP, MP, P, P, I32, P, P, I32, P]),
-    "txs_march_fill_masked": (I32, [GP, MP, P, P, I32, P, I64, P, P, P, P, I32, P]),
     "txs_transmittance_prefix": (I32, [P, I32, I64, P, P, P, F32, P, P]),
     "txs_gather_prefix": (I32, [P, P, I32, I64, P, P, I64, P, P, P, P]),
     "txs_render_fwd": (I32, [P, I32, I32, I64, P, P, P, P, P, P, P, P, P, P, P]),

@@ -34,8 +34,6 @@ namespace txs {
 namespace {
 
 constexpr int kMaxLevels = 8;
-// group masks per ray at most (2^20 lattice points)
-constexpr int32_t kMaxMaskGroups = 1 << 14;
 constexpr int32_t kLatticeLimit = 1 << 24;  // k stays exact in binary32
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
@@ -66,9 +64,6 @@ struct MarchArgs {
   const uint32_t* coarse;
   int32_t cshift;       // log2(bricks per axis)
   int32_t coarse_half;  // words of one of a level's two arrays
-  // group masks: rows of mask_groups + 1 words per ray, or null
-  uint64_t* masks;
-  int32_t mask_groups;
 };
 
 // Level-l box and grid scale, evaluated exactly as the recipe defines them.
@@ -117,47 +112,7 @@ struct Emit {
   int64_t capacity;
   int32_t ray;
   float lo, hi;  // kSpan: the span so far (wave-uniform)
-  // group masks of the ray (see txs_march_count_masked): its row, the groups
-  // walked so far, the row's capacity; record (count) or replay (fill).
-  // mchunk holds row words 1 + mbase .. 1 + mbase + 63, word 1 + mbase + j in
-  // lane j: the count fills it and stores it whole, the fill reads it by
-  // readlane, so a step costs no memory access of its own.
-  uint64_t* mrow;
-  uint64_t mchunk;
-  int32_t mbase;
-  int32_t gi;
-  int32_t mask_groups;
-  bool record, replay;
 };
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// v with lane l replaced by the wave-uniform x (v_writelane_b32 per half)
-__device__ __forceinline__ uint64_t writelane64(uint64_t v, uint64_t x, int l) {
-  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  asm volatile("s_mov_b32 m0, %4\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
-               : "+v"(lo), "+v"(hi)
-               : "s"((uint32_t)x), "s"((uint32_t)(x >> 32)), "s"(l)
-               : "m0");
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Count: stores the recorded words mbase .. gi - 1 that fit the row.
-__device__ __forceinline__ void store_mask_chunk(const Emit& em) {
-  const int32_t w = em.mbase + lane();
-  if (w < em.gi && w < em.mask_groups) em.mrow[1 + w] = em.mchunk;
-}
-
-// Fill: words mbase .. mbase + 63 of the row (zero past its capacity).
-__device__ __forceinline__ uint64_t load_mask_chunk(const uint64_t* mrow, int32_t mbase,
-                                                    int32_t mask_groups) {
-  const int32_t w = mbase + lane();
-  return w < mask_groups ? mrow[1 + w] : 0ull;
-}
 
 // Lattice point k of segment [a, b) on level l: its midpoint a + (k + 1/2) dt
 // must lie before b; valid points issue the load of their cell's grid word.
@@ -283,61 +238,32 @@ __device__ __forceinline__ int32_t march_segment(const MarchArgs& g, const float
   const float lane_h = (float)ln + 0.5f;
   // kLatticeLimit is a multiple of 64 kGroups, so every k of a step is below it
   static_assert(kLatticeLimit % (kWave * kGroups) == 0, "lattice limit");
-  static_assert(kWave % kGroups == 0, "a step's group masks share a 64-word chunk");
   for (int32_t k0 = 0; k0 < kLatticeLimit; k0 += kWave * kGroups) {
     bool valid[kGroups], occ[kGroups];
-    uint64_t masks[kGroups];
-    if (kMode == kFill && em.replay) {
-      // the count pass recorded these groups' occupancy: only the segment's
-      // end is evaluated again (the same midpoint, so the same decision).
-      // gi is even and chunks hold 64 words, so a step's groups share a chunk.
-      if (em.gi - em.mbase >= kWave) {
-        em.mbase += kWave;
-        em.mchunk = load_mask_chunk(em.mrow, em.mbase, em.mask_groups);
-      }
+    uint32_t word[kGroups];
+    int32_t sh[kGroups];
 #pragma unroll
-      for (int q = 0; q < kGroups; ++q) {
-        const float m = p.a + ((float)(k0 + kWave * q) + lane_h) * p.dt;
+    for (int q = 0; q < kGroups; ++q) {
+      if (kContract) {
+        valid[q] = probe<kContract>(p, o, d, k0 + kWave * q + ln, word[q], sh[q]);
+      } else {
+        // (float)k + 1/2 as a scalar plus a lane constant: exact below 2^24
+        const float kh = (float)(k0 + kWave * q) + lane_h;
+        uint32_t bt;
+        float m;
+        word[q] = cell_word(p, o, d, kh, bt, m);
+        sh[q] = (int32_t)bt;
         valid[q] = m < p.b;
-        masks[q] = readlane64(em.mchunk, em.gi + q - em.mbase);
-        occ[q] = (masks[q] >> ln) & 1u;
-      }
-    } else {
-      uint32_t word[kGroups];
-      int32_t sh[kGroups];
-#pragma unroll
-      for (int q = 0; q < kGroups; ++q) {
-        if (kContract) {
-          valid[q] = probe<kContract>(p, o, d, k0 + kWave * q + ln, word[q], sh[q]);
-        } else {
-          // (float)k + 1/2 as a scalar plus a lane constant: exact below 2^24
-          const float kh = (float)(k0 + kWave * q) + lane_h;
-          uint32_t bt;
-          float m;
-          word[q] = cell_word(p, o, d, kh, bt, m);
-          sh[q] = (int32_t)bt;
-          valid[q] = m < p.b;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kGroups; ++q) occ[q] = valid[q] && ((word[q] >> sh[q]) & 1u);
-      // every group's ballot before any early exit: the loads of all groups
-      // then stay in flight together (a convergent ballot is not sunk into a
-      // branch)
-#pragma unroll
-      for (int q = 0; q < kGroups; ++q) masks[q] = __ballot(occ[q]);
-      if (kMode == kCount && em.record) {
-        // the (wave-uniform) ballot goes into lane gi + q - mbase
-#pragma unroll
-        for (int q = 0; q < kGroups; ++q)
-          em.mchunk = writelane64(em.mchunk, masks[q], em.gi + q - em.mbase);
       }
     }
-    if (kMode != kSpan) em.gi += kGroups;
-    if (kMode == kCount && em.record && em.gi - em.mbase == kWave) {
-      store_mask_chunk(em);
-      em.mbase += kWave;
-    }
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) occ[q] = valid[q] && ((word[q] >> sh[q]) & 1u);
+    // every group's ballot before any early exit: the loads of all groups
+    // then stay in flight together (a convergent ballot is not sunk into a
+    // branch)
+    uint64_t masks[kGroups];
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) masks[q] = __ballot(occ[q]);
 #pragma unroll
     for (int q = 0; q < kGroups; ++q) {
       const int32_t k = k0 + kWave * q + ln;
@@ -696,26 +622,14 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float*
   const int64_t base = (int64_t)blockIdx.x * kRaysPerBlock;
   const int64_t end = min(base + kRaysPerBlock, (int64_t)n_rays);
   int64_t r64 = base + w;
-  // the fill's packed row and, when replaying, the mask row's word 0 and
-  // first 64 group words are fetched one ray ahead as well
-  const bool replaying = kMode == kFill && !kSkip && g.masks != nullptr;
   float on[3] = {0.0f, 0.0f, 0.0f}, dn[3] = {0.0f, 0.0f, 0.0f};
-  int2 row_n = make_int2(0, 0);
-  uint64_t walked_n = 0ull, chunk_n = 0ull;
-  auto fetch = [&](int64_t rr) {
+  if (r64 < end) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      on[c] = ro[3 * rr + c];
-      dn[c] = rd[3 * rr + c];
+      on[c] = ro[3 * r64 + c];
+      dn[c] = rd[3 * r64 + c];
     }
-    if (kMode == kFill) row_n = reinterpret_cast<const int2*>(info)[rr];
-    if (replaying) {
-      const uint64_t* mrow = g.masks + rr * (g.mask_groups + 1);
-      walked_n = mrow[0];
-      chunk_n = load_mask_chunk(mrow, 0, g.mask_groups);
-    }
-  };
-  if (r64 < end) fetch(r64);
+  }
   for (; r64 < end; r64 += kWavesPerBlock) {
     const int32_t r = __builtin_amdgcn_readfirstlane((int32_t)r64);
     float o[3], d[3];
@@ -724,34 +638,22 @@ __global__ __launch_bounds__(kBlock) void march_kernel(MarchArgs g, const float*
       o[c] = on[c];
       d[c] = dn[c];
     }
-    const int2 row = row_n;
-    const uint64_t walked = walked_n, chunk = chunk_n;
     const int64_t rn = r64 + kWavesPerBlock;
-    if (rn < end) fetch(rn);
+    if (rn < end) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        on[c] = ro[3 * rn + c];
+        dn[c] = rd[3 * rn + c];
+      }
+    }
     Emit em{t0, t1, ray_id, 0, 0, capacity, r, 0.0f, 0.0f};
     if (kMode == kFill) {
+      const int2 row = reinterpret_cast<const int2*>(info)[r];
       em.base = row.x;
       em.count = (row.x < 0 || row.y < 0) ? 0 : row.y;  // malformed row: nothing written
     }
-    em.mask_groups = g.mask_groups;
-    if (kMode != kSpan && g.masks) {
-      em.mrow = g.masks + (int64_t)r * (g.mask_groups + 1);
-      if (kSkip) {
-        // skipped runs record nothing: the row is marked as not replayable
-        if (kMode == kCount && lane() == 0) em.mrow[0] = (uint64_t)g.mask_groups + 1;
-      } else if (kMode == kCount) {
-        em.record = true;
-      } else {
-        em.replay = walked <= (uint64_t)g.mask_groups;  // every group recorded
-        em.mchunk = chunk;
-      }
-    }
     const int32_t n = march_ray<kMode, kContract, kSkip>(g, coarse_lds, staged, list, o, d, em);
     if (kMode == kCount && lane() == 0) counts[r] = n;
-    if (kMode == kCount && em.record) {
-      store_mask_chunk(em);
-      if (lane() == 0) em.mrow[0] = (uint64_t)em.gi;
-    }
     if (kMode == kSpan && lane() == 0) {
       span[2 * (int64_t)r] = em.lo;
       span[2 * (int64_t)r + 1] = em.hi;
@@ -794,8 +696,6 @@ txs_status make_args(const txs_grid* grid, const txs_march_params* p, MarchArgs&
   g.coarse = nullptr;
   g.cshift = 0;
   g.coarse_half = 0;
-  g.masks = nullptr;
-  g.mask_groups = 0;
   const int64_t cw = txs_grid_coarse_words(res);
   if (grid->coarse && cw > 0 && cw * grid->n_levels <= kCoarseLdsWords) {
     g.coarse = grid->coarse;
@@ -859,57 +759,6 @@ extern "C" txs_status txs_march_fill(const txs_grid* grid, const txs_march_param
   TXS_REQUIRE(capacity == 0 || (t0 && t1), "txs_march_fill: null output");
   return launch_march<kFill, false>(g, stream, rays_o, rays_d, n_rays, nullptr, packed_info,
                                     capacity, t0, t1, ray_id, nullptr, "txs_march_fill");
-}
-
-extern "C" int64_t txs_march_mask_words(int32_t n_rays, int32_t groups_per_ray) {
-  if (n_rays < 0 || groups_per_ray < 0) return 0;
-  return (int64_t)n_rays * ((int64_t)groups_per_ray + 1);
-}
-
-extern "C" txs_status txs_march_count_masked(const txs_grid* grid,
-                                             const txs_march_params* params,
-                                             const float* rays_o, const float* rays_d,
-                                             int32_t n_rays, int32_t* counts, uint64_t* masks,
-                                             int32_t groups_per_ray, void* stream) {
-  using namespace txs;
-  clear_error();
-  MarchArgs g;
-  if (txs_status s = make_args(grid, params, g)) return s;
-  TXS_REQUIRE(n_rays >= 0, "txs_march_count_masked: n_rays < 0");
-  TXS_REQUIRE(groups_per_ray >= 0 && groups_per_ray <= kMaxMaskGroups,
-              "txs_march_count_masked: groups_per_ray must be in [0,%d], got %d",
-              kMaxMaskGroups, groups_per_ray);
-  if (n_rays == 0) return TXS_OK;
-  TXS_REQUIRE(rays_o && rays_d && counts && masks, "txs_march_count_masked: null array");
-  g.masks = masks;
-  g.mask_groups = groups_per_ray;
-  return launch_march<kCount, false>(g, stream, rays_o, rays_d, n_rays, counts, nullptr, 0,
-                                     nullptr, nullptr, nullptr, nullptr,
-                                     "txs_march_count_masked");
-}
-
-extern "C" txs_status txs_march_fill_masked(const txs_grid* grid,
-                                            const txs_march_params* params,
-                                            const float* rays_o, const float* rays_d,
-                                            int32_t n_rays, const int32_t* packed_info,
-                                            int64_t capacity, float* t0, float* t1,
-                                            int32_t* ray_id, const uint64_t* masks,
-                                            int32_t groups_per_ray, void* stream) {
-  using namespace txs;
-  clear_error();
-  MarchArgs g;
-  if (txs_status s = make_args(grid, params, g)) return s;
-  TXS_REQUIRE(n_rays >= 0 && capacity >= 0, "txs_march_fill_masked: negative size");
-  TXS_REQUIRE(groups_per_ray >= 0 && groups_per_ray <= kMaxMaskGroups,
-              "txs_march_fill_masked: groups_per_ray must be in [0,%d], got %d", kMaxMaskGroups,
-              groups_per_ray);
-  if (n_rays == 0) return TXS_OK;
-  TXS_REQUIRE(rays_o && rays_d && packed_info && masks, "txs_march_fill_masked: null array");
-  TXS_REQUIRE(capacity == 0 || (t0 && t1), "txs_march_fill_masked: null output");
-  g.masks = const_cast<uint64_t*>(masks);  // read only in the fill
-  g.mask_groups = groups_per_ray;
-  return launch_march<kFill, false>(g, stream, rays_o, rays_d, n_rays, nullptr, packed_info,
-                                    capacity, t0, t1, ray_id, nullptr, "txs_march_fill_masked");
 }
 
 extern "C" txs_status txs_march_span(const txs_grid* grid, const txs_march_params* params,

@@ -7,7 +7,6 @@ torch's current stream.  No computation of the method happens here.
 from __future__ import annotations
 
 import ctypes as C
-import math
 from dataclasses import dataclass
 
 import torch
@@ -140,54 +139,15 @@ def _rays(rays_o, rays_d):
     return n
 
 
-class MarchMasks:
-    """Per-ray group masks that txs_march_count_masked records for the fill.
-
-    words: int64 device tensor (the uint64 words), groups: masks per ray.
-    """
-
-    def __init__(self, n_rays, groups, device):
-        self.groups = int(groups)
-        self.words = torch.empty(int(load().txs_march_mask_words(n_rays, self.groups)),
-                                 dtype=torch.int64, device=device)
-
-    @staticmethod
-    def pays(grid: GridSpec):
-        """Whether recording pays: the replay saves the fill its cell tests,
-        and the count pays for writing the masks.  Measured on MI355X, 2^20
-        camera rays: on a 4-level cascade of 128^3 grids count + fill
-        5.40 -> 5.18 ms; on one 128^3 level 2.33 -> 2.38 ms (the fill there is
-        bound by its sample writes, not its tests)."""
-        return grid.n_levels > 1
-
-    @staticmethod
-    def groups_for(grid: GridSpec, dt0):
-        """Groups a ray of `grid` can walk: 2 (ceil(chord / (128 dt)) + 1) per
-        segment, the cube's longest chord over its step, 2 n_levels - 1
-        segments (each level's chord over its step is the innermost one's)."""
-        chord = 2.0 * math.sqrt(3.0) * grid.half_extent0
-        per_segment = 2 * (math.ceil(chord / (128.0 * dt0)) + 1)
-        return (2 * grid.n_levels - 1) * per_segment
-
-
 def march_count(grid: GridSpec, rays_o, rays_d, *, near=0.0, far=float("inf"), dt0,
-                max_per_ray=0, counts=None, masks: "MarchMasks" = None):
-    """Per-ray sample counts; with `masks`, the groups' occupancy is recorded
-    for march_fill."""
+                max_per_ray=0, counts=None):
     n = _rays(rays_o, rays_d)
     counts = counts if counts is not None else torch.empty(n, dtype=torch.int32,
                                                            device=rays_o.device)
     _need(counts, "counts", torch.int32, (n,))
     g, p = grid.struct(), _params(near, far, dt0, max_per_ray)
-    if masks is None:
-        check(load().txs_march_count(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d), n,
-                                     _ptr(counts), _stream()), "txs_march_count")
-    else:
-        _need(masks.words, "masks", torch.int64,
-              (int(load().txs_march_mask_words(n, masks.groups)),))
-        check(load().txs_march_count_masked(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d),
-                                            n, _ptr(counts), _ptr(masks.words), masks.groups,
-                                            _stream()), "txs_march_count_masked")
+    check(load().txs_march_count(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d), n,
+                                 _ptr(counts), _stream()), "txs_march_count")
     return counts
 
 
@@ -226,10 +186,7 @@ def exclusive_scan_noalloc_max_rays():
 
 
 def march_fill(grid: GridSpec, rays_o, rays_d, packed_info, n_samples, *, near=0.0,
-               far=float("inf"), dt0, max_per_ray=0, want_ray_id=True,
-               masks: "MarchMasks" = None):
-    """Packed samples; with `masks` (recorded by march_count), the recorded
-    groups are replayed instead of tested."""
+               far=float("inf"), dt0, max_per_ray=0, want_ray_id=True):
     n = _rays(rays_o, rays_d)
     _need(packed_info, "packed_info", torch.int32, (n, 2))
     dev = rays_o.device
@@ -237,17 +194,9 @@ def march_fill(grid: GridSpec, rays_o, rays_d, packed_info, n_samples, *, near=0
     t1 = torch.empty(n_samples, dtype=torch.float32, device=dev)
     rid = torch.empty(n_samples, dtype=torch.int32, device=dev) if want_ray_id else None
     g, p = grid.struct(), _params(near, far, dt0, max_per_ray)
-    if masks is None:
-        check(load().txs_march_fill(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d), n,
-                                    _ptr(packed_info), n_samples, _ptr(t0), _ptr(t1), _ptr(rid),
-                                    _stream()), "txs_march_fill")
-    else:
-        _need(masks.words, "masks", torch.int64,
-              (int(load().txs_march_mask_words(n, masks.groups)),))
-        check(load().txs_march_fill_masked(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d),
-                                           n, _ptr(packed_info), n_samples, _ptr(t0), _ptr(t1),
-                                           _ptr(rid), _ptr(masks.words), masks.groups,
-                                           _stream()), "txs_march_fill_masked")
+    check(load().txs_march_fill(C.byref(g), C.byref(p), _ptr(rays_o), _ptr(rays_d), n,
+                                _ptr(packed_info), n_samples, _ptr(t0), _ptr(t1), _ptr(rid),
+                                _stream()), "txs_march_fill")
     return t0, t1, rid
 
 

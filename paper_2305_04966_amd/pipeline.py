@@ -43,15 +43,13 @@ def _host_total(total: torch.Tensor) -> int:
 
 
 def march(grid: ops.GridSpec, rays_o, rays_d, *, dt0, near=0.0, far=float("inf"),
-          max_per_ray=0, masks: ops.MarchMasks = None) -> Packed:
-    """Lattice march -> packed samples; `masks` (optional, sized for these
-    rays) lets the fill replay the count pass's tests."""
+          max_per_ray=0) -> Packed:
     counts = ops.march_count(grid, rays_o, rays_d, near=near, far=far, dt0=dt0,
-                             max_per_ray=max_per_ray, masks=masks)
+                             max_per_ray=max_per_ray)
     info, total = ops.exclusive_scan(counts)
     s = _host_total(total)
     t0, t1, rid = ops.march_fill(grid, rays_o, rays_d, info, s, near=near, far=far, dt0=dt0,
-                                 max_per_ray=max_per_ray, masks=masks)
+                                 max_per_ray=max_per_ray)
     return Packed(info, t0, t1, rid, tight=True)
 
 

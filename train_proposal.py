@@ -253,12 +253,8 @@ def run(*, steps=1000, hidden=128, bins=128, ray_stride=1, train_stride=1,
     # 4. timing, fwd + bwd, field included on both sides
     g_rgb = dev(w.grads[ev])
 
-    # the count pass's group masks for the fill (sized for these rays)
-    masks = (txs.MarchMasks(N, txs.MarchMasks.groups_for(grid, w.dt0), o.device)
-             if txs.MarchMasks.pays(grid) else None)
-
     def grid_step():
-        p = txs.march(grid, o, d, dt0=w.dt0, masks=masks)
+        p = txs.march(grid, o, d, dt0=w.dt0)
         sg, _ = txs.blob_field(fp, nb, o, d, p.t0, p.t1, p.ray_id, want_rgb=False)
         q = txs.filter_transmittance(p, sg, w.t_min)
         sg, rgb = txs.blob_field(fp, nb, o, d, q.t0, q.t1, q.ray_id)
@@ -431,12 +427,8 @@ def run_combined(*, steps=300, hidden=128, bins=128, eval_bins=(16, 32, 64, 128)
                      "final_loss": losses[-1][1] if losses else None,
                      "ms_per_train_step": 1000.0 * secs / max(steps, 1)}
 
-    # the count pass's group masks for the fill (sized for these rays)
-    masks = (txs.MarchMasks(N, txs.MarchMasks.groups_for(grid, w.dt0), o.device)
-             if txs.MarchMasks.pays(grid) else None)
-
     def grid_step():
-        p = txs.march(grid, o, d, dt0=w.dt0, masks=masks)
+        p = txs.march(grid, o, d, dt0=w.dt0)
         sg, _ = txs.blob_field(sc.fp, w.fld.n_blobs, o, d, p.t0, p.t1, p.ray_id, want_rgb=False)
         q = txs.filter_transmittance(p, sg, w.t_min)
         sg, rgb = txs.blob_field(sc.fp, w.fld.n_blobs, o, d, q.t0, q.t1, q.ray_id)
