@@ -242,6 +242,20 @@ __device__ __forceinline__ void load_k(const float* __restrict__ src, int64_t po
   }
 }
 
+// load_k for a lane whose K samples all lie below the window's limit.
+__device__ __forceinline__ void load_k_whole(const float* __restrict__ src, int64_t pos0,
+                                             float (&v)[K]) {
+  const float4* p = reinterpret_cast<const float4*>(src + pos0);
+#pragma unroll
+  for (int q = 0; q < K / 4; ++q) {
+    const float4 x = p[q];
+    v[4 * q] = x.x;
+    v[4 * q + 1] = x.y;
+    v[4 * q + 2] = x.z;
+    v[4 * q + 3] = x.w;
+  }
+}
+
 __device__ __forceinline__ void load_rgb(const float* __restrict__ src, int64_t pos0, int64_t lim,
                                          float (&c)[K][3]) {
   if (pos0 + K <= lim) {

@@ -5,7 +5,7 @@
 namespace txs {
 namespace {
 
-template <int kMode>
+template <int kMode, bool kColour>
 __global__ __launch_bounds__(kBlock) void fwd_kernel(Args a) {
   __shared__ MarkLds lds[kWaves];
   __shared__ float4 stage_mem[kWaves][StageSize<kMode>::value];
@@ -23,7 +23,10 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(Args a) {
   FwdCarry carry{-1, 0.0, Acc5{0.f, 0.f, 0.f, 0.f, 0.f}, 0};
   for (int64_t p = R.lo & ~int64_t(3); p < R.hi; p += W) {
     write_marks(L, p, R.st, R.en, R.active);
-    carry = fwd_window<kMode>(a, L, stage, r0, p, min(p + W, R.hi), carry);
+    if (R.hi - p >= W)  // a whole window (no overflow: p < R.hi)
+      carry = fwd_window<kMode, kColour, true>(a, L, stage, r0, p, p + W, carry);
+    else
+      carry = fwd_window<kMode, kColour, false>(a, L, stage, r0, p, R.hi, carry);
   }
 }
 
@@ -58,7 +61,8 @@ extern "C" txs_status txs_render_fwd(const int32_t* packed_info, int32_t fixed_c
   a.out_depth = out_depth;
   a.out_w = out_weights;
   a.out_optical = out_optical_depth;
-  return launch(fwd_kernel<kFwd>, a, stream, "txs_render_fwd");
+  return rgb ? launch(fwd_kernel<kFwd, true>, a, stream, "txs_render_fwd")
+             : launch(fwd_kernel<kFwd, false>, a, stream, "txs_render_fwd");
 }
 
 extern "C" txs_status txs_transmittance_prefix(const int32_t* packed_info, int32_t n_rays,
@@ -83,5 +87,5 @@ extern "C" txs_status txs_transmittance_prefix(const int32_t* packed_info, int32
   a.sigma = sigma;
   a.p_max = -std::log((double)t_min);
   a.kept = kept_counts;
-  return launch(fwd_kernel<kPrefix>, a, stream, "txs_transmittance_prefix");
+  return launch(fwd_kernel<kPrefix, false>, a, stream, "txs_transmittance_prefix");
 }

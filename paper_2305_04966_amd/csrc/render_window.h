@@ -36,15 +36,36 @@ __device__ __forceinline__ void emit_ray(const Args& a, int32_t r, const Acc5& s
 
 // One window of the forward direction: samples [p, p+W) clipped to lim, the
 // window's marks already in LDS, cin the state entering the window.
-template <int kMode, class Lds>
+// kColour: the render reads colours (a.rgb non-null); kFull: the window is
+// whole (lim = p + W).  A whole window issues all of its loads (t0, t1, sigma
+// and the colour rows) in one branch-free run, so the first wait covers them
+// together instead of the colours' latency following pass 1.
+template <int kMode, bool kColour, bool kFull, class Lds>
 __device__ FwdCarry fwd_window(const Args& a, Lds& L, float4* stage, int32_t r0, int64_t p,
                                int64_t lim, const FwdCarry& cin) {
   const int ln = lane();
   const int64_t pos0 = p + (int64_t)K * ln;
   float t0v[K], t1v[K], sg[K];
-  load_k(a.t0, pos0, lim, t0v);
-  load_k(a.t1, pos0, lim, t1v);
-  load_k(a.sigma, pos0, lim, sg);
+  float4 rg[3 * K / 4];
+#pragma unroll
+  for (int q = 0; q < 3 * K / 4; ++q) rg[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (kFull) {
+    load_k_whole(a.t0, pos0, t0v);
+    load_k_whole(a.t1, pos0, t1v);
+    load_k_whole(a.sigma, pos0, sg);
+    if (kMode == kFwd && kColour) {
+      // consecutive-lane float4s of the window's rows, unstaged after pass 1
+      const float4* s4 = reinterpret_cast<const float4*>(a.rgb + 3 * p);
+#pragma unroll
+      for (int q = 0; q < 3 * K / 4; ++q) rg[q] = s4[q * kWave + ln];
+    }
+    // keep the scheduler from sinking the colour loads to their use
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+    load_k(a.t0, pos0, lim, t0v);
+    load_k(a.t1, pos0, lim, t1v);
+    load_k(a.sigma, pos0, lim, sg);
+  }
   int mk[K + 1];
   read_marks(L, mk);
 
@@ -89,8 +110,8 @@ __device__ FwdCarry fwd_window(const Args& a, Lds& L, float4* stage, int32_t r0,
   bool own[K];
   float c[K][3];
   if (kMode == kFwd) {
-    if (a.rgb) {
-      if (p + W <= lim) load_rgb_staged(a.rgb, p, stage, c);  // wave-uniform
+    if (kColour) {
+      if (kFull) unstage_rgb(rg, stage, c);
       else load_rgb(a.rgb, pos0, lim, c);
     } else {  // colourless: weights, opacity and depth only
 #pragma unroll
@@ -108,7 +129,7 @@ __device__ FwdCarry fwd_window(const Args& a, Lds& L, float4* stage, int32_t r0,
       cnt = 0;
       first = false;
     }
-    const bool live = cur >= 0 && (pos0 + j) < lim;
+    const bool live = cur >= 0 && (kFull || (pos0 + j) < lim);
     own[j] = live;
     if (kMode == kFwd) {
       const float T = __builtin_amdgcn_exp2f((Psf + loc) * -1.44269504f);
@@ -179,7 +200,10 @@ __device__ __forceinline__ void wave_optical_depth(const Args& a, WaveLds& L, in
   FwdCarry carry{-1, 0.0, Acc5{0.f, 0.f, 0.f, 0.f, 0.f}, 0};
   for (int64_t p = R.lo & ~int64_t(3); p < R.hi; p += W) {
     write_marks(L, p, R.st, R.en, R.active);
-    carry = fwd_window<kTotal>(a, L, nullptr, r0, p, min(p + W, R.hi), carry);
+    if (R.hi - p >= W)  // (R.hi - p: p + W could pass INT64_MAX only if R.hi did)
+      carry = fwd_window<kTotal, false, true>(a, L, nullptr, r0, p, p + W, carry);
+    else
+      carry = fwd_window<kTotal, false, false>(a, L, nullptr, r0, p, R.hi, carry);
   }
   wave_sync();
 }
