@@ -67,25 +67,43 @@ __global__ __launch_bounds__(kWave* kLossWaves) void hist_loss_kernel(
   float* cc = reinterpret_cast<float*>(base + ((size_t)(2 * nb + 1) * 4 + 15) / 16 * 16);
   int16_t* jl = reinterpret_cast<int16_t*>(cc + kChunk);
   int16_t* jh = jl + kChunk;
-  for (int j = ln; j <= nb; j += kWave) e[j] = edges[r * (nb + 1) + j];
-  for (int j = ln; j < nb; j += kWave) pw[j] = prop[r * nb + j];
-  wave_sync();
+  // The ray's packed row, its edges and proposal weights load together, and
+  // the first targets as soon as the row is in: two memory latencies before
+  // the first target is processed instead of three in a row.
   int64_t st = info[2 * r], ct = info[2 * r + 1];
+  float ev[kBinsPerLane + 1], pv[kBinsPerLane];
+#pragma unroll
+  for (int q = 0; q <= kBinsPerLane; ++q) {
+    const int j = ln + q * kWave;
+    ev[q] = j <= nb ? edges[r * (nb + 1) + j] : 0.0f;
+    if (q < kBinsPerLane) pv[q] = j < nb ? prop[r * nb + j] : 0.0f;
+  }
   if (st < 0 || ct < 0 || st + ct > n_targets) ct = 0;  // malformed row: no targets
+  // each lane's next target loads while its current one is processed; the
+  // first targets of a chunk load before the previous chunk's bin sums
+  float na = 0.0f, nb_ = 0.0f, nw = 0.0f;
+  auto first_targets = [&](int64_t c0) {
+    if (ln < min<int64_t>(kChunk, ct - c0)) {
+      const int64_t i = st + c0 + ln;
+      na = t0[i];
+      nb_ = t1[i];
+      nw = w[i];
+    }
+  };
+  first_targets(0);
+#pragma unroll
+  for (int q = 0; q <= kBinsPerLane; ++q) {
+    const int j = ln + q * kWave;
+    if (j <= nb) e[j] = ev[q];
+    if (q < kBinsPerLane && j < nb) pw[j] = pv[q];
+  }
+  wave_sync();
   float gacc[kBinsPerLane];
 #pragma unroll
   for (int q = 0; q < kBinsPerLane; ++q) gacc[q] = 0.0f;
   float acc = 0.0f;
   for (int64_t c0 = 0; c0 < ct || c0 == 0; c0 += kChunk) {
     const int n = (int)min<int64_t>(kChunk, ct - c0);
-    // each lane's next target loads while its current one is processed
-    float na = 0.0f, nb_ = 0.0f, nw = 0.0f;
-    if (ln < n) {
-      const int64_t i = st + c0 + ln;
-      na = t0[i];
-      nb_ = t1[i];
-      nw = w[i];
-    }
     for (int k = ln; k < n; k += kWave) {
       const float a = na, b = nb_, wi = nw;
       if (k + kWave < n) {
@@ -109,6 +127,7 @@ __global__ __launch_bounds__(kWave* kLossWaves) void hist_loss_kernel(
       jh[k] = (int16_t)jhi;
     }
     wave_sync();
+    if (c0 + kChunk < ct) first_targets(c0 + kChunk);
     if (d_prop) {
 #pragma unroll
       for (int q = 0; q < kBinsPerLane; ++q) {
