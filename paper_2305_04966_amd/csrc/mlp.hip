@@ -246,6 +246,8 @@ __attribute__((amdgpu_waves_per_eu(kThreads == 512 ? 4 : 1))) void mlp_fwd_kerne
   __shared__ bf16x8 sA2[MT * KS * 64];
   __shared__ bf16x8 sA3[KS * 64];
   __shared__ float sb1[H], sb2[H];
+  // per wave: the encoded coordinates of its NT * 16 points, axis-major
+  __shared__ float sY[kThreads / kWave][3][kWave];
   // weights to LDS once per block
   {
     const bf16x8* src = reinterpret_cast<const bf16x8*>(a.packed);
@@ -270,32 +272,40 @@ __attribute__((amdgpu_waves_per_eu(kThreads == 512 ? 4 : 1))) void mlp_fwd_kerne
   const int ln = lane(), g = ln >> 4, col = ln & 15;
   const int64_t n_points = (int64_t)a.n_rays * a.n_bins;
   const int64_t n_tiles = (n_points + 15) / 16;
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int wv = threadIdx.x / kWave;
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
   const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  // inputs of the current tile group, fetched one group ahead
-  PointIn in[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int64_t p = (wave * NT + t) * 16 + col;
-    if (p < n_points) in[t] = load_point(a, p);
+  // A group of NT tiles holds NT * 16 <= 64 points: lane l loads and encodes
+  // point l of the group (once, where the lanes of a tile column would each
+  // repeat it), fetched one group ahead; the coordinates reach the lanes
+  // that form the features through LDS.
+  static_assert(NT * 16 <= kWave, "one point per lane");
+  const bool loads = ln < NT * 16;
+  PointIn in{};
+  {
+    const int64_t p = wave * NT * 16 + ln;
+    if (loads && p < n_points) in = load_point(a, p);
   }
   for (int64_t t0 = wave * NT; t0 < n_tiles; t0 += n_waves * NT) {
+    if (loads) {
+      float y[3] = {0.0f, 0.0f, 0.0f};
+      if (t0 * 16 + ln < n_points) encode_loaded(a, in, y);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sY[wv][c][ln] = y[c];
+      const int64_t pn = (t0 + n_waves * NT) * 16 + ln;
+      if (pn < n_points) in = load_point(a, pn);
+    }
+    wave_sync();
     bf16x8 B1[NT][2];
     bool valid[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int64_t p = (t0 + t) * 16 + col;
       valid[t] = p < n_points;
-      float y[3] = {0.0f, 0.0f, 0.0f};
-      if (valid[t]) encode_loaded(a, in[t], y);
-      const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
+      const float xa = sY[wv][g < 2 ? g : 2][16 * t + col];
       features(xa, g, B1[t][0], B1[t][1]);
     }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int64_t pn = (t0 + n_waves * NT + t) * 16 + col;
-      if (pn < n_points) in[t] = load_point(a, pn);
-    }
+    wave_sync();  // the slots are rewritten by the next group
     // layer 1; B operand of layer 2's K-step s = fragments 2s and 2s+1
     bf16x8 B2[NT][KS];
 #pragma unroll
@@ -571,34 +581,40 @@ void mlp_bwd_kernel(BwdArgs a) {
   for (int m = 0; m < MT; ++m) acc3[m] = db2p[m] = 0.0f;
 
   // Per chunk: the raw inputs and features, then the phases below.  The
-  // previous group's dW1 products run beside the d2 arithmetic.  Out-of-range
-  // points load the last point (clamped, so no branch splits the scheduling
-  // regions) and are zeroed through ds.  Weight tiles are read two steps ahead
-  // of their products (the wq, w1q, wtq rings): LDS latency is then covered by
-  // the products in between, which with one wave per SIMD nothing else covers.
+  // previous group's dW1 products run beside the d2 arithmetic.  Lane l < 32
+  // loads point l of a chunk (clamped to the last point, so no branch splits
+  // the scheduling regions) one chunk ahead and encodes it once; the
+  // coordinates and d_sigma reach the feature lanes through LDS, out-of-range
+  // points as zeros.  Weight tiles are read two steps ahead of their products
+  // (the wq, w1q, wtq rings): LDS latency is then covered by the products in
+  // between, which with one wave per SIMD nothing else covers.
   const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
   bf16x8* slot_w = sX + w * kSlot * 64;
-  PointIn in[2];
-  float dsig[2];
+  __shared__ float sPt[kBwdWaves][4][32];  // x, y, z, d_sigma of the chunk's points
+  PointIn in;
+  float dsig;
   const auto fetch = [&](int64_t chunk) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int64_t p = min(chunk * 32 + 16 * t + col, n_points - 1);
-      in[t] = load_point(a, p);
-      dsig[t] = a.d_sigma[p];
-    }
+    const int64_t p = min(chunk * 32 + (ln & 31), n_points - 1);
+    in = load_point(a, p);
+    dsig = a.d_sigma[p];
   };
   bf16x8 B1[2][2];
   float ds[2];
   const auto encode_chunk = [&](int64_t chunk) {
+    wave_sync();  // the previous chunk's reads of the slots are done
+    if (ln < 32) {
+      const bool valid = chunk * 32 + ln < n_points;
+      float y[3];
+      encode_loaded(a, in, y);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sPt[w][k][ln] = valid ? y[k] : 0.0f;
+      sPt[w][3][ln] = valid ? dsig : 0.0f;
+    }
+    wave_sync();
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      const bool valid = chunk * 32 + 16 * t + col < n_points;
-      float y[3];
-      encode_loaded(a, in[t], y);
-      const float xa = g == 0 ? y[0] : g == 1 ? y[1] : y[2];
-      features(valid ? xa : 0.0f, g, B1[t][0], B1[t][1]);
-      ds[t] = valid ? dsig[t] : 0.0f;
+      features(sPt[w][g < 2 ? g : 2][16 * t + col], g, B1[t][0], B1[t][1]);
+      ds[t] = sPt[w][3][16 * t + col];
     }
   };
 
@@ -612,8 +628,9 @@ void mlp_bwd_kernel(BwdArgs a) {
     int opaque;
     asm volatile("v_mov_b32 %0, 0" : "=v"(opaque));
     const int li = ln + opaque;
-    fetch(c);
+    if (grp == blockIdx.x) fetch(c);
     encode_chunk(c);
+    fetch(c + (int64_t)gridDim.x * kBwdWaves);  // the next group's chunk, while this one computes
     // gamma point-major, and layer 1 unit-major (K-step s of layer 2 = row
     // tiles 2s and 2s+1)
     bf16x8 G[3];
