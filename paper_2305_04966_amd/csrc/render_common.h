@@ -282,35 +282,9 @@ __device__ __forceinline__ void load_rgb(const float* __restrict__ src, int64_t 
   }
 }
 
-// Stores v[j] where own[j]; a full vector store when every element is owned.
-// The window's rgb rows [p, p+W) through LDS: lane l loads float4s l, l+64,
-// ... (consecutive lanes, consecutive 16 bytes), then reads back its own K
-// rows.  Caller guarantees p + W <= the array's row count.
-__device__ __forceinline__ void load_rgb_staged(const float* __restrict__ src, int64_t p,
-                                                float4* stage, float (&c)[K][3]) {
-  const int ln = lane();
-  const float4* s4 = reinterpret_cast<const float4*>(src + 3 * p);
-#pragma unroll
-  for (int q = 0; q < 3 * K / 4; ++q) stage[q * kWave + ln] = s4[q * kWave + ln];
-  wave_sync();
-  float f[3 * K];
-#pragma unroll
-  for (int q = 0; q < 3 * K / 4; ++q) {
-    const float4 x = stage[(3 * K / 4) * ln + q];
-    f[4 * q] = x.x;
-    f[4 * q + 1] = x.y;
-    f[4 * q + 2] = x.z;
-    f[4 * q + 3] = x.w;
-  }
-#pragma unroll
-  for (int j = 0; j < K; ++j)
-#pragma unroll
-    for (int c3 = 0; c3 < 3; ++c3) c[j][c3] = f[3 * j + c3];
-  wave_sync();
-}
-
-// The second half of load_rgb_staged, for rows already loaded as
-// consecutive-lane float4s (rg[q] = float4 q*64 + lane of the window).
+// A window's rgb rows [p, p+W) loaded as consecutive-lane float4s (rg[q] =
+// float4 q*64 + lane of the window: consecutive lanes, consecutive 16 bytes)
+// to each lane's own K rows, through LDS.
 __device__ __forceinline__ void unstage_rgb(const float4 (&rg)[3 * K / 4], float4* stage,
                                             float (&c)[K][3]) {
   const int ln = lane();
@@ -344,6 +318,7 @@ __device__ __forceinline__ void store_rgb_staged(float* __restrict__ dst, int64_
   wave_sync();
 }
 
+// Stores v[j] where own[j]; a full vector store when every element is owned.
 __device__ __forceinline__ void store_k(float* __restrict__ dst, int64_t pos0, const float (&v)[K],
                                         const bool (&own)[K]) {
   bool all = true;

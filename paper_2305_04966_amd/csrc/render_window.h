@@ -46,6 +46,8 @@ __device__ FwdCarry fwd_window(const Args& a, Lds& L, float4* stage, int32_t r0,
   const int ln = lane();
   const int64_t pos0 = p + (int64_t)K * ln;
   float t0v[K], t1v[K], sg[K];
+  // (zeroed: left undefined on the paths that do not load it, the compiler
+  // kept the array in scratch memory)
   float4 rg[3 * K / 4];
 #pragma unroll
   for (int q = 0; q < 3 * K / 4; ++q) rg[q] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -200,7 +202,7 @@ __device__ __forceinline__ void wave_optical_depth(const Args& a, WaveLds& L, in
   FwdCarry carry{-1, 0.0, Acc5{0.f, 0.f, 0.f, 0.f, 0.f}, 0};
   for (int64_t p = R.lo & ~int64_t(3); p < R.hi; p += W) {
     write_marks(L, p, R.st, R.en, R.active);
-    if (R.hi - p >= W)  // (R.hi - p: p + W could pass INT64_MAX only if R.hi did)
+    if (R.hi - p >= W)  // a whole window (no overflow: p < R.hi)
       carry = fwd_window<kTotal, false, true>(a, L, nullptr, r0, p, p + W, carry);
     else
       carry = fwd_window<kTotal, false, false>(a, L, nullptr, r0, p, R.hi, carry);
