@@ -72,6 +72,25 @@ def test_mlp_one_feature_networks(gpu_lib, H):
         assert_bf16_close(got, ref, f"feature {f}")
 
 
+@pytest.mark.parametrize("H,n_rays,n_bins,contract", [
+    (64, 1, 1, False),      # one point: one lane of one tile group loads
+    (64, 37, 13, False),    # 481 points: the last group and its last tile are partial
+    (128, 37, 13, True),
+    (128, 5, 3, False),     # 15 points: less than one tile
+    (64, 1001, 7, True),    # 7007 points
+])
+def test_mlp_fwd_ragged_sizes(gpu_lib, H, n_rays, n_bins, contract):
+    params = scenes.mlp_init(H)
+    radius = 6.0 if contract else 3.0
+    o, d, edges = rays_and_edges(gpu_lib, n_rays, n_bins=n_bins, radius=radius)
+    got = host(gpu_lib.prop_mlp_fwd(mlp_spec(gpu_lib, params, H, contract=contract), dev(o),
+                                    dev(d), edges))
+    assert got.shape == (n_rays, n_bins)
+    x = oracle.bin_midpoints(o, d, host(edges))
+    ref = oracle.mlp_fwd(x, params, H, contract=contract, emulate_bf16=True).reshape(got.shape)
+    assert_bf16_close(got, ref, f"H={H} {n_rays}x{n_bins}")
+
+
 @pytest.mark.parametrize("H,contract", [(64, False), (128, False), (128, True)])
 def test_mlp_random_network(gpu_lib, H, contract):
     params = scenes.mlp_init(H)
