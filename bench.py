@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--learned-near", type=float, default=0.5)
     ap.add_argument("--learned-bins", type=int, default=16,
                     help="proposal bins per ray")
+    ap.add_argument("--cascade-steps", type=int, default=5,
+                    help="also time this many steps of the unbounded workload (4 x 128^3 "
+                         "cascade, distance-scaled steps) through the same path (0 = skip)")
     ap.add_argument("--combined-steps", type=int, default=300,
                     help="train the proposal network alone and inside the grid's occupied "
                          "spans this many steps each on the image scene and report both "
@@ -294,6 +297,29 @@ def mfma_roofline(lv, pc):
         out.append({"kernel": name, "bound": "mfma", "achieved": tf, "peak": BF16_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": tf / BF16_PEAK_TFLOPS,
                     "flop_per_launch": flop, "ms": rec[f"mlp_{key}_ms"]})
+    return out
+
+
+def cascade_step(args):
+    """The unbounded workload (2^20 rays through a 4 x 128^3 cascade with
+    distance-doubling steps) through the headline's path and timing, with
+    each library kernel's algorithmic bytes against 8 TB/s."""
+    import copy
+    a = copy.copy(args)
+    a.steps, a.warmup = args.cascade_steps, 1
+    w, desc = make_workload("unbounded")
+    elapsed, ker, st = gpu_bench(a, w)
+    N, K = w.n_rays, a.steps
+    lib_ms = sum(t * n for name, (t, n) in ker.items() if not name.startswith("field")) / K
+    out = {"workload": desc, "steps": K, "ms_per_step": 1000.0 * elapsed / K,
+           "rays_per_s": N * K / elapsed, "marched_samples": st["Sm"], "kept_samples": st["S"],
+           "library_ms_per_step": lib_ms, "kernels_ms": {k: round(v[0], 4) for k, v in ker.items()},
+           "hbm": {}}
+    for k, f in BYTES.items():
+        if k in ker:
+            b = f(N, st["Sm"], st["S"]) / (ker[k][1] / K)
+            gbps = b / (ker[k][0] * 1e-3) / 1e9
+            out["hbm"][k] = {"alg_bytes_per_launch": b, "GBps": gbps, "frac": gbps / HBM_PEAK_GBS}
     return out
 
 
@@ -536,7 +562,6 @@ def main():
                                               if dom == "render_bwd" and "pattern_ms" in st
                                               else None)},
     }
-    extras = None
     if "render_fwd" in ker:
         # the forward render against 8 TB/s and against its own read pattern
         fwd_bytes = BYTES["render_fwd"](N, st["Sm"], st["S"])
@@ -550,6 +575,8 @@ def main():
         c = rec["render_fwd_roofline"]["read_pattern_ceiling_GBps"]
         rec["render_fwd_roofline"]["frac_of_ceiling"] = fwd_gbps / c if c else None
     extras = None
+    if args.cascade_steps > 0 and args.workload != "unbounded":
+        rec["unbounded_step"] = cascade_step(args)
     if args.learned_steps > 0:
         rec["learned_vs_grid"], extras = learned_vs_grid(args)
     if args.combined_steps > 0:
