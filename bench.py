@@ -122,6 +122,17 @@ class Timeline:
         return {k: (float(np.mean(v)), len(v)) for k, v in out.items()}
 
 
+def ragged_summary(counts):
+    """Per-ray sample counts as a histogram (bin edges 0, 1, 2^k) and percentiles."""
+    edges = [0, 1] + [1 << k for k in range(1, 13)] + [np.iinfo(np.int64).max]
+    hist, _ = np.histogram(counts, bins=edges)
+    return {"bins": [f"[{a},{b})" if b < edges[-1] else f"[{a},inf)"
+                     for a, b in zip(edges[:-1], edges[1:])],
+            "rays": [int(h) for h in hist],
+            "percentiles": {str(q): float(np.percentile(counts, q)) for q in (0, 50, 90, 99, 100)},
+            "mean": float(counts.mean())}
+
+
 def gpu_bench(args, w):
     import torch
 
@@ -159,6 +170,7 @@ def gpu_bench(args, w):
                        optical_depth=out[4], tight=True)
         stats["Sm"], stats["S"] = sm, s
         stats["_probe"] = (q0, q1, sig, rgb)
+        stats["_counts"] = (counts, kept)
         return out, grads
 
     last = None
@@ -171,6 +183,11 @@ def gpu_bench(args, w):
         last = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    # raggedness of the packed rows: per-ray marched and kept counts
+    rows = stats.pop("_counts", None)
+    if rows is not None:
+        stats["raggedness"] = {which: ragged_summary(c.cpu().numpy())
+                               for which, c in zip(("marched", "kept"), rows)}
     # live reference: the render adjoint's traffic (same arrays, same layout,
     # trivial arithmetic) -- the ceiling of that pattern on this device
     sp = stats.pop("_probe", None)
@@ -314,7 +331,7 @@ def cascade_step(args):
     out = {"workload": desc, "steps": K, "ms_per_step": 1000.0 * elapsed / K,
            "rays_per_s": N * K / elapsed, "marched_samples": st["Sm"], "kept_samples": st["S"],
            "library_ms_per_step": lib_ms, "kernels_ms": {k: round(v[0], 4) for k, v in ker.items()},
-           "hbm": {}}
+           "raggedness": st.get("raggedness"), "hbm": {}}
     for k, f in BYTES.items():
         if k in ker:
             b = f(N, st["Sm"], st["S"]) / (ker[k][1] / K)
@@ -550,6 +567,7 @@ def main():
         "library_rays_per_s": N / (lib_ms * 1e-3),
         "library_alg_GBps": alg_total / (lib_ms * 1e-3) / 1e9,
         "kernels_ms": {k: round(v[0], 4) for k, v in ker.items()},
+        "raggedness": st.get("raggedness"),
         "grid_update": {"cells": st["grid_cells"], "ms": st["grid_update_ms"],
                         "what": "EMA update of the occupancy grid: cell points, field at "
                                 "them, blend, binarise (gamma 0.95, tau 0.01)"},
