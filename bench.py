@@ -268,7 +268,7 @@ def learned_vs_grid(args):
     heldout = tuple(int(c) for c in args.learned_heldout.split(",")) if args.learned_heldout \
         else None
     rec, _, extras = run(steps=args.learned_steps, train_stride=args.learned_train_stride,
-                         sweep=[int(s) for s in args.learned_sweep.split(",")], untrained=False,
+                         sweep=[int(s) for s in args.learned_sweep.split(",")], untrained=True,
                          spacing=args.learned_spacing, near=args.learned_near,
                          bins=args.learned_bins, heldout=heldout,
                          log_every=max(args.learned_steps // 4, 1), time_reps=3,
@@ -278,7 +278,8 @@ def learned_vs_grid(args):
             "mlp_fwd_flop_per_point", "mlp_bwd_flop_per_point",
             "mlp_bwd_recompute_flop_per_point", "training_rays",
             "heldout_cameras", "select_err", "n_final", "within_err_bar", "heldout_err",
-            "heldout_within_err_bar", "trained_err", "trained_err_seen", "rays_seen",
+            "heldout_within_err_bar", "untrained_err", "trained_err", "trained_err_seen",
+            "rays_seen",
             "grid_samples", "grid_ms",
             "learned_ms", "grid_rays_per_s", "learned_rays_per_s", "learned_over_grid")
     out = {k: rec[k] for k in keep if k in rec}
