@@ -51,7 +51,7 @@ __host__ __device__ inline size_t loss_lds_bytes(int nb) {
 // Rays with more than kChunk targets are staged in chunks, each bin carrying
 // its partial sum across them (same order).  kBinsPerLane = ceil(nb / 64)
 // rounded up to 1, 4 or 16: the bins' partial sums a lane carries.
-template <int kBinsPerLane>
+template <int kBinsPerLane, int kRegEdges>
 __global__ __launch_bounds__(kWave* kLossWaves) void hist_loss_kernel(
     const int32_t* __restrict__ info, const float* __restrict__ t0, const float* __restrict__ t1,
     const float* __restrict__ w, int32_t n_rays, int64_t n_targets, int32_t nb,
@@ -98,6 +98,14 @@ __global__ __launch_bounds__(kWave* kLossWaves) void hist_loss_kernel(
     if (q < kBinsPerLane && j < nb) pw[j] = pv[q];
   }
   wave_sync();
+  // rows of at most kRegEdges bins: every lane holds the row's edges
+  float er[kRegEdges + 1];
+  float e_last = 0.0f;
+  if (kRegEdges > 0) {
+#pragma unroll
+    for (int m = 0; m <= kRegEdges; ++m) er[m] = m <= nb ? e[m] : INFINITY;
+    e_last = e[nb];
+  }
   float gacc[kBinsPerLane];
 #pragma unroll
   for (int q = 0; q < kBinsPerLane; ++q) gacc[q] = 0.0f;
@@ -113,7 +121,21 @@ __global__ __launch_bounds__(kWave* kLossWaves) void hist_loss_kernel(
         nw = w[i];
       }
       int jlo, jhi;
-      bin_range(e, nb, a, b, jlo, jhi);
+      if (kRegEdges > 0) {
+        // the same bounds as counts over the edges held in registers (sorted
+        // edges; +inf past e[nb]): jlo = #{m in [1, nb]: !(e[m] > a)}, jhi =
+        // #{m in [0, nb - 1]: e[m] < b} - 1
+        int cl = 0, ch = 0;
+#pragma unroll
+        for (int m = 0; m <= kRegEdges; ++m) {
+          if (m > 0) cl += !(er[m] > a);
+          ch += er[m] < b;
+        }
+        jlo = min(cl, nb);
+        jhi = ch - (e_last < b) - 1;
+      } else {
+        bin_range(e, nb, a, b, jlo, jhi);
+      }
       float bound = 0.0f;
       for (int j = jlo; j <= jhi; ++j) bound += pw[j];
       const float gap = wi - bound;
@@ -207,9 +229,10 @@ extern "C" txs_status txs_hist_loss(const int32_t* packed_info, int32_t n_rays, 
   TXS_REQUIRE(n_targets == 0 || (t0 && t1 && w), "txs_hist_loss: null target array");
   const int64_t blocks = ((int64_t)n_rays + kLossWaves - 1) / kLossWaves;
   const size_t lds = kLossWaves * loss_lds_bytes(n_bins);
-  const auto kern = n_bins <= kWave       ? hist_loss_kernel<1>
-                    : n_bins <= 4 * kWave ? hist_loss_kernel<4>
-                                          : hist_loss_kernel<kMaxBins / kWave>;
+  const auto kern = n_bins <= 16          ? hist_loss_kernel<1, 16>
+                    : n_bins <= kWave       ? hist_loss_kernel<1, 0>
+                    : n_bins <= 4 * kWave ? hist_loss_kernel<4, 0>
+                                          : hist_loss_kernel<kMaxBins / kWave, 0>;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kWave * kLossWaves), lds,
                      as_stream(stream), packed_info, t0, t1, w, n_rays, n_targets, n_bins, edges,
                      prop_w, eps, 1.0f / (float)n_rays, loss, d_prop);
